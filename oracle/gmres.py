@@ -1,0 +1,194 @@
+"""Oracle: reference preconditioners and restarted GMRES on the dense matrix.
+
+TEST INFRASTRUCTURE ONLY (see oracle/mom.py).  Used for iteration-count parity
+and for the iterative-versus-direct check; the Z_p target itself is always the
+LU result of oracle/mom.py.
+
+Preconditioners (Sec. III-A):
+* P_K, the block diagonal of Z on the lowest level (the element self blocks),
+  each block LU-factorised (the older strategy, Table I first row);
+* P_A, the block diagonal of Z^H Z (eq. (precondA)), taken here by brute force
+  as the diagonal M x M blocks of the explicit product Z^H Z, each Cholesky
+  factorised (P = L L^H); GMRES then runs on P^{-1} Z^H Z I = P^{-1} Z^H V.
+
+GMRES(m) (the solver of the "new M1" configuration; the paper relies on
+MATLAB's implementation and states none of its details, so this reading fixes
+them): x0 = 0, Arnoldi with classical Gram-Schmidt applied twice (CGS2),
+complex Givens rotations, stop as soon as the least-squares residual
+|g_{j+1}| <= tol * ||b||, explicit residual recomputed at every restart.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import mom
+
+
+# --------------------------------------------------------------------------- preconditioners
+
+def pk_factors(Z: np.ndarray, lat, dip):
+    """LU factors of every element self block of Z."""
+    P = mom.n_elements(lat)
+    return [sla.lu_factor(mom.block(Z, lat, dip, e, e)) for e in range(P)]
+
+
+def pk_apply(factors, x: np.ndarray, M: int) -> np.ndarray:
+    y = np.empty_like(x)
+    for e, f in enumerate(factors):
+        y[e * M:(e + 1) * M] = sla.lu_solve(f, x[e * M:(e + 1) * M])
+    return y
+
+
+def pa_blocks(Z: np.ndarray, lat, dip) -> List[np.ndarray]:
+    """Diagonal M x M blocks of Z^H Z by brute force: P_e = Z[:, cols_e]^H Z[:, cols_e]."""
+    M = dip.nbases
+    out = []
+    for e in range(mom.n_elements(lat)):
+        Zc = Z[:, e * M:(e + 1) * M]
+        out.append(Zc.conj().T @ Zc)
+    return out
+
+
+def pa_factors(blocks):
+    """Cholesky P_e = L L^H of each block (lower factor)."""
+    return [sla.cho_factor(B, lower=True) for B in blocks]
+
+
+def pa_apply(factors, x: np.ndarray, M: int) -> np.ndarray:
+    y = np.empty_like(x)
+    for e, f in enumerate(factors):
+        y[e * M:(e + 1) * M] = sla.cho_solve(f, x[e * M:(e + 1) * M])
+    return y
+
+
+class PreconditionedSystem:
+    """The system GMRES runs on, for one of the two strategies.
+
+    'element_block':  A = P_K^{-1} Z,        b = P_K^{-1} V
+    'normal_eq':      A = P^{-1} Z^H Z,      b = P^{-1} Z^H V
+    """
+
+    def __init__(self, Z: np.ndarray, lat, dip, kind: str):
+        self.Z = Z
+        self.M = dip.nbases
+        self.kind = kind
+        if kind == "element_block":
+            self.f = pk_factors(Z, lat, dip)
+            self.pinv = lambda x: pk_apply(self.f, x, self.M)
+        elif kind == "normal_eq":
+            self.f = pa_factors(pa_blocks(Z, lat, dip))
+            self.pinv = lambda x: pa_apply(self.f, x, self.M)
+        else:
+            raise ValueError(kind)
+
+    def apply(self, x: np.ndarray) -> np.ndarray:
+        if self.kind == "element_block":
+            return self.pinv(self.Z @ x)
+        return self.pinv(self.Z.conj().T @ (self.Z @ x))
+
+    def rhs(self, v: np.ndarray) -> np.ndarray:
+        if self.kind == "element_block":
+            return self.pinv(v)
+        return self.pinv(self.Z.conj().T @ v)
+
+
+# --------------------------------------------------------------------------- GMRES
+
+def givens(h1: complex, h2: complex):
+    """Complex rotation (c real, s complex) with c*h1 + s*h2 = r, -conj(s)*h1 + c*h2 = 0."""
+    if h1 == 0:
+        return 0.0, 1.0 + 0j
+    t = np.sqrt(abs(h1) ** 2 + abs(h2) ** 2)
+    c = abs(h1) / t
+    s = (h1 / abs(h1)) * np.conj(h2) / t
+    return c, s
+
+
+@dataclass
+class GmresResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    cycles: int
+    history: List[float] = field(default_factory=list)   # |g_{j+1}| after every iteration
+    restart_residuals: List[float] = field(default_factory=list)
+
+
+def gmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, restart: int = 50,
+          tol: float = 1e-10, max_cycles: int = 400) -> GmresResult:
+    n = b.shape[0]
+    m = restart
+    x = np.zeros(n, dtype=np.complex128)
+    bnorm = np.linalg.norm(b)
+    res = GmresResult(x, 0, False, 0)
+    if bnorm == 0.0:
+        res.converged = True
+        return res
+    r = b.copy()
+    beta = np.linalg.norm(r)
+    for cycle in range(max_cycles):
+        res.restart_residuals.append(beta)
+        if beta <= tol * bnorm:
+            res.converged = True
+            break
+        res.cycles = cycle + 1
+        V = np.zeros((m + 1, n), dtype=np.complex128)
+        H = np.zeros((m + 1, m), dtype=np.complex128)
+        cs = np.zeros(m)
+        sn = np.zeros(m, dtype=np.complex128)
+        g = np.zeros(m + 1, dtype=np.complex128)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        for j in range(m):
+            w = apply_A(V[j])
+            # classical Gram-Schmidt, twice
+            h = V[:j + 1].conj() @ w
+            w = w - V[:j + 1].T @ h
+            h2 = V[:j + 1].conj() @ w
+            w = w - V[:j + 1].T @ h2
+            h = h + h2
+            hn = np.linalg.norm(w)
+            H[:j + 1, j] = h
+            H[j + 1, j] = hn
+            for i in range(j):
+                a_, b_ = H[i, j], H[i + 1, j]
+                H[i, j] = cs[i] * a_ + sn[i] * b_
+                H[i + 1, j] = -np.conj(sn[i]) * a_ + cs[i] * b_
+            cs[j], sn[j] = givens(H[j, j], H[j + 1, j])
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -np.conj(sn[j]) * g[j]
+            g[j] = cs[j] * g[j]
+            res.iters += 1
+            res.history.append(abs(g[j + 1]))
+            k = j + 1
+            if abs(g[j + 1]) <= tol * bnorm or hn == 0.0:
+                break
+            V[j + 1] = w / hn
+        y = sla.solve_triangular(H[:k, :k], g[:k], lower=False)
+        x = x + V[:k].T @ y
+        if abs(g[k]) <= tol * bnorm:
+            res.converged = True
+            break
+        r = b - apply_A(x)
+        beta = np.linalg.norm(r)
+    res.x = x
+    return res
+
+
+def gmres_all(system: PreconditionedSystem, V: np.ndarray, restart: int = 50, tol: float = 1e-10,
+              max_cycles: int = 400):
+    """Independent GMRES for every column of V; returns (I, per-RHS results)."""
+    B = system.rhs(V)
+    I = np.zeros_like(V)
+    results = []
+    for j in range(V.shape[1]):
+        r = gmres(system.apply, B[:, j], restart, tol, max_cycles)
+        I[:, j] = r.x
+        results.append(r)
+    return I, results

@@ -1,0 +1,134 @@
+"""Seeded synthetic workloads: array geometries, frequencies, scan angles and
+serving request streams.
+
+This module only describes inputs (sizes, seeds, random draws).  It holds none
+of the solver's arithmetic, so the CPU oracle and the GPU path can both draw
+their inputs from it without sharing any computation.
+
+Geometry is in units of the wavelength at the reference frequency f0; a
+frequency is given as the ratio s = f / f0.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, asdict
+from typing import List, Tuple
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Dipole:
+    """z-directed thin-wire dipole element (lengths in wavelengths at f0)."""
+    length: float = 0.5
+    radius: float = 0.005
+    nbases: int = 15          # rooftop bases per element, odd (center basis is the port)
+
+
+@dataclass(frozen=True)
+class Lattice:
+    """Rectangular lattice: element (ix, iy) sits at (ix*dx, iy*dy)."""
+    nx: int = 5
+    ny: int = 5
+    dx: float = 0.5
+    dy: float = 0.5
+
+
+@dataclass
+class Workload:
+    name: str
+    dipole: Dipole
+    lattice: Lattice
+    freqs: List[float]
+    theta: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    phi: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    z0: float = 50.0
+    restart: int = 50
+    tol: float = 1e-10
+
+    def describe(self) -> dict:
+        return {
+            "workload": self.name,
+            "nx": self.lattice.nx, "ny": self.lattice.ny,
+            "dx": self.lattice.dx, "dy": self.lattice.dy,
+            "length": self.dipole.length, "radius": self.dipole.radius,
+            "nbases": self.dipole.nbases,
+            "unknowns": self.lattice.nx * self.lattice.ny * self.dipole.nbases,
+            "ports": self.lattice.nx * self.lattice.ny,
+            "freqs": list(self.freqs), "nscan": int(len(self.theta)),
+            "restart": self.restart, "tol": self.tol,
+        }
+
+
+def scan_angles(n: int, seed: int = 0, broadside_first: bool = False) -> Tuple[np.ndarray, np.ndarray]:
+    """Seeded scan directions: theta ~ U[0, 60 deg], phi ~ U[0, 360 deg), radians."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(0.0, np.deg2rad(60.0), size=n)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    if broadside_first:
+        th = np.concatenate([[0.0], th])
+        ph = np.concatenate([[0.0], ph])
+    return th, ph
+
+
+def cpu_size_5x5() -> Workload:
+    """5x5 dipoles, 15 bases, one frequency, broadside plus 10 seeded scans."""
+    th, ph = scan_angles(10, seed=0, broadside_first=True)
+    return Workload("dipole_5x5_m15", Dipole(0.5, 0.005, 15), Lattice(5, 5, 0.5, 0.5), [1.0], th, ph)
+
+
+def gpu_size_32x32() -> Workload:
+    """32x32 dipoles, 31 bases (N = 31,744), all 1024 ports, 64 seeded scans."""
+    th, ph = scan_angles(64, seed=0)
+    return Workload("dipole_32x32_m31", Dipole(0.5, 0.005, 31), Lattice(32, 32, 0.5, 0.5), [1.0], th, ph)
+
+
+def sweep_5x5_21f() -> Workload:
+    """The 5x5 array at 21 frequencies s_i = 0.5 + 0.05 i."""
+    th, ph = scan_angles(10, seed=0, broadside_first=True)
+    freqs = [0.5 + 0.05 * i for i in range(21)]
+    return Workload("dipole_5x5_m15_21f", Dipole(0.5, 0.005, 15), Lattice(5, 5, 0.5, 0.5), freqs, th, ph)
+
+
+@dataclass
+class Request:
+    """One serving request: an array, its frequencies and its scan set."""
+    rid: int
+    arrival: float            # seconds after stream start
+    dipole: Dipole
+    lattice: Lattice
+    freqs: List[float]
+    theta: np.ndarray
+    phi: np.ndarray
+    z0: float = 50.0
+
+
+def serving_stream(n: int, rate: float, seed: int = 0, nx_range=(8, 48), ny_range=(8, 48),
+                   nbases_choices=(15, 31), nfreq_range=(1, 8), nscan_range=(1, 64)) -> List[Request]:
+    """Poisson arrivals at `rate` requests/s; each request draws Nx, Ny uniform
+    in the given ranges, M from `nbases_choices`, 1-8 frequencies uniform in
+    [0.5, 1.5] f0 and 1-64 scan angles."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate) if rate > 0 else 0.0
+        nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
+        ny = int(rng.integers(ny_range[0], ny_range[1] + 1))
+        m = int(rng.choice(nbases_choices))
+        nf = int(rng.integers(nfreq_range[0], nfreq_range[1] + 1))
+        freqs = sorted(float(f) for f in rng.uniform(0.5, 1.5, size=nf))
+        ns = int(rng.integers(nscan_range[0], nscan_range[1] + 1))
+        th = rng.uniform(0.0, np.deg2rad(60.0), size=ns)
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=ns)
+        out.append(Request(i, t, Dipole(0.5, 0.005, m), Lattice(nx, ny, 0.5, 0.5), freqs, th, ph))
+    return out
+
+
+def random_vectors(n: int, r: int, seed: int = 0, dtype=np.complex128) -> np.ndarray:
+    """Seeded complex Gaussian test vectors, shape (n, r)."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r))).astype(dtype)
+
+
+def to_dict(obj) -> dict:
+    return asdict(obj)

@@ -1,0 +1,61 @@
+"""Writes the stored oracle results for the 32x32-dipole workload.
+
+Calls only oracle/ (dense fill from absolute positions, LAPACK LU, extraction)
+and the seeded workload description.  The full dense system (N = 31,744,
+16 GB complex128) is too large to rebuild inside a test, so a compact subset of
+the result is stored in dipole_32x32_m31_reference.npz:
+
+* Zp_center_row, Zp_diag, Zp_samples (rows, cols, values) and the Frobenius
+  and max norms of Z_p;
+* Yp columns for a handful of ports;
+* S center row;
+* Za, Gamma, Gamma_wave at the 64 seeded scan angles;
+* phase timings of the oracle run and the host it ran on.
+
+Usage:  python tests/golden/make_reference.py   (about 10 minutes on 8 cores)
+"""
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import mom  # noqa: E402
+from paper_2608_17844_amd import workloads as W  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "dipole_32x32_m31_reference.npz")
+SAMPLE_PORTS = [0, 1, 31, 16 * 32 + 16, 16 * 32 + 15, 527, 992, 1023]
+
+
+def main():
+    w = W.gpu_size_32x32()
+    lat, dip = w.lattice, w.dipole
+    t0 = time.time()
+    r = mom.solve_array(lat, dip, 1.0, w.theta, w.phi, z0=w.z0)
+    t1 = time.time()
+    Zp = r.Zp
+    c = mom.center_element(lat)
+    rng = np.random.default_rng(0)
+    rows = rng.integers(0, Zp.shape[0], 4096)
+    cols = rng.integers(0, Zp.shape[0], 4096)
+    np.savez_compressed(
+        OUT,
+        Zp_center_row=Zp[c, :], Zp_diag=np.diag(Zp).copy(),
+        Zp_rows=rows, Zp_cols=cols, Zp_samples=Zp[rows, cols],
+        Zp_fro=np.linalg.norm(Zp), Zp_max=np.abs(Zp).max(),
+        Yp_ports=np.array(SAMPLE_PORTS), Yp_cols=r.Yp[:, SAMPLE_PORTS],
+        S_center_row=r.S[c, :],
+        theta=w.theta, phi=w.phi, Za=r.Za, Gamma=r.Gamma, Gamma_wave=r.Gamma_wave,
+        center=c,
+        times=np.array([r.times["fill"], r.times["lu"], r.times["solve"], r.times["extract"]]),
+        host=np.array(platform.processor() or platform.machine()), cores=os.cpu_count(),
+    )
+    print("wrote", OUT, "in %.1f s" % (t1 - t0), r.times)
+
+
+if __name__ == "__main__":
+    main()

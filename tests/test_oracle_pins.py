@@ -1,0 +1,335 @@
+"""Pins for the CPU oracle: each test checks it against something other than
+itself (closed forms, exact invariants of the physics, independent formulas,
+brute force on tiny inputs), so that a dropped term, a wrong sign or index, or a
+transposed operand in the oracle fails at least one of them."""
+import numpy as np
+import pytest
+
+from oracle import gmres as og
+from oracle import mom
+from paper_2608_17844_amd import workloads as W
+
+from physics import radiated_power
+
+
+# ----------------------------------------------------------------- quadrature rule
+
+def test_gl4_integrates_degree_7_exactly_and_not_8():
+    x, w = mom.gl4_rule()
+    for deg in range(8):
+        exact = 0.0 if deg % 2 else 2.0 / (deg + 1)
+        assert abs(np.sum(w * x ** deg) - exact) < 1e-15
+    assert abs(np.sum(w * x ** 8) - 2.0 / 9.0) > 1e-4
+
+
+# ----------------------------------------------------------------- fill: closed form with a polynomial kernel
+
+def _exact_polynomial_kernel_matrix(lat, dip, k, eta):
+    """Closed-form Galerkin integrals with kernel R^2 = rho^2 + (z-z')^2 + a^2,
+    integrated symbolically (rooftops written as explicit piecewise-linear
+    functions of the node coordinates)."""
+    import sympy as sp
+    z, zp = sp.symbols("z zp", real=True)
+    L = sp.Rational(str(dip.length))
+    a = sp.Rational(str(dip.radius))
+    dx = sp.Rational(str(lat.dx))
+    dy = sp.Rational(str(lat.dy))
+    M = dip.nbases
+    D = L / (M + 1)
+    node = [-L / 2 + i * D for i in range(M + 2)]
+
+    def pieces(p, var):
+        # (interval, value, derivative) of rooftop p: rises on [node p, node p+1], falls on [node p+1, node p+2]
+        return [((node[p], node[p + 1]), (var - node[p]) / D, 1 / D),
+                ((node[p + 1], node[p + 2]), (node[p + 2] - var) / D, -1 / D)]
+
+    P = lat.nx * lat.ny
+    xy = [(dx * (e % lat.nx), dy * (e // lat.nx)) for e in range(P)]
+    cache = {}
+    N = P * M
+    Z = np.zeros((N, N), dtype=complex)
+    for em in range(P):
+        for en in range(P):
+            rho2 = (xy[em][0] - xy[en][0]) ** 2 + (xy[em][1] - xy[en][1]) ** 2
+            for pm in range(M):
+                for pn in range(M):
+                    key = (rho2, pm, pn)
+                    if key not in cache:
+                        A = 0
+                        Phi = 0
+                        for (iz, fm, dm) in pieces(pm, z):
+                            for (izp, fn, dn) in pieces(pn, zp):
+                                ker = rho2 + (z - zp) ** 2 + a ** 2
+                                A += sp.integrate(fm * fn * ker, (z, iz[0], iz[1]), (zp, izp[0], izp[1]))
+                                Phi += dm * dn * sp.integrate(ker, (z, iz[0], iz[1]), (zp, izp[0], izp[1]))
+                        cache[key] = (float(A), float(Phi))
+                    A, Phi = cache[key]
+                    Z[em * M + pm, en * M + pn] = 1j * eta * (k * A - Phi / k)
+    return Z
+
+
+def test_fill_assembly_matches_closed_form_with_polynomial_kernel():
+    lat = W.Lattice(2, 2, 0.5, 0.75)       # dx != dy pins the element ordering e = iy*nx + ix
+    dip = W.Dipole(0.5, 0.005, 3)
+    s = 1.0
+    Zo = mom.fill_dense(lat, dip, s, kernel_mode=1)
+    Ze = _exact_polynomial_kernel_matrix(lat, dip, mom.wavenumber(s), mom.ETA0)
+    assert np.max(np.abs(Zo - Ze)) <= 1e-12 * np.max(np.abs(Ze))
+
+
+# ----------------------------------------------------------------- fill: exact invariants of the physical matrix
+
+def test_fill_reciprocity_symmetric(cfg1_dense):
+    Z = cfg1_dense
+    assert np.linalg.norm(Z - Z.T) / np.linalg.norm(Z) <= 1e-14
+
+
+def test_fill_translation_invariance(cfg1, cfg1_dense):
+    lat, dip = cfg1.lattice, cfg1.dipole
+    Z = cfg1_dense
+    worst = 0.0
+    for em in range(lat.nx * lat.ny):
+        for en in range(lat.nx * lat.ny):
+            ym, xm = divmod(em, lat.nx)
+            yn, xn = divmod(en, lat.nx)
+            # the same offset anchored at element 0 or at the last element
+            if 0 <= xm - xn + 0 < lat.nx and 0 <= ym - yn < lat.ny:
+                ref = mom.block(Z, lat, dip, (ym - yn) * lat.nx + (xm - xn), 0)
+                worst = max(worst, np.max(np.abs(mom.block(Z, lat, dip, em, en) - ref)))
+    assert worst <= 1e-14 * np.max(np.abs(Z))
+
+
+def test_fill_dipole_block_symmetries(cfg1, cfg1_dense):
+    """z-dipoles: each block depends on |rho| only, is symmetric and Toeplitz."""
+    lat, dip = cfg1.lattice, cfg1.dipole
+    Z = cfg1_dense
+    sc = np.max(np.abs(Z))
+    B = lambda dx_, dy_: mom.block(Z, lat, dip, (2 + dy_) * lat.nx + (2 + dx_), 2 * lat.nx + 2)
+    for (dx_, dy_) in [(0, 0), (1, 0), (2, 1), (1, 1), (2, 2)]:
+        T = B(dx_, dy_)
+        assert np.max(np.abs(T - T.T)) <= 1e-14 * sc
+        assert np.max(np.abs(T - B(-dx_, -dy_))) <= 1e-14 * sc
+        assert np.max(np.abs(T - B(-dx_, dy_))) <= 1e-14 * sc
+        assert np.max(np.abs(T - B(dy_, dx_))) <= 1e-14 * sc     # dx == dy spacing
+        for d in range(1, dip.nbases):
+            diag = np.diagonal(T, d)
+            assert np.max(np.abs(diag - diag[0])) <= 1e-14 * sc
+
+
+@pytest.mark.parametrize("lat,excite", [
+    (W.Lattice(1, 1, 0.5, 0.5), "port"),
+    (W.Lattice(3, 2, 0.5, 0.6), "port"),
+    (W.Lattice(3, 3, 0.5, 0.5), "phased"),
+])
+def test_fill_power_balance_against_far_field(lat, excite):
+    """0.5 Re(I^H Z I) equals the radiated power from the far-field pattern of
+    the same currents (checks eta, k, the potential/charge signs and e^{-jkR})."""
+    dip = W.Dipole(0.5, 0.005, 15)
+    s = 1.0
+    Z = mom.fill_dense(lat, dip, s)
+    P = lat.nx * lat.ny
+    if excite == "port":
+        V = mom.excitation(lat, dip, [P // 2])[:, 0]
+    else:
+        th, ph = 0.4, 1.1
+        V = np.zeros(Z.shape[0], complex)
+        V[mom.port_unknown(lat, dip, np.arange(P))] = mom.scan_phases(lat, s, [th], [ph])[:, 0]
+    I = np.linalg.solve(Z, V)
+    p_in = 0.5 * np.real(np.vdot(I, Z @ I))
+    p_rad = radiated_power(lat, dip, s, I)
+    assert abs(p_in / p_rad - 1.0) < 2e-3
+
+
+def test_power_balance_detects_wrong_impedance_scale():
+    lat = W.Lattice(1, 1, 0.5, 0.5)
+    dip = W.Dipole(0.5, 0.005, 15)
+    Z = mom.fill_dense(lat, dip, 1.0, eta=mom.ETA0 * 1.02)      # planted error, in the oracle, on the CPU
+    V = mom.excitation(lat, dip)[:, 0]
+    I = np.linalg.solve(Z, V)
+    p_in = 0.5 * np.real(np.vdot(I, Z @ I))
+    assert abs(p_in / radiated_power(lat, dip, 1.0, I) - 1.0) > 1e-2
+
+
+def test_isolated_dipole_input_impedance_regression():
+    """Loose sanity of this discretisation (a reading of the benchmark element,
+    not a number from the paper): Z_in of the isolated 0.5 lambda dipole."""
+    lat = W.Lattice(1, 1, 0.5, 0.5)
+    dip = W.Dipole(0.5, 0.005, 15)
+    Z = mom.fill_dense(lat, dip, 1.0)
+    zin = 1.0 / np.linalg.solve(Z, mom.excitation(lat, dip))[mom.port_basis(dip), 0]
+    assert abs(zin - (94.08 + 40.53j)) < 0.05
+
+
+def test_fill_entries_match_dense(cfg1, cfg1_dense):
+    rng = np.random.default_rng(3)
+    N = cfg1_dense.shape[0]
+    r = rng.integers(0, N, 50)
+    c = rng.integers(0, N, 50)
+    e = mom.fill_entries(cfg1.lattice, cfg1.dipole, 1.0, r, c)
+    assert np.array_equal(e, cfg1_dense[r, c])
+
+
+# ----------------------------------------------------------------- solve and port quantities
+
+def test_lu_solution_residual(cfg1, cfg1_oracle):
+    Z = cfg1_oracle.Z
+    V = mom.excitation(cfg1.lattice, cfg1.dipole)
+    I = mom.solve_lu(Z, V)
+    assert np.linalg.norm(Z @ I - V) / np.linalg.norm(V) < 1e-13
+
+
+def test_port_impedance_symmetric_and_passive(cfg1_oracle):
+    Zp, S = cfg1_oracle.Zp, cfg1_oracle.S
+    assert np.linalg.norm(Zp - Zp.T) / np.linalg.norm(Zp) < 1e-13
+    ev = np.linalg.eigvalsh(0.5 * (Zp + Zp.conj().T))
+    assert ev[0] > -1e-10 * ev[-1] and ev[0] > 0
+    assert np.max(np.sum(np.abs(S) ** 2, axis=0)) <= 1.0 + 1e-10
+
+
+def test_s_and_z_round_trip(cfg1_oracle):
+    Zp, S = cfg1_oracle.Zp, cfg1_oracle.S
+    assert np.linalg.norm(mom.z_from_s(S) - Zp) / np.linalg.norm(Zp) < 1e-12
+
+
+def test_broadside_active_impedance_is_row_sum(cfg1, cfg1_oracle):
+    c = mom.center_element(cfg1.lattice)
+    za = mom.active_impedance(cfg1_oracle.Zp, cfg1.lattice, 1.0, [0.0], [0.0])[0]
+    assert abs(za - np.sum(cfg1_oracle.Zp[c, :])) < 1e-12 * abs(za)
+
+
+def test_single_element_reduces_to_input_impedance():
+    lat = W.Lattice(1, 1, 0.5, 0.5)
+    dip = W.Dipole(0.5, 0.005, 15)
+    r = mom.solve_array(lat, dip, 1.0, [0.3, 0.9], [0.2, 4.0])
+    zin = 1.0 / r.Yp[0, 0]
+    assert np.allclose(r.Zp[0, 0], zin, rtol=1e-14)
+    assert np.allclose(r.Za, zin, rtol=1e-14)
+    assert np.allclose(r.Gamma, (zin - 50) / (zin + 50), rtol=1e-14)
+    assert np.allclose(r.Gamma_wave, r.S[0, 0], rtol=1e-14)
+    assert np.allclose(r.Gamma, r.Gamma_wave, rtol=1e-12)
+
+
+def test_arc_special_values():
+    assert mom.arc(np.array([50.0 + 0j]))[0] == 0
+    assert abs(mom.arc(np.array([1e300 + 0j]))[0] - 1) < 1e-12
+    assert mom.arc(np.array([0j]))[0] == -1
+
+
+def test_scan_center_symmetry_odd_array(cfg1, cfg1_oracle):
+    """A centrosymmetric odd array: Z_a,c(theta, phi) = Z_a,c(theta, phi + pi);
+    square lattice: also invariant under phi -> pi/2 - phi and phi -> pi - phi."""
+    th = np.array([0.2, 0.5, 0.9])
+    ph = np.array([0.3, 1.7, 4.0])
+    f = lambda p: mom.active_impedance(cfg1_oracle.Zp, cfg1.lattice, 1.0, th, p)
+    base = f(ph)
+    for other in (ph + np.pi, np.pi / 2 - ph, np.pi - ph):
+        assert np.max(np.abs(f(other) - base)) < 1e-11 * np.max(np.abs(base))
+
+
+def test_wave_arc_consistent_with_impedance_form(cfg1, cfg1_oracle):
+    """Incident waves a give port currents proportional to (1 - S) a; the active
+    impedance of those currents must equal z0 (1 + Gamma_wave)/(1 - Gamma_wave)."""
+    lat = cfg1.lattice
+    S, Zp = cfg1_oracle.S, cfg1_oracle.Zp
+    th, ph = np.array([0.35, 0.8]), np.array([0.5, 2.5])
+    a = mom.scan_phases(lat, 1.0, th, ph)
+    c = mom.center_element(lat)
+    gw = mom.wave_arc(S, lat, 1.0, th, ph)
+    Ipc = a - S @ a
+    za = (Zp[c, :] @ Ipc) / Ipc[c, :]
+    assert np.max(np.abs(za - 50.0 * (1 + gw) / (1 - gw))) < 1e-10 * np.max(np.abs(za))
+
+
+# ----------------------------------------------------------------- preconditioners and reference GMRES
+
+def test_givens_rotation_zeroes_and_preserves_norm():
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        h1, h2 = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        c, s = og.givens(h1, h2)
+        r1 = c * h1 + s * h2
+        r2 = -np.conj(s) * h1 + c * h2
+        assert abs(r2) < 1e-15 * abs(r1)
+        assert abs(abs(r1) - np.hypot(abs(h1), abs(h2))) < 1e-14 * abs(r1)
+    c, s = og.givens(0.0, 2.0 + 1j)
+    assert c == 0 and s == 1
+
+
+def test_gmres_iterate_minimises_residual_over_krylov_space(cfg1, cfg1_dense):
+    sysm = og.PreconditionedSystem(cfg1_dense, cfg1.lattice, cfg1.dipole, "element_block")
+    b = sysm.rhs(mom.excitation(cfg1.lattice, cfg1.dipole, [12]))[:, 0]
+    A = lambda x: sysm.apply(x)
+    for k in (1, 3, 6):
+        r = og.gmres(A, b, restart=k, tol=0.0, max_cycles=1)
+        K = np.empty((b.size, k), complex)
+        K[:, 0] = b
+        for i in range(1, k):
+            K[:, i] = A(K[:, i - 1])
+        Q, _ = np.linalg.qr(K)
+        AQ = np.stack([A(Q[:, i]) for i in range(k)], axis=1)
+        y = np.linalg.lstsq(AQ, b, rcond=None)[0]
+        x_ls = Q @ y
+        assert np.linalg.norm(r.x - x_ls) <= 1e-9 * np.linalg.norm(x_ls)
+
+
+def test_full_gmres_converges_within_n_steps():
+    rng = np.random.default_rng(2)
+    n = 30
+    A = np.eye(n) * 3 + rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    b = rng.standard_normal(n) + 0j
+    r = og.gmres(lambda x: A @ x, b, restart=n, tol=1e-12, max_cycles=1)
+    assert r.converged and r.iters <= n
+    assert np.linalg.norm(A @ r.x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("kind", ["element_block", "normal_eq"])
+def test_single_element_converges_in_one_iteration(kind):
+    lat = W.Lattice(1, 1, 0.5, 0.5)
+    dip = W.Dipole(0.5, 0.005, 15)
+    Z = mom.fill_dense(lat, dip, 1.0)
+    sysm = og.PreconditionedSystem(Z, lat, dip, kind)
+    I, res = og.gmres_all(sysm, mom.excitation(lat, dip))
+    assert res[0].iters == 1 and res[0].converged
+    assert np.allclose(I, mom.solve_lu(Z, mom.excitation(lat, dip)), rtol=1e-9)
+
+
+def test_normal_eq_preconditioner_blocks(cfg1, cfg1_dense):
+    lat, dip = cfg1.lattice, cfg1.dipole
+    blocks = og.pa_blocks(cfg1_dense, lat, dip)
+    M = dip.nbases
+    ZhZ = cfg1_dense.conj().T @ cfg1_dense
+    for e in (0, 7, 12, 24):
+        Pb = blocks[e]
+        assert np.allclose(Pb, ZhZ[e * M:(e + 1) * M, e * M:(e + 1) * M], rtol=0, atol=1e-12 * np.abs(Pb).max())
+        assert np.allclose(Pb, Pb.conj().T, rtol=0, atol=1e-13 * np.abs(Pb).max())
+        assert np.linalg.eigvalsh(Pb)[0] > 0
+
+
+def test_normal_eq_spectrum_real_positive_and_split_form_identical(cfg1, cfg1_dense):
+    """sigma(P^{-1} Z^H Z) is real, positive, and equals sigma(L^{-1} Z^H Z L^{-H})."""
+    import scipy.linalg as sla
+    lat, dip = cfg1.lattice, cfg1.dipole
+    Z = cfg1_dense
+    blocks = og.pa_blocks(Z, lat, dip)
+    Pfull = sla.block_diag(*blocks)
+    Lfull = sla.block_diag(*[np.linalg.cholesky(B) for B in blocks])
+    ZhZ = Z.conj().T @ Z
+    ev1 = np.linalg.eigvals(np.linalg.solve(Pfull, ZhZ))
+    Li = np.linalg.inv(Lfull)
+    ev2 = np.linalg.eigvalsh(Li @ ZhZ @ Li.conj().T)
+    assert np.max(np.abs(ev1.imag)) < 1e-10 * np.max(np.abs(ev1))
+    assert np.min(ev1.real) > 0
+    assert np.allclose(np.sort(ev1.real), ev2, rtol=1e-8, atol=1e-10)
+
+
+@pytest.mark.parametrize("kind", ["element_block", "normal_eq"])
+def test_iterative_agrees_with_direct(cfg1, cfg1_oracle, kind):
+    lat, dip = cfg1.lattice, cfg1.dipole
+    sysm = og.PreconditionedSystem(cfg1_oracle.Z, lat, dip, kind)
+    I, res = og.gmres_all(sysm, mom.excitation(lat, dip), restart=50, tol=1e-10)
+    assert all(r.converged for r in res)
+    Zp = mom.port_impedance(mom.port_admittance(I, lat, dip))
+    err = np.linalg.norm(Zp - cfg1_oracle.Zp) / np.linalg.norm(cfg1_oracle.Zp)
+    assert err < 1e-9
+    it = [r.iters for r in res]
+    assert 5 <= min(it) and max(it) <= 60
