@@ -1,0 +1,247 @@
+/*
+ * mbt.h -- C ABI of the MI355X multilevel-block-Toeplitz (MBT) finite-array
+ * Method-of-Moments solver.
+ *
+ * Problem (paper Sec. II-C, eq. (eqProb)): Z I = V for a regular nx x ny
+ * lattice of identical elements with M bases each, for every port excitation
+ * at once (one feed per element, F = 1).  Z is multilevel block-Toeplitz
+ * (Sec. II-A): the M x M block between two elements depends only on their
+ * lattice offset, so only the (2ny-1)(2nx-1) unique blocks are stored and
+ * Z x is applied by a two-level FFT over the circulant embedding (eq. (multL)),
+ * Z^H y from the same stored spectra (eq. (multCom)).  Outputs are the port
+ * admittance / open-circuit port impedance (eq. (passZ)), the active
+ * impedance (eqs. (actZ), (actZmat)) and active reflection coefficient
+ * (eq. (ARC)) of the center element, and the wave-excited reflection
+ * coefficient from the phased S-sum (Sec. II-D with eq. (S2Z)).
+ *
+ * Element: a z-directed thin-wire dipole (length, radius in wavelengths at the
+ * reference frequency f0; nbases odd rooftops; port at the center rooftop),
+ * filled by Galerkin EFIE with the reduced kernel exp(-jkR)/(4 pi R),
+ * R = sqrt(rho^2 + (z-z')^2 + a^2), and 4-point Gauss-Legendre per segment.
+ *
+ * Conventions
+ *  - complex numbers are interleaved FP64 {re, im} pairs (C99 double _Complex,
+ *    numpy complex128); a "complex array of n entries" is 2n doubles;
+ *  - host matrices are column-major: A[i + ld*j];
+ *  - unknown index n = e*M + p, element e = iy*nx + ix at (ix*dx, iy*dy);
+ *    port j is element j (its center rooftop p_c = (M-1)/2);
+ *  - the center element is (nx/2, ny/2) (integer division);
+ *  - a frequency is the ratio s = f/f0 (wavenumber k = 2 pi s);
+ *  - unless stated, pointers are host memory owned by the caller; handles
+ *    are owned by the library and released by their _destroy call;
+ *  - every call returns an mbt_status; on error mbt_last_error() returns a
+ *    thread-local message; on MBT_ENOCONV outputs still hold the last iterate;
+ *  - one context is not re-entrant (serialize calls on it); the server is
+ *    internally threaded.
+ */
+#ifndef MBT_H
+#define MBT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MBT_OK = 0,
+    MBT_EINVAL = -1,      /* invalid argument (geometry, sizes, ports, options) */
+    MBT_ENOMEM = -2,      /* device-memory footprint exceeds the context budget */
+    MBT_ENOCONV = -3,     /* max_cycles reached; outputs hold the last iterate */
+    MBT_EDEVICE = -4,     /* HIP runtime error */
+    MBT_EBUSY = -5,       /* server queue full */
+    MBT_EBREAKDOWN = -6,  /* non-finite value met in the Krylov recurrence */
+    MBT_ETIMEOUT = -7     /* mbt_server_wait timed out */
+} mbt_status;
+
+/* Precision of the FFT-Toeplitz operator inside the Krylov solve.
+ * MBT_FP64: everything FP64.  MBT_FP32 / MBT_BF16 / MBT_FP16: the lattice FFTs
+ * and per-bin block products run in reduced precision (FP32 MFMA with FP32
+ * accumulation; BF16/FP16 inputs with FP32 accumulation), the Krylov basis is
+ * stored in FP32 with FP64 dot products, Givens rotations are FP64, and FP64
+ * iterative refinement with an FP64 residual recovers the accuracy. */
+typedef enum { MBT_FP64 = 0, MBT_FP32 = 1, MBT_BF16 = 2, MBT_FP16 = 3 } mbt_prec;
+
+/* Preconditioning strategy.
+ * MBT_PC_NORMAL_EQ:     GMRES on P^{-1} Z^H Z I = P^{-1} Z^H V, P the block
+ *                       diagonal of Z^H Z (Sec. II-B, eqs. (precondA), (precond)).
+ * MBT_PC_ELEMENT_BLOCK: GMRES on P_K^{-1} Z I = P_K^{-1} V, P_K the element
+ *                       self blocks of Z (the older strategy of Table I). */
+typedef enum { MBT_PC_NORMAL_EQ = 0, MBT_PC_ELEMENT_BLOCK = 1 } mbt_pc;
+
+typedef struct { double length, radius; int32_t nbases; } mbt_dipole;
+typedef struct { int32_t nx, ny; double dx, dy; } mbt_lattice;
+
+typedef struct {
+    int32_t prec;         /* mbt_prec */
+    int32_t pc;           /* mbt_pc */
+    int32_t restart;      /* GMRES restart length m (>= 1), default 50 */
+    double tol;           /* FP64 path: relative preconditioned residual, default 1e-10 */
+    int32_t max_cycles;   /* restart cycles per (inner) solve, default 400 */
+    int32_t refine_max;   /* reduced precision: max outer refinement steps, default 3 */
+    double refine_tol;    /* reduced precision: outer stop on ||V - Z I|| / ||V||, default 1e-9 */
+    double inner_tol;     /* reduced precision: inner relative tolerance (0 = by precision) */
+    int32_t rhs_chunk;    /* RHS per batched solve (0 = all at once, within the budget) */
+    int32_t flags;        /* reserved, 0 */
+} mbt_solve_opts;
+
+typedef struct {
+    int32_t nrhs;             /* RHS solved */
+    int32_t nconverged;       /* RHS that met the tolerance */
+    int32_t cycles;           /* restart cycles (max over RHS, summed over outer steps) */
+    int32_t outer_steps;      /* refinement steps (1 for FP64) */
+    int32_t iters_min, iters_max;
+    int64_t iters_total;      /* Arnoldi steps summed over RHS */
+    int64_t matvecs;          /* batched operator applications (Z or Z^H, each counted) */
+    double true_relres_max;   /* max over RHS of ||V - Z I|| / ||V||, FP64 */
+    double t_setup, t_solve, t_extract;   /* seconds (device-synchronised phases) */
+} mbt_stats;
+
+typedef struct mbt_ctx mbt_ctx;
+typedef struct mbt_array mbt_array;
+
+/* Defaults listed in mbt_solve_opts. */
+void mbt_default_opts(mbt_solve_opts* opts);
+
+/* Context on HIP device `hip_device`; hbm_budget_bytes = 0 means 90% of free
+ * device memory.  Errors: MBT_EINVAL (bad device), MBT_EDEVICE. */
+mbt_status mbt_ctx_create(int32_t hip_device, size_t hbm_budget_bytes, mbt_ctx** out);
+void mbt_ctx_destroy(mbt_ctx* ctx);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* mbt_last_error(void);
+
+/* Library build string (kernels, target). */
+const char* mbt_version(void);
+
+/* Array geometry.  MBT_EINVAL: nbases even or < 1, radius <= 0, length <= 0,
+ * nx/ny < 1 or > 1024, dx/dy <= 0. */
+mbt_status mbt_array_create_dipole(mbt_ctx* ctx, const mbt_dipole* elem, const mbt_lattice* lat,
+                                   mbt_array** out);
+void mbt_array_destroy(mbt_array* arr);
+
+/* Sizes: unknowns N = nx*ny*M, ports P = nx*ny, FFT grid (gx, gy) >= (2nx-1, 2ny-1). */
+mbt_status mbt_array_info(const mbt_array* arr, int64_t* nunknowns, int32_t* nports, int32_t* gx,
+                          int32_t* gy);
+
+/* Device-memory estimate (bytes) of one batched solve of `nrhs` RHS. */
+size_t mbt_footprint(const mbt_array* arr, int32_t nrhs, const mbt_solve_opts* opts);
+
+/* Port admittance columns: unit delta-gap voltage at each port in `ports`
+ * (ports == NULL and nports == -1: all P ports, in order), every other port
+ * shorted.  Y (P x nports, column-major, complex) receives the port-basis
+ * currents: Y[i + P*j] = I(port i) for excitation ports[j].  iters (nports, may
+ * be NULL) receives per-RHS Arnoldi-step counts (summed over refinement steps).
+ * Errors: MBT_EINVAL (freq_ratio <= 0, port out of range, restart < 1),
+ * MBT_ENOMEM, MBT_ENOCONV, MBT_EDEVICE. */
+mbt_status mbt_port_admittance(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio,
+                               const int32_t* ports, int32_t nports, const mbt_solve_opts* opts,
+                               double* Y, int32_t* iters, mbt_stats* stats);
+
+/* Same, with Y a device pointer (P x nports complex, column-major) and the
+ * work ordered on HIP stream `stream` (NULL: the context stream).  The call
+ * returns after the work completes. */
+mbt_status mbt_port_admittance_dev(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio,
+                                   const int32_t* ports, int32_t nports, const mbt_solve_opts* opts,
+                                   void* Y_dev, void* stream, int32_t* iters, mbt_stats* stats);
+
+/* Full open-circuit port impedance Z_p = Y_p^{-1} (P x P complex). */
+mbt_status mbt_port_impedance(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio,
+                              const mbt_solve_opts* opts, double* Zp, mbt_stats* stats);
+
+/* End to end for one frequency: geometry, lattice, frequency and all port
+ * excitations in; Z_p (P x P, may be NULL), and for each of the nscan
+ * directions (theta, phi radians) the center-element active impedance Za,
+ * ARC Gamma = (Za - z0)/(Za + z0) and the wave-excited Gamma_wave (may be
+ * NULL) out.  Everything after the solve (Y_p^{-1}, S, scans) runs on the GPU
+ * in FP64. */
+mbt_status mbt_solve(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, const mbt_solve_opts* opts,
+                     const double* theta, const double* phi, int32_t nscan, double z0, double* Zp,
+                     double* Za, double* Gamma, double* Gamma_wave, mbt_stats* stats);
+
+/* Scan quantities from a given Z_p (host, P x P): Za, Gamma, Gamma_wave as in
+ * mbt_solve; center < 0 selects (nx/2, ny/2).  Computed on the GPU. */
+mbt_status mbt_active(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, const double* Zp,
+                      int32_t center, const double* theta, const double* phi, int32_t nscan, double z0,
+                      double* Za, double* Gamma, double* Gamma_wave);
+
+/* ---------------------------------------------------------------- serving
+ * A persistent request loop: requests are admitted while in-flight slots and
+ * the device-memory budget allow, their solves overlap on the device on
+ * separate streams, FFT'd block spectra are cached across requests, and
+ * per-request latency (submit -> result) is recorded. */
+typedef struct {
+    mbt_dipole elem;
+    mbt_lattice lat;
+    int32_t nfreq;
+    const double* freq_ratio;   /* nfreq entries, copied at submit */
+    int32_t nscan;
+    const double* theta;        /* nscan entries, copied */
+    const double* phi;
+    double z0;
+    mbt_solve_opts opts;
+} mbt_request;
+
+typedef struct {
+    mbt_status status;
+    int32_t nfreq, nports, nscan;
+    double* Zp;          /* nfreq blocks of P x P complex (library-owned) */
+    double* Za;          /* nfreq x nscan complex, frequency-major */
+    double* Gamma;       /* nfreq x nscan complex */
+    double* Gamma_wave;  /* nfreq x nscan complex */
+    int32_t* iters_max;  /* nfreq */
+    double t_submit, t_start, t_done;   /* seconds on the server clock */
+} mbt_result;
+
+typedef struct mbt_server mbt_server;
+
+/* max_inflight concurrent requests (>= 1); hbm_budget_bytes 0 = the context's. */
+mbt_status mbt_server_create(mbt_ctx* ctx, int32_t max_inflight, size_t hbm_budget_bytes, mbt_server** out);
+/* Copies the request, returns at once with a ticket.  MBT_EINVAL for a bad
+ * request, MBT_ENOMEM if it can never fit the budget. */
+mbt_status mbt_server_submit(mbt_server* srv, const mbt_request* req, uint64_t* ticket);
+/* Waits for `ticket` (timeout_ms < 0: forever); the result is library-owned
+ * and released by mbt_result_free.  MBT_ETIMEOUT if not done in time. */
+mbt_status mbt_server_wait(mbt_server* srv, uint64_t ticket, int32_t timeout_ms, mbt_result** out);
+void mbt_result_free(mbt_result* res);
+/* Seconds on the server clock (for arrival scheduling by the caller). */
+double mbt_server_clock(const mbt_server* srv);
+/* Finishes in-flight requests, then stops the loop. */
+void mbt_server_destroy(mbt_server* srv);
+
+/* ---------------------------------------------------------------- test hooks
+ * Expose single steps of the path for parity tests; same ABI conventions. */
+
+/* Unique blocks T[d] (host, (2ny-1)(2nx-1) blocks of M x M complex, block
+ * index (dy + ny - 1)*(2nx-1) + (dx + nx - 1), each block row-major T[p*M+q]
+ * = Z(test basis p of element e + d, source basis q of element e)). */
+mbt_status mbt_dbg_fill_blocks(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, double* T);
+
+/* y = op(Z) x for R columns (x, y host N x R complex, column-major).
+ * op: 0 -> Z, 1 -> Z^H, 2 -> Z^H Z.  prec: mbt_prec of the FFT/product path. */
+mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, int32_t prec, int32_t op,
+                          const double* x, int32_t R, double* y);
+
+/* y = P^{-1} x with the preconditioner of strategy pc (host N x R, column-major). */
+mbt_status mbt_dbg_precond_apply(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, int32_t pc,
+                                 const double* x, int32_t R, double* y);
+
+/* The preconditioner blocks before factorisation: pc NORMAL_EQ -> P blocks of
+ * M x M (row-major each); ELEMENT_BLOCK -> the single self block. */
+mbt_status mbt_dbg_precond_blocks(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, int32_t pc, double* Pb);
+
+/* Batched GMRES on the preconditioned system for arbitrary right-hand sides
+ * V (host N x R): returns I (N x R) and per-RHS iteration counts. */
+mbt_status mbt_dbg_solve(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, const mbt_solve_opts* opts,
+                         const double* V, int32_t R, double* I, int32_t* iters, mbt_stats* stats);
+
+/* Inverse of an n x n complex matrix (host, column-major) on the device:
+ * Gauss-Jordan with partial pivoting in FP64. */
+mbt_status mbt_dbg_inverse(mbt_ctx* ctx, const double* A, int32_t n, double* Ainv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBT_H */

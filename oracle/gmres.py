@@ -115,6 +115,7 @@ class GmresResult:
     converged: bool
     cycles: int
     history: List[float] = field(default_factory=list)   # |g_{j+1}| after every iteration
+    arnoldi_ratio: List[float] = field(default_factory=list)  # ||w|| after / before orthogonalisation
     restart_residuals: List[float] = field(default_factory=list)
 
 
@@ -146,6 +147,7 @@ def gmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, restart: i
         k = 0
         for j in range(m):
             w = apply_A(V[j])
+            wnorm0 = np.linalg.norm(w)
             # classical Gram-Schmidt, twice
             h = V[:j + 1].conj() @ w
             w = w - V[:j + 1].T @ h
@@ -166,6 +168,7 @@ def gmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, restart: i
             g[j] = cs[j] * g[j]
             res.iters += 1
             res.history.append(abs(g[j + 1]))
+            res.arnoldi_ratio.append(hn / wnorm0 if wnorm0 > 0 else 0.0)
             k = j + 1
             if abs(g[j + 1]) <= tol * bnorm or hn == 0.0:
                 break

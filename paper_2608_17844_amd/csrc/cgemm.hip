@@ -1,0 +1,167 @@
+// Batched complex block products Y_b = op(A_b) X_b on the matrix cores.
+//
+// Used for the per-bin products of the FFT-Toeplitz matvec, where A_b is the
+// spectrum C^_b of the circulant embedding at bin b (paper eq. (multL)) and
+// op = ^H gives Z^H from the same stored spectra (eq. (multCom)), and for the
+// block-diagonal preconditioner apply, where A_b is an element's inverse block.
+//
+// A complex product becomes one real product of twice the size:
+//   [Y_re]   [A_re  -A_im] [X_re]
+//   [Y_im] = [A_im   A_re] [X_im],
+// with the real K index interleaving (q, re/im).  With X stored as interleaved
+// complex, a lane that loads X[q][col] feeds both K slots (q, re) and (q, im)
+// of a 16x16x4 MFMA pair, so no de-interleaving is needed.  Rows of the real
+// result are (p, re/im) pairs, so each lane's four accumulator rows are two
+// complete complex outputs.
+//
+// Each wave keeps its A_b fragments in registers and streams 16-column tiles
+// of X_b; M is padded to MP (16 or 32) with predicated loads and stores.  At
+// M = 31 the FP64 product has about 8 flop/byte (below the FP64 MFMA ridge of
+// 9.8) and the FP32 one about 16 (below 19.7): both are HBM-bound.
+#include "common.h"
+
+namespace mbt {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { using type = d4; };
+template <> struct Acc<float> { using type = f4; };
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T, int MP, bool HERM>
+__global__ __launch_bounds__(256) void cgemm_kernel(const cplx<T>* __restrict__ A, int64_t strideA,
+                                                    const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Y, int M,
+                                                    int R, int groups, int tpw) {
+    using C = cplx<T>;
+    using V = typename Acc<T>::type;
+    constexpr int NRT = MP / 8;   // 16-row tiles of the 2MP-row real matrix
+    constexpr int NS = MP / 4;    // complex K groups of 4
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t b = blockIdx.x / groups;
+    const int grp = blockIdx.x % groups;
+    const int ntiles = (R + 15) >> 4;
+    const int t0 = (grp * 4 + wave) * tpw;
+    if (t0 >= ntiles) return;
+    const int t1 = min(t0 + tpw, ntiles);
+
+    const C* Ab = A + b * strideA;
+    const C* Xb = X + b * (int64_t)M * R;
+    C* Yb = Y + b * (int64_t)M * R;
+    const int g = lane >> 4;       // lane group: K slot inside a group of 4
+    const int li = lane & 15;
+
+    // A fragments: lane li supplies row li of the tile; K slot q = 4s + g.
+    // The accumulator of row i sits in lane group i%4, register i/4 for the
+    // f64 16x16x4 MFMA, and in lane group i/4, register i%4 for the f32 one;
+    // the row -> (p, re/im) assignment is chosen per type so that every lane
+    // ends with registers {(p0, re), (p0, im), (p0+1, re), (p0+1, im)},
+    // p0 = 8t + 2*(lane/16).
+    T are[NRT][NS], aim[NRT][NS];
+#pragma unroll
+    for (int t = 0; t < NRT; ++t) {
+        int p;
+        bool odd;
+        if constexpr (sizeof(T) == 8) {
+            const int v = li >> 2, gg = li & 3;
+            p = 8 * t + 2 * gg + (v >> 1);
+            odd = v & 1;
+        } else {
+            const int rho = 16 * t + li;
+            p = rho >> 1;
+            odd = rho & 1;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int q = 4 * s + g;
+            C c = mk<T>(0, 0);
+            if (p < M && q < M) {
+                c = HERM ? Ab[(int64_t)q * M + p] : Ab[(int64_t)p * M + q];
+                if (HERM) c.y = -c.y;
+            }
+            are[t][s] = odd ? c.y : c.x;
+            aim[t][s] = odd ? c.x : -c.y;
+        }
+    }
+
+    C bcur[NS], bnext[NS];
+    auto load = [&](int tile, C* dst) {
+        const int col = tile * 16 + li;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int q = 4 * s + g;
+            dst[s] = (q < M && col < R) ? Xb[(int64_t)q * R + col] : mk<T>(0, 0);
+        }
+    };
+    load(t0, bcur);
+    for (int tile = t0; tile < t1; ++tile) {
+        if (tile + 1 < t1) load(tile + 1, bnext);
+        V acc[NRT];
+#pragma unroll
+        for (int t = 0; t < NRT; ++t) acc[t] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) {
+                acc[t] = mfma(are[t][s], bcur[s].x, acc[t]);
+                acc[t] = mfma(aim[t][s], bcur[s].y, acc[t]);
+            }
+        }
+        const int col = tile * 16 + li;
+        if (col < R) {
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) {
+                const int p0 = 8 * t + 2 * g;
+                if (p0 < M) Yb[(int64_t)p0 * R + col] = mk<T>(acc[t][0], acc[t][1]);
+                if (p0 + 1 < M) Yb[(int64_t)(p0 + 1) * R + col] = mk<T>(acc[t][2], acc[t][3]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bcur[s] = bnext[s];
+    }
+}
+
+template <typename T, int MP>
+void launch_mp(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R, int64_t nbatch,
+               int op, hipStream_t s) {
+    const int ntiles = (R + 15) / 16;
+    const int64_t total = nbatch * ntiles;
+    int tpw = (int)std::max<int64_t>(1, std::min<int64_t>(8, total / 32768));
+    tpw = std::min(tpw, ntiles);
+    const int groups = (ntiles + 4 * tpw - 1) / (4 * tpw);
+    const int64_t blocks = nbatch * groups;
+    MBT_REQUIRE(blocks < (1LL << 31), "cgemm: grid too large");
+    if (op == 0)
+        hipLaunchKernelGGL((cgemm_kernel<T, MP, false>), dim3((unsigned)blocks), dim3(256), 0, s, A, strideA, X, Y, M,
+                           R, groups, tpw);
+    else
+        hipLaunchKernelGGL((cgemm_kernel<T, MP, true>), dim3((unsigned)blocks), dim3(256), 0, s, A, strideA, X, Y, M,
+                           R, groups, tpw);
+    MBT_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+template <typename T>
+void cgemm_batched(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R, int64_t nbatch,
+                   int op, hipStream_t s) {
+    if (nbatch <= 0 || R <= 0) return;
+    if (M <= 16) launch_mp<T, 16>(A, strideA, X, Y, M, R, nbatch, op, s);
+    else if (M <= 32) launch_mp<T, 32>(A, strideA, X, Y, M, R, nbatch, op, s);
+    else throw Error(-1, "cgemm: block size above 32 is not supported");
+}
+
+template void cgemm_batched<double>(const double2*, int64_t, const double2*, double2*, int, int, int64_t, int, hipStream_t);
+template void cgemm_batched<float>(const float2*, int64_t, const float2*, float2*, int, int, int64_t, int, hipStream_t);
+
+}  // namespace mbt

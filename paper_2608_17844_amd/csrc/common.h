@@ -1,0 +1,137 @@
+// Shared declarations of the MI355X MBT solver library (internal, not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+namespace mbt {
+
+// ------------------------------------------------------------------ complex helpers
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+template <typename T> using cplx = typename cplx_t<T>::type;
+
+template <typename T> __host__ __device__ __forceinline__ cplx<T> mk(T re, T im) {
+    cplx<T> r;
+    r.x = re;
+    r.y = im;
+    return r;
+}
+template <typename C> __host__ __device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __host__ __device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C> __host__ __device__ __forceinline__ C cmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+// conj(a) * b
+template <typename C> __host__ __device__ __forceinline__ C cmulc(C a, C b) {
+    C r;
+    r.x = a.x * b.x + a.y * b.y;
+    r.y = a.x * b.y - a.y * b.x;
+    return r;
+}
+template <typename C> __host__ __device__ __forceinline__ C cconj(C a) { C r; r.x = a.x; r.y = -a.y; return r; }
+// multiply by +i (inv == true) or -i
+template <typename C> __host__ __device__ __forceinline__ C cmul_i(C a, bool plus) {
+    C r;
+    if (plus) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; }
+    return r;
+}
+
+__host__ __device__ __forceinline__ double2 to_d2(float2 a) { return make_double2(a.x, a.y); }
+__host__ __device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+template <typename C> __host__ __device__ __forceinline__ C from_d2(double2 a);
+template <> __host__ __device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
+template <> __host__ __device__ __forceinline__ float2 from_d2<float2>(double2 a) {
+    return make_float2((float)a.x, (float)a.y);
+}
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define MBT_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            throw ::mbt::Error(-4, std::string("HIP error '") + hipGetErrorString(e_) + "' at " + \
+                                       __FILE__ + ":" + std::to_string(__LINE__) + " (" #call ")"); \
+    } while (0)
+
+#define MBT_LAUNCH_CHECK() MBT_HIP(hipGetLastError())
+
+#define MBT_REQUIRE(cond, msg)                                   \
+    do {                                                         \
+        if (!(cond)) throw ::mbt::Error(-1, std::string(msg));   \
+    } while (0)
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int nx = 0, ny = 0, M = 0;     // lattice size, bases per element
+    double dx = 0, dy = 0;         // lattice spacing (wavelengths at f0)
+    double L = 0, a = 0;           // dipole length and wire radius
+    int P = 0;                     // elements = ports
+    int64_t N = 0;                 // unknowns
+    int Lx = 0, Ly = 0;            // half FFT grid: powers of two >= nx, ny
+    int Px = 0, Py = 0;            // FFT grid 2*Lx x 2*Ly >= (2nx-1) x (2ny-1)
+    int nox = 0, noy = 0;          // offsets per axis 2nx-1, 2ny-1
+    int pc = 0;                    // port basis (M-1)/2
+    int64_t bins() const { return (int64_t)Px * Py; }
+    int64_t noff() const { return (int64_t)nox * noy; }
+};
+
+// ------------------------------------------------------------------ kernels (host launchers)
+// fill.hip: unique interaction blocks T[(dy+ny-1)*nox + (dx+nx-1)][p][q] (row-major M x M)
+void fill_blocks(const Geom& g, double k, double2* T, hipStream_t s);
+
+// fft.hip
+// spectrum of the circulant embedding: Chat[ky*Px+kx][p][q] = scale * DFT2(C_1)[p][q]
+void embed_blocks_fft(const Geom& g, const double2* T, double2* Chat, double scale, double2* scratch,
+                      hipStream_t s);
+// twiddle table tw[j] = exp(-2 pi i j / P), j < P
+void make_twiddles(int P, double2* tw, hipStream_t s);
+template <typename T>
+void fft_fwd_pad(const Geom& g, const cplx<T>* X, cplx<T>* Xh, int64_t B, const cplx<T>* twx,
+                 const cplx<T>* twy, hipStream_t s);
+template <typename T>
+void fft_inv_crop(const Geom& g, const cplx<T>* Yh, cplx<T>* Y, int64_t B, const cplx<T>* twx,
+                  const cplx<T>* twy, hipStream_t s);
+
+// cgemm.hip: Y_b = op(A_b) X_b for b < nbatch; A_b = A + b*strideA (M x M row-major complex),
+// X_b / Y_b = X/Y + b*M*R (M x R row-major).  op: 0 = A, 1 = A^H.
+template <typename T>
+void cgemm_batched(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R,
+                   int64_t nbatch, int op, hipStream_t s);
+
+// precond.hip
+void gram_blocks(const Geom& g, const double2* T, double2* G, hipStream_t s);            // G[d] = T[d]^H T[d]
+void window_sum(const Geom& g, const double2* G, double2* Pblk, hipStream_t s);          // P_e = sum_j G[j-e]
+// batched inverses of M x M blocks: hpd = true -> Cholesky based; false -> LU with partial pivoting.
+// info[b] != 0 flags a non-positive pivot / singular block.
+void batched_inverse(const double2* A, double2* Ainv, int M, int64_t nbatch, bool hpd, int* info,
+                     hipStream_t s);
+
+// elementwise / conversion helpers (vec.hip)
+template <typename TS, typename TD>
+void convert(const TS* src, TD* dst, int64_t n, hipStream_t s);     // n complex values
+void scatter_ports(const Geom& g, const int32_t* ports, int R, double2* V, hipStream_t s);  // V = unit delta gaps
+void axpby_d(double2* y, const double2* x, double a, double b, int64_t n, hipStream_t s);  // y = a*x + b*y (real a,b)
+template <typename TS>
+void add_to_f64(double2* x, const TS* d, int64_t n, hipStream_t s);                         // x += d
+void sub_d(const double2* a, const double2* b, double2* out, int64_t n, hipStream_t s);    // out = a - b
+void column_norms(const double2* X, int64_t N, int R, double* partial, double* out, hipStream_t s);
+void gather_ports(const Geom& g, const double2* I, int R, double2* Y, hipStream_t s);      // Y (P x R col-major)
+void transpose_nr(const double2* src, double2* dst, int64_t N, int R, bool to_device_layout, hipStream_t s);
+void scale_columns_d(double2* X, const double* scale, int64_t N, int R, hipStream_t s);      // X[n][r] *= scale[r]
+void zero_d(double2* p, int64_t n, hipStream_t s);                                             // fill kernel, no memset
+
+}  // namespace mbt

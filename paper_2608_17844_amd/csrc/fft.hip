@@ -1,0 +1,378 @@
+// Two-level FFT over the lattice (paper eq. (F2): F_{N2} (x) (F_{N1} (x) I_{N0})).
+//
+// Vectors are stored RHS-innermost: x[e][p][r] with element e = iy*nx + ix, so
+// for the lattice transform every (p, r) pair is an independent column
+// c = p*R + r of a batch of B = M*R columns, and the lattice points of one
+// column are B entries apart.  The in-block index is a batch dimension, which
+// is the point of the 4-D arrangement of Sec. III-B; here it is the innermost,
+// contiguous one so that a workgroup streams whole cache lines.
+//
+// The circulant embedding (eq. (multL)) uses a grid Px x Py = 2Lx x 2Ly with
+// Lx >= nx, Ly >= ny (powers of two, at least 8), so that
+// Px >= 2nx - 1 and the cyclic convolution reproduces the Toeplitz product on
+// the cropped outputs.  A zero-padded transform of size 2L splits by output
+// parity into four transforms of size L of pre-twiddled inputs:
+//   X[2a+al][2b+be] = DFT_{Ly x Lx}( x[iy][ix] W_Py^{al iy} W_Px^{be ix} )[a][b],
+// and the cropped inverse is the twiddled sum of the four parity sub-grids.
+// Each workgroup holds an Ly x Lx x W tile (W adjacent columns) in LDS and runs
+// the four sub-transforms there, so X is read once and X^ written once.
+#include "common.h"
+
+namespace mbt {
+
+namespace {
+
+// ------------------------------------------------------------------ small DFTs in registers
+template <typename C, bool INV> __device__ __forceinline__ void dft2(C* v) {
+    C t = v[0];
+    v[0] = cadd(t, v[1]);
+    v[1] = csub(t, v[1]);
+}
+
+template <typename C, bool INV> __device__ __forceinline__ void dft4(C* v) {
+    C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    C c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+    C id = cmul_i(d, INV);   // -i d forward, +i d inverse
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, id);
+    v[3] = csub(b, id);
+}
+
+template <typename C, bool INV> __device__ __forceinline__ void dft8(C* v) {
+    using T = decltype(v[0].x);
+    const T h = (T)0.70710678118654752440;
+    C a0[4], a1[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        a0[n] = cadd(v[n], v[n + 4]);
+        a1[n] = csub(v[n], v[n + 4]);
+    }
+    // a1[n] *= W8^{n}  (conjugate for the inverse)
+    {
+        C t = a1[1];
+        a1[1] = INV ? mk<T>(h * (t.x - t.y), h * (t.x + t.y)) : mk<T>(h * (t.x + t.y), h * (t.y - t.x));
+        a1[2] = cmul_i(a1[2], INV);
+        t = a1[3];
+        a1[3] = INV ? mk<T>(-h * (t.x + t.y), h * (t.x - t.y)) : mk<T>(h * (t.y - t.x), -h * (t.x + t.y));
+    }
+    dft4<C, INV>(a0);
+    dft4<C, INV>(a1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[2 * k] = a0[k];
+        v[2 * k + 1] = a1[k];
+    }
+}
+
+template <typename C, int R, bool INV> __device__ __forceinline__ void dft(C* v) {
+    if constexpr (R == 2) dft2<C, INV>(v);
+    else if constexpr (R == 4) dft4<C, INV>(v);
+    else if constexpr (R == 8) dft8<C, INV>(v);
+}
+
+template <int L> struct Split;
+template <> struct Split<8> { static constexpr int R1 = 8, R2 = 1; };
+template <> struct Split<16> { static constexpr int R1 = 4, R2 = 4; };
+template <> struct Split<32> { static constexpr int R1 = 8, R2 = 4; };
+template <> struct Split<64> { static constexpr int R1 = 8, R2 = 8; };
+
+// In-LDS FFTs of length L along one axis of a tile.  FFT f = (o, w) has its
+// element i at tile[o*ostride + i*stride + w], o < nouter, w < W.
+// Four-step: L = R1*R2, n = n1*R2 + n2, k = k1 + R1*k2;
+//   pass 1: for each n2, DFT_R1 over n1, times W_L^{n2 k1}, stored in place;
+//   pass 2: for each k1, DFT_R2 over n2, stored at k1 + R1*k2.
+// tw is the twiddle table of the full grid P = 2L: W_L^m = tw[2m].
+// OUTER_FAST orders work items so that neighbouring lanes step the smaller stride.
+template <typename T, int L, bool INV, bool OUTER_FAST, int NT, int nouter, int ostride, int stride, int W>
+__device__ __forceinline__ void lds_fft_axis(cplx<T>* tile, const cplx<T>* __restrict__ tw) {
+    using C = cplx<T>;
+    constexpr int R1 = Split<L>::R1, R2 = Split<L>::R2;
+    const int tid = threadIdx.x;
+    if constexpr (R2 == 1) {
+        const int items = nouter * W;
+        for (int it = tid; it < items; it += NT) {
+            const int w = it % W, o = it / W;
+            C* base = tile + o * ostride + w;
+            C v[R1];
+#pragma unroll
+            for (int n = 0; n < R1; ++n) v[n] = base[n * stride];
+            dft<C, R1, INV>(v);
+#pragma unroll
+            for (int n = 0; n < R1; ++n) base[n * stride] = v[n];
+        }
+    } else {
+        const int items1 = nouter * W * R2;
+        for (int it = tid; it < items1; it += NT) {
+            int w = it % W, rest = it / W, o, n2;
+            if (OUTER_FAST) { o = rest % nouter; n2 = rest / nouter; }
+            else { n2 = rest % R2; o = rest / R2; }
+            C* base = tile + o * ostride + w;
+            C v[R1];
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) v[n1] = base[(n1 * R2 + n2) * stride];
+            dft<C, R1, INV>(v);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                C t = tw[(2 * n2 * k1) % (2 * L)];
+                if (INV) t.y = -t.y;
+                base[(k1 * R2 + n2) * stride] = (k1 == 0 || n2 == 0) ? v[k1] : cmul(v[k1], t);
+            }
+        }
+        __syncthreads();
+        const int items2 = nouter * W * R1;
+        constexpr int MAXIT = (nouter * W * R1 + NT - 1) / NT;
+        C reg[MAXIT][R2];
+#pragma unroll
+        for (int i = 0; i < MAXIT; ++i) {
+            const int it = tid + i * NT;
+            if (it < items2) {
+                int w = it % W, rest = it / W, o, k1;
+                if (OUTER_FAST) { o = rest % nouter; k1 = rest / nouter; }
+                else { k1 = rest % R1; o = rest / R1; }
+                const C* base = tile + o * ostride + w;
+#pragma unroll
+                for (int n2 = 0; n2 < R2; ++n2) reg[i][n2] = base[(k1 * R2 + n2) * stride];
+                dft<C, R2, INV>(reg[i]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXIT; ++i) {
+            const int it = tid + i * NT;
+            if (it < items2) {
+                int w = it % W, rest = it / W, o, k1;
+                if (OUTER_FAST) { o = rest % nouter; k1 = rest / nouter; }
+                else { k1 = rest % R1; o = rest / R1; }
+                C* base = tile + o * ostride + w;
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) base[(k1 + R1 * k2) * stride] = reg[i][k2];
+            }
+        }
+    }
+}
+
+constexpr int kNT = 256;
+
+template <typename T, int LX, int LY, int W>
+__global__ __launch_bounds__(kNT) void fft_fwd_pad_kernel(const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Xh,
+                                                          int nx, int ny, int64_t B, const cplx<T>* __restrict__ twx,
+                                                          const cplx<T>* __restrict__ twy) {
+    using C = cplx<T>;
+    constexpr int PX = 2 * LX, NTILE = LX * LY * W;
+    __shared__ C tile[NTILE];
+    const int64_t c0 = (int64_t)blockIdx.x * W;
+    for (int par = 0; par < 4; ++par) {
+        const int al = par >> 1, be = par & 1;
+        for (int t = threadIdx.x; t < NTILE; t += kNT) {
+            const int w = t % W, ix = (t / W) % LX, iy = t / (W * LX);
+            const int64_t c = c0 + w;
+            C v = mk<T>(0, 0);
+            if (ix < nx && iy < ny && c < B) {
+                v = X[(int64_t)(iy * nx + ix) * B + c];
+                if (al && iy) v = cmul(v, twy[iy]);
+                if (be && ix) v = cmul(v, twx[ix]);
+            }
+            tile[t] = v;
+        }
+        __syncthreads();
+        lds_fft_axis<T, LX, false, false, kNT, LY, LX * W, W, W>(tile, twx);
+        __syncthreads();
+        lds_fft_axis<T, LY, false, true, kNT, LX, W, LX * W, W>(tile, twy);
+        __syncthreads();
+        for (int t = threadIdx.x; t < NTILE; t += kNT) {
+            const int w = t % W, b = (t / W) % LX, a = t / (W * LX);
+            const int64_t c = c0 + w;
+            if (c < B) Xh[((int64_t)(2 * a + al) * PX + (2 * b + be)) * B + c] = tile[t];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int LX, int LY, int W>
+__global__ __launch_bounds__(kNT) void fft_inv_crop_kernel(const cplx<T>* __restrict__ Yh, cplx<T>* __restrict__ Y,
+                                                           int nx, int ny, int64_t B, const cplx<T>* __restrict__ twx,
+                                                           const cplx<T>* __restrict__ twy) {
+    using C = cplx<T>;
+    constexpr int PX = 2 * LX, NTILE = LX * LY * W;
+    constexpr int NOWN = (NTILE + kNT - 1) / kNT;
+    __shared__ C tile[NTILE];
+    const int64_t c0 = (int64_t)blockIdx.x * W;
+    C acc[NOWN];
+#pragma unroll
+    for (int i = 0; i < NOWN; ++i) acc[i] = mk<T>(0, 0);
+    for (int par = 0; par < 4; ++par) {
+        const int al = par >> 1, be = par & 1;
+        for (int t = threadIdx.x; t < NTILE; t += kNT) {
+            const int w = t % W, b = (t / W) % LX, a = t / (W * LX);
+            const int64_t c = c0 + w;
+            tile[t] = (c < B) ? Yh[((int64_t)(2 * a + al) * PX + (2 * b + be)) * B + c] : mk<T>(0, 0);
+        }
+        __syncthreads();
+        lds_fft_axis<T, LX, true, false, kNT, LY, LX * W, W, W>(tile, twx);
+        __syncthreads();
+        lds_fft_axis<T, LY, true, true, kNT, LX, W, LX * W, W>(tile, twy);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NOWN; ++i) {
+            const int t = threadIdx.x + i * kNT;
+            if (t < NTILE) {
+                const int ix = (t / W) % LX, iy = t / (W * LX);
+                if (ix < nx && iy < ny) {
+                    C v = tile[t];
+                    if (al && iy) v = cmul(v, cconj(twy[iy]));
+                    if (be && ix) v = cmul(v, cconj(twx[ix]));
+                    acc[i] = cadd(acc[i], v);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NOWN; ++i) {
+        const int t = threadIdx.x + i * kNT;
+        if (t < NTILE) {
+            const int w = t % W, ix = (t / W) % LX, iy = t / (W * LX);
+            const int64_t c = c0 + w;
+            if (ix < nx && iy < ny && c < B) Y[(int64_t)(iy * nx + ix) * B + c] = acc[i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ twiddles and block spectra
+__global__ void twiddle_kernel(int P, double2* tw) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < P) {
+        double s, c;
+        sincospi(2.0 * (double)j / (double)P, &s, &c);
+        tw[j] = make_double2(c, -s);
+    }
+}
+
+// Stage 1 of the block spectrum: tmp[oy][kx][e] = sum_ox T[oy][ox][e] W_Px^{kx*dx}, dx = ox-(nx-1).
+__global__ void embed_x_kernel(const double2* __restrict__ T, double2* __restrict__ tmp, int nx, int noy, int Px,
+                               int MM, const double2* __restrict__ twx) {
+    const int64_t total = (int64_t)noy * Px * MM;
+    const int nox = 2 * nx - 1;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int e = (int)(t % MM);
+        const int kx = (int)((t / MM) % Px);
+        const int oy = (int)(t / ((int64_t)MM * Px));
+        double sr = 0, si = 0;
+        for (int ox = 0; ox < nox; ++ox) {
+            const int dxo = ox - (nx - 1);
+            const int idx = (int)((((int64_t)kx * dxo) % Px + Px) % Px);
+            const double2 w = twx[idx];
+            const double2 v = T[((int64_t)oy * nox + ox) * MM + e];
+            sr += v.x * w.x - v.y * w.y;
+            si += v.x * w.y + v.y * w.x;
+        }
+        tmp[t] = make_double2(sr, si);
+    }
+}
+
+// Stage 2: Chat[ky][kx][e] = scale * sum_oy tmp[oy][kx][e] W_Py^{ky*dy}.
+__global__ void embed_y_kernel(const double2* __restrict__ tmp, double2* __restrict__ Chat, int ny, int Px, int Py,
+                               int MM, double scale, const double2* __restrict__ twy) {
+    const int64_t total = (int64_t)Py * Px * MM;
+    const int noy = 2 * ny - 1;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int e = (int)(t % MM);
+        const int kx = (int)((t / MM) % Px);
+        const int ky = (int)(t / ((int64_t)MM * Px));
+        double sr = 0, si = 0;
+        for (int oy = 0; oy < noy; ++oy) {
+            const int dyo = oy - (ny - 1);
+            const int idx = (int)((((int64_t)ky * dyo) % Py + Py) % Py);
+            const double2 w = twy[idx];
+            const double2 v = tmp[((int64_t)oy * Px + kx) * MM + e];
+            sr += v.x * w.x - v.y * w.y;
+            si += v.x * w.y + v.y * w.x;
+        }
+        Chat[t] = make_double2(sr * scale, si * scale);
+    }
+}
+
+template <typename T> constexpr int tile_w(int lx, int ly) {
+    int w = (int)(65536 / (lx * ly * (int)sizeof(cplx<T>)));
+    return w > 16 ? 16 : (w < 1 ? 1 : w);
+}
+
+template <typename T, bool FWD, int LX, int LY>
+void launch_fft_t(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
+                  hipStream_t s) {
+    constexpr int W = tile_w<T>(LX, LY);
+    const int64_t blocks = (B + W - 1) / W;
+    MBT_REQUIRE(blocks < (1LL << 31), "fft: batch too large");
+    if (FWD)
+        hipLaunchKernelGGL((fft_fwd_pad_kernel<T, LX, LY, W>), dim3((unsigned)blocks), dim3(kNT), 0, s, in, out,
+                           g.nx, g.ny, B, twx, twy);
+    else
+        hipLaunchKernelGGL((fft_inv_crop_kernel<T, LX, LY, W>), dim3((unsigned)blocks), dim3(kNT), 0, s, in, out,
+                           g.nx, g.ny, B, twx, twy);
+    MBT_LAUNCH_CHECK();
+}
+
+template <typename T, bool FWD, int LX>
+void dispatch_ly(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
+                 hipStream_t s) {
+    switch (g.Ly) {
+        case 8: launch_fft_t<T, FWD, LX, 8>(g, in, out, B, twx, twy, s); break;
+        case 16: launch_fft_t<T, FWD, LX, 16>(g, in, out, B, twx, twy, s); break;
+        case 32: launch_fft_t<T, FWD, LX, 32>(g, in, out, B, twx, twy, s); break;
+        case 64: launch_fft_t<T, FWD, LX, 64>(g, in, out, B, twx, twy, s); break;
+        default: throw Error(-1, "fft: unsupported grid (ny > 64)");
+    }
+}
+
+template <typename T, bool FWD>
+void dispatch(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
+              hipStream_t s) {
+    switch (g.Lx) {
+        case 8: dispatch_ly<T, FWD, 8>(g, in, out, B, twx, twy, s); break;
+        case 16: dispatch_ly<T, FWD, 16>(g, in, out, B, twx, twy, s); break;
+        case 32: dispatch_ly<T, FWD, 32>(g, in, out, B, twx, twy, s); break;
+        case 64: dispatch_ly<T, FWD, 64>(g, in, out, B, twx, twy, s); break;
+        default: throw Error(-1, "fft: unsupported grid (nx > 64)");
+    }
+}
+
+}  // namespace
+
+void make_twiddles(int P, double2* tw, hipStream_t s) {
+    hipLaunchKernelGGL(twiddle_kernel, dim3((P + 255) / 256), dim3(256), 0, s, P, tw);
+    MBT_LAUNCH_CHECK();
+}
+
+void embed_blocks_fft(const Geom& g, const double2* T, double2* Chat, double scale, double2* scratch, hipStream_t s) {
+    // scratch: noy * Px * M*M complex; twiddle tables are placed after it
+    const int MM = g.M * g.M;
+    double2* tmp = scratch;
+    double2* twx = scratch + (int64_t)g.noy * g.Px * MM;
+    double2* twy = twx + g.Px;
+    make_twiddles(g.Px, twx, s);
+    make_twiddles(g.Py, twy, s);
+    hipLaunchKernelGGL(embed_x_kernel, dim3(2048), dim3(256), 0, s, T, tmp, g.nx, g.noy, g.Px, MM, twx);
+    MBT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(embed_y_kernel, dim3(2048), dim3(256), 0, s, tmp, Chat, g.ny, g.Px, g.Py, MM, scale, twy);
+    MBT_LAUNCH_CHECK();
+}
+
+template <typename T>
+void fft_fwd_pad(const Geom& g, const cplx<T>* X, cplx<T>* Xh, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
+                 hipStream_t s) {
+    dispatch<T, true>(g, X, Xh, B, twx, twy, s);
+}
+
+template <typename T>
+void fft_inv_crop(const Geom& g, const cplx<T>* Yh, cplx<T>* Y, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
+                  hipStream_t s) {
+    dispatch<T, false>(g, Yh, Y, B, twx, twy, s);
+}
+
+template void fft_fwd_pad<double>(const Geom&, const double2*, double2*, int64_t, const double2*, const double2*, hipStream_t);
+template void fft_fwd_pad<float>(const Geom&, const float2*, float2*, int64_t, const float2*, const float2*, hipStream_t);
+template void fft_inv_crop<double>(const Geom&, const double2*, double2*, int64_t, const double2*, const double2*, hipStream_t);
+template void fft_inv_crop<float>(const Geom&, const float2*, float2*, int64_t, const float2*, const float2*, hipStream_t);
+
+}  // namespace mbt

@@ -1,0 +1,66 @@
+// Batched GMRES driver interface and the device arena it allocates from (internal).
+#pragma once
+
+#include <functional>
+#include <vector>
+
+#include "common.h"
+
+namespace mbt {
+
+// Bump allocator over one device buffer; reset per solve.  No hipMalloc inside.
+struct DevArena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t off = 0;
+    template <typename T> T* get(size_t count) {
+        const size_t bytes = ((sizeof(T) * count) + 255) & ~(size_t)255;
+        if (off + bytes > cap) throw Error(-2, "device workspace exhausted (internal sizing error)");
+        T* p = reinterpret_cast<T*>(base + off);
+        off += bytes;
+        return p;
+    }
+};
+
+// Per-RHS recurrence state, passed by value to kernels.
+struct GmresState {
+    double tol;
+    double2* H;      // [m][m+1][R]  column j, row i
+    double* cs;      // [m][R]
+    double2* sn;     // [m][R]
+    double2* g;      // [m+1][R]
+    double* bnorm;   // [R]
+    double* beta;    // [R]
+    double* scale;   // [R]  1/||w|| for the next basis vector, 0 if the RHS stopped
+    int* active;     // [R]  iterating in this cycle
+    int* conv;       // [R]  met the tolerance
+    int* flag;       // [R]  non-finite value met
+    int* kcyc;       // [R]  Arnoldi steps in this cycle
+    int* iters;      // [R]  Arnoldi steps in total
+};
+
+struct GmresParams {
+    int restart = 50;
+    double tol = 1e-10;
+    int max_cycles = 400;
+    int matvecs_per_apply = 1;
+    int* host_count = nullptr;   // pinned host int for the active-count readback
+};
+
+struct GmresResult {
+    std::vector<int> iters, conv, flag;
+    int cycles = 0;
+    int64_t matvecs = 0;
+};
+
+int64_t gmres_rows_per_chunk(int64_t N);
+int gmres_nchunk(int64_t N);
+size_t gmres_state_bytes(int64_t N, int R, int m);
+
+// Solves A x = b for R independent columns (b, basis of type TB = double2 or
+// float2; x accumulated in FP64).  Vbasis holds (restart+1) vectors of N x R.
+template <typename TB>
+GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, const TB* b, double2* x, TB* Vbasis,
+                          int64_t N, int R, const GmresParams& prm, DevArena& arena, hipStream_t s);
+
+}  // namespace mbt

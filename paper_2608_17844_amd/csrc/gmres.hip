@@ -1,0 +1,453 @@
+// Batched restarted GMRES(m): one independent Krylov solve per right-hand side,
+// all sharing the batched operator (the paper's "new M1" GMRES with the
+// normal-equation strategy, or GMRES with the element-block preconditioner).
+//
+// The paper uses MATLAB's GMRES and states no details; this solver fixes them:
+// x0 = 0; Arnoldi by classical Gram-Schmidt applied twice (CGS2); complex
+// Givens rotations (c real, s complex, c = 0 and s = 1 when the pivot is zero);
+// stop as soon as the least-squares residual |g_{j+1}| <= tol * ||b||; the
+// explicit residual b - A x is recomputed at every restart.
+//
+// Vectors are RHS-innermost, v[n][r]: a lane owns one RHS and walks rows, so
+// every per-RHS dot product is accumulated in a fixed order that does not
+// depend on how many other RHS share the batch (bit-identical results alone or
+// batched).  Rows are split into fixed chunks (a function of N only) whose
+// partial sums are reduced in chunk order by a second kernel.
+//
+// HBM traffic per Arnoldi step j is dominated by the basis reads.  CGS2 is
+// fused into three passes over V_{0..j}: (1) h = V^H w; (2) w <- w - V h
+// together with h2 = V^H w; (3) w <- w - V h2 together with ||w||^2.  The four
+// waves of a workgroup share the same rows and RHS and split the basis
+// vectors; the per-row combination is reduced across waves through LDS.
+// The basis may be stored in FP32 (reduced-precision inner solves) while all
+// dot products, norms and the Hessenberg/Givens recurrences stay FP64.
+#include "common.h"
+#include "gmres.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace mbt {
+
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kMaxG = 16;              // basis vectors per wave -> restart <= 63
+constexpr int kMaxVec = kWaves * kMaxG;
+
+__device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
+__device__ __forceinline__ double2 ld2(const float2* p) { float2 v = *p; return make_double2(v.x, v.y); }
+__device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
+// MODE 0: h[i] = sum_n conj(V_i[n]) w[n]                         (partials per chunk)
+// MODE 1: w <- w - sum_i coef_i V_i ; h2[i] = sum_n conj(V_i) w   (partials per chunk)
+// MODE 2: w <- w - sum_i coef_i V_i ; ||w||^2                      (partials per chunk)
+// MODE 3: out <- out + sum_i coef_i V_i  (out is FP64; solution update)
+template <typename TB, typename TO, int MODE>
+__global__ __launch_bounds__(256) void arnoldi_kernel(const TB* __restrict__ V, int64_t vstride, int nvec,
+                                                      const double2* __restrict__ coef, TO* w, int64_t N, int R,
+                                                      int64_t rows_per_chunk, double2* __restrict__ partial) {
+    __shared__ double2 xch[2][kWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r = blockIdx.x * 64 + lane;
+    const bool live = r < R;
+    const int64_t chunk = blockIdx.y;
+    const int64_t n0 = chunk * rows_per_chunk;
+    const int64_t n1 = min(N, n0 + rows_per_chunk);
+
+    double2 acc[kMaxG];
+    double2 cf[kMaxG];
+#pragma unroll
+    for (int g = 0; g < kMaxG; ++g) {
+        acc[g] = make_double2(0, 0);
+        const int i = wave + kWaves * g;
+        cf[g] = (MODE != 0 && live && i < nvec) ? coef[(int64_t)i * R + r] : make_double2(0, 0);
+    }
+    double nrm = 0.0;
+    int buf = 0;
+    for (int64_t n = n0; n < n1; ++n) {
+        const int64_t off = n * R + r;
+        if (MODE == 0) {
+            if (live) {
+                const double2 wv = ld2(w + off);
+#pragma unroll
+                for (int g = 0; g < kMaxG; ++g) {
+                    const int i = wave + kWaves * g;
+                    if (i < nvec) acc[g] = cadd(acc[g], cmulc(ld2(V + i * vstride + off), wv));
+                }
+            }
+        } else {
+            double2 vv[kMaxG];
+            double2 u = make_double2(0, 0);
+            double2 wv = make_double2(0, 0);
+            if (live) {
+                wv = ld2(w + off);
+#pragma unroll
+                for (int g = 0; g < kMaxG; ++g) {
+                    const int i = wave + kWaves * g;
+                    vv[g] = (i < nvec) ? ld2(V + i * vstride + off) : make_double2(0, 0);
+                    u = cadd(u, cmul(cf[g], vv[g]));
+                }
+            }
+            xch[buf][wave][lane] = u;
+            __syncthreads();
+            double2 tot = xch[buf][0][lane];
+#pragma unroll
+            for (int k = 1; k < kWaves; ++k) tot = cadd(tot, xch[buf][k][lane]);
+            buf ^= 1;
+            if (live) {
+                const double2 nw = (MODE == 3) ? cadd(wv, tot) : csub(wv, tot);
+                if (MODE == 1) {
+#pragma unroll
+                    for (int g = 0; g < kMaxG; ++g) acc[g] = cadd(acc[g], cmulc(vv[g], nw));
+                } else if (MODE == 2) {
+                    nrm += nw.x * nw.x + nw.y * nw.y;
+                }
+                if (wave == 0) st2(w + off, nw);
+            }
+        }
+    }
+    if (!live) return;
+    if (MODE == 0 || MODE == 1) {
+#pragma unroll
+        for (int g = 0; g < kMaxG; ++g) {
+            const int i = wave + kWaves * g;
+            if (i < nvec) partial[(chunk * nvec + i) * R + r] = acc[g];
+        }
+    } else if (MODE == 2) {
+        if (wave == 0) partial[chunk * R + r] = make_double2(nrm, 0.0);
+    }
+}
+
+// out[i][r] = sum over chunks of partial[chunk][i][r], in chunk order
+__global__ void reduce_partials_kernel(const double2* __restrict__ partial, int nchunk, int nvec, int R,
+                                       double2* __restrict__ out) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nvec * R) return;
+    const int i = (int)(t / R), r = (int)(t % R);
+    double2 s = make_double2(0, 0);
+    for (int c = 0; c < nchunk; ++c) s = cadd(s, partial[((int64_t)c * nvec + i) * R + r]);
+    out[t] = s;
+}
+
+template <typename TB>
+__global__ void colnorm2_kernel(const TB* __restrict__ X, int64_t N, int R, int64_t rows_per_chunk,
+                                double2* __restrict__ partial) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t chunk = blockIdx.y;
+    if (r >= R) return;
+    const int64_t n0 = chunk * rows_per_chunk, n1 = min(N, n0 + rows_per_chunk);
+    double s = 0;
+    for (int64_t n = n0; n < n1; ++n) {
+        const double2 v = ld2(X + n * R + r);
+        s += v.x * v.x + v.y * v.y;
+    }
+    partial[chunk * R + r] = make_double2(s, 0.0);
+}
+
+__device__ __forceinline__ double sum_norm_partials(const double2* partial, int nchunk, int R, int r) {
+    double s = 0;
+    for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * R + r].x;
+    return sqrt(s);
+}
+
+// Start of a restart cycle: beta = ||r||; decide convergence at restart.
+__global__ void cycle_init_kernel(GmresState st, const double2* __restrict__ partial, int nchunk, int R, int first) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const double beta = sum_norm_partials(partial, nchunk, R, r);
+    if (first) {
+        st.bnorm[r] = beta;
+        st.conv[r] = (beta == 0.0) ? 1 : 0;
+        st.iters[r] = 0;
+        st.flag[r] = 0;
+    }
+    st.beta[r] = beta;
+    st.kcyc[r] = 0;
+    int act = 0;
+    if (!st.conv[r] && !st.flag[r]) {
+        if (!(beta == beta) || isinf(beta)) {
+            st.flag[r] = 1;
+        } else if (beta <= st.tol * st.bnorm[r]) {
+            st.conv[r] = 1;
+        } else {
+            act = 1;
+        }
+    }
+    st.active[r] = act;
+    st.scale[r] = act ? 1.0 / beta : 0.0;
+    st.g[r] = make_double2(act ? beta : 0.0, 0.0);
+}
+
+// Arnoldi step j bookkeeping: Hessenberg column, Givens rotations, residual
+// estimate, per-RHS stop decision and the normalisation factor of v_{j+1}.
+__global__ void finalize_kernel(GmresState st, const double2* __restrict__ h1, const double2* __restrict__ h2,
+                                const double2* __restrict__ npart, int nchunk, int R, int j, int m) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    if (!st.active[r]) {
+        st.scale[r] = 0.0;
+        return;
+    }
+    const double hn = sum_norm_partials(npart, nchunk, R, r);
+    const int64_t ldH = (int64_t)(m + 1) * R;   // H[j][i][r]: column j, row i
+    double2* Hj = st.H + (int64_t)j * ldH;
+    for (int i = 0; i <= j; ++i) Hj[(int64_t)i * R + r] = cadd(h1[(int64_t)i * R + r], h2[(int64_t)i * R + r]);
+    // previous rotations
+    for (int i = 0; i < j; ++i) {
+        const double c = st.cs[(int64_t)i * R + r];
+        const double2 s = st.sn[(int64_t)i * R + r];
+        const double2 a = Hj[(int64_t)i * R + r], b = Hj[(int64_t)(i + 1) * R + r];
+        Hj[(int64_t)i * R + r] = cadd(make_double2(c * a.x, c * a.y), cmul(s, b));
+        Hj[(int64_t)(i + 1) * R + r] = csub(make_double2(c * b.x, c * b.y), cmulc(s, a));
+    }
+    const double2 h1v = Hj[(int64_t)j * R + r];
+    double c;
+    double2 s;
+    const double a1 = hypot(h1v.x, h1v.y);
+    if (a1 == 0.0) {
+        c = 0.0;
+        s = make_double2(1.0, 0.0);
+    } else {
+        const double t = hypot(a1, hn);
+        c = a1 / t;
+        // s = (h1/|h1|) * conj(hn) / t, hn real
+        s = make_double2(h1v.x / a1 * hn / t, h1v.y / a1 * hn / t);
+    }
+    st.cs[(int64_t)j * R + r] = c;
+    st.sn[(int64_t)j * R + r] = s;
+    Hj[(int64_t)j * R + r] = cadd(make_double2(c * h1v.x, c * h1v.y), make_double2(s.x * hn, s.y * hn));
+    Hj[(int64_t)(j + 1) * R + r] = make_double2(0, 0);
+    const double2 gj = st.g[(int64_t)j * R + r];
+    const double2 gn = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));  // -conj(s) g_j
+    st.g[(int64_t)j * R + r] = make_double2(c * gj.x, c * gj.y);
+    st.g[(int64_t)(j + 1) * R + r] = gn;
+    st.iters[r] += 1;
+    st.kcyc[r] = j + 1;
+    const double res = hypot(gn.x, gn.y);
+    const bool bad = !(hn == hn) || isinf(hn) || !(res == res);
+    if (bad) {
+        st.flag[r] = 1;
+        st.active[r] = 0;
+        st.scale[r] = 0.0;
+        return;
+    }
+    if (res <= st.tol * st.bnorm[r] || hn == 0.0 || j == m - 1) {
+        st.active[r] = 0;
+        st.scale[r] = 0.0;
+    } else {
+        st.scale[r] = 1.0 / hn;
+    }
+}
+
+template <typename TB>
+__global__ void scale_cols_kernel(TB* __restrict__ v, const double* __restrict__ scale, int64_t N, int R) {
+    const int64_t total = N * R;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const double sc = scale[t % R];
+        const double2 x = ld2(v + t);
+        st2(v + t, make_double2(x.x * sc, x.y * sc));
+    }
+}
+
+// End of cycle: y = R_k^{-1} g_k per RHS (k = steps done this cycle), and the
+// convergence verdict from |g_k|.
+__global__ void cycle_solve_kernel(GmresState st, int R, int m, double2* __restrict__ y) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int k = st.kcyc[r];
+    const int64_t ldH = (int64_t)(m + 1) * R;
+    for (int i = 0; i < m; ++i) y[(int64_t)i * R + r] = make_double2(0, 0);
+    if (k == 0 || st.flag[r]) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double2 acc = st.g[(int64_t)i * R + r];
+        for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(st.H[(int64_t)l * ldH + (int64_t)i * R + r], y[(int64_t)l * R + r]));
+        const double2 d = st.H[(int64_t)i * ldH + (int64_t)i * R + r];
+        const double den = d.x * d.x + d.y * d.y;
+        y[(int64_t)i * R + r] = make_double2((acc.x * d.x + acc.y * d.y) / den, (acc.y * d.x - acc.x * d.y) / den);
+    }
+    const double2 gk = st.g[(int64_t)k * R + r];
+    if (hypot(gk.x, gk.y) <= st.tol * st.bnorm[r]) st.conv[r] = 1;
+}
+
+// sum of active flags into one int (single workgroup)
+__global__ void count_kernel(const int* __restrict__ a, int R, int* __restrict__ out) {
+    __shared__ int s[256];
+    int v = 0;
+    for (int r = threadIdx.x; r < R; r += 256) v += a[r];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0];
+}
+
+// r = b - Ax (in place on Ax), both of the basis type
+template <typename TB>
+__global__ void residual_kernel(const TB* __restrict__ b, TB* __restrict__ ax, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        st2(ax + t, csub(ld2(b + t), ld2(ax + t)));
+}
+
+template <typename TB>
+__global__ void copy_kernel(const TB* __restrict__ src, TB* __restrict__ dst, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        dst[t] = src[t];
+}
+
+template <typename TB>
+__global__ void from_f64_kernel(const double2* __restrict__ src, TB* __restrict__ dst, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        st2(dst + t, src[t]);
+}
+
+__global__ void zero_kernel(double2* __restrict__ p, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = make_double2(0, 0);
+}
+
+inline unsigned ew_grid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536));
+}
+
+}  // namespace
+
+int64_t gmres_rows_per_chunk(int64_t N) { return std::max<int64_t>(32, (N + 127) / 128); }
+int gmres_nchunk(int64_t N) { return (int)((N + gmres_rows_per_chunk(N) - 1) / gmres_rows_per_chunk(N)); }
+
+size_t gmres_state_bytes(int64_t N, int R, int m) {
+    const int nchunk = gmres_nchunk(N);
+    size_t s = 0;
+    s += sizeof(double2) * (size_t)(m + 1) * (m + 1) * R;      // H (column j has m+1 rows, one spare)
+    s += sizeof(double) * (size_t)m * R;                       // cs
+    s += sizeof(double2) * (size_t)m * R;                      // sn
+    s += sizeof(double2) * (size_t)(m + 1) * R;                // g
+    s += sizeof(double2) * (size_t)(m + 1) * R * 2;            // h1, h2
+    s += sizeof(double2) * (size_t)m * R;                      // y
+    s += sizeof(double2) * (size_t)nchunk * (m + 1) * R;       // partials
+    s += sizeof(double) * (size_t)R * 4 + sizeof(int) * (size_t)R * 6 + 64;
+    return s;
+}
+
+template <typename TB>
+GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, const TB* b, double2* x, TB* Vbasis,
+                          int64_t N, int R, const GmresParams& prm, DevArena& arena, hipStream_t s) {
+    const int m = prm.restart;
+    MBT_REQUIRE(m >= 1 && m + 1 <= kMaxVec, "gmres: restart must be in 1..63");
+    const int64_t rpc = gmres_rows_per_chunk(N);
+    const int nchunk = gmres_nchunk(N);
+    const int64_t vs = N * R;   // basis vector stride
+
+    GmresState st;
+    st.tol = prm.tol;
+    st.H = arena.get<double2>((size_t)(m + 1) * (m + 1) * R);
+    st.cs = arena.get<double>((size_t)m * R);
+    st.sn = arena.get<double2>((size_t)m * R);
+    st.g = arena.get<double2>((size_t)(m + 1) * R);
+    st.bnorm = arena.get<double>(R);
+    st.beta = arena.get<double>(R);
+    st.scale = arena.get<double>(R);
+    st.active = arena.get<int>(R);
+    st.conv = arena.get<int>(R);
+    st.flag = arena.get<int>(R);
+    st.kcyc = arena.get<int>(R);
+    st.iters = arena.get<int>(R);
+    int* d_count = arena.get<int>(16);
+    double2* h1 = arena.get<double2>((size_t)(m + 1) * R);
+    double2* h2 = arena.get<double2>((size_t)(m + 1) * R);
+    double2* y = arena.get<double2>((size_t)m * R);
+    double2* partial = arena.get<double2>((size_t)nchunk * (m + 1) * R);
+
+    GmresResult res;
+    res.iters.assign(R, 0);
+    res.conv.assign(R, 0);
+    res.flag.assign(R, 0);
+
+    const dim3 gA((R + 63) / 64, nchunk), bA(256);
+    const dim3 gR((R + 255) / 256), bR(256);
+    int* h_count = prm.host_count;
+
+    auto count_active = [&]() -> int {
+        hipLaunchKernelGGL(count_kernel, dim3(1), dim3(256), 0, s, st.active, R, d_count);
+        MBT_LAUNCH_CHECK();
+        MBT_HIP(hipMemcpyAsync(h_count, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+        MBT_HIP(hipStreamSynchronize(s));
+        return *h_count;
+    };
+
+    // x = 0, r0 = b
+    hipLaunchKernelGGL(zero_kernel, dim3(ew_grid(vs)), dim3(256), 0, s, x, vs);
+    hipLaunchKernelGGL((copy_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, b, Vbasis, vs);
+    MBT_LAUNCH_CHECK();
+    bool first = true;
+    for (int cycle = 0; cycle < prm.max_cycles; ++cycle) {
+        // beta = ||r|| (r sits in V_0)
+        hipLaunchKernelGGL((colnorm2_kernel<TB>), dim3((R + 63) / 64, nchunk), dim3(64), 0, s, Vbasis, N, R, rpc, partial);
+        hipLaunchKernelGGL(cycle_init_kernel, gR, bR, 0, s, st, partial, nchunk, R, first ? 1 : 0);
+        MBT_LAUNCH_CHECK();
+        first = false;
+        if (count_active() == 0) break;
+        res.cycles++;
+        hipLaunchKernelGGL((scale_cols_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, Vbasis, st.scale, N, R);
+        MBT_LAUNCH_CHECK();
+        int steps = 0;
+        for (int j = 0; j < m; ++j) {
+            steps = j + 1;
+            TB* vj = Vbasis + (int64_t)j * vs;
+            TB* w = Vbasis + (int64_t)(j + 1) * vs;
+            apply(vj, w);
+            res.matvecs += prm.matvecs_per_apply;
+            const int nvec = j + 1;
+            hipLaunchKernelGGL((arnoldi_kernel<TB, TB, 0>), gA, bA, 0, s, Vbasis, vs, nvec, nullptr, w, N, R, rpc, partial);
+            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nvec * R + 255) / 256)), bR, 0, s,
+                               partial, nchunk, nvec, R, h1);
+            hipLaunchKernelGGL((arnoldi_kernel<TB, TB, 1>), gA, bA, 0, s, Vbasis, vs, nvec, h1, w, N, R, rpc, partial);
+            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nvec * R + 255) / 256)), bR, 0, s,
+                               partial, nchunk, nvec, R, h2);
+            hipLaunchKernelGGL((arnoldi_kernel<TB, TB, 2>), gA, bA, 0, s, Vbasis, vs, nvec, h2, w, N, R, rpc, partial);
+            hipLaunchKernelGGL(finalize_kernel, gR, bR, 0, s, st, h1, h2, partial, nchunk, R, j, m);
+            hipLaunchKernelGGL((scale_cols_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, w, st.scale, N, R);
+            MBT_LAUNCH_CHECK();
+            if (count_active() == 0) break;
+        }
+        // y = R^{-1} g ; x += V y
+        hipLaunchKernelGGL(cycle_solve_kernel, gR, bR, 0, s, st, R, m, y);
+        MBT_LAUNCH_CHECK();
+        hipLaunchKernelGGL((arnoldi_kernel<TB, double2, 3>), gA, bA, 0, s, Vbasis, vs, steps, y, x, N, R, rpc, partial);
+        MBT_LAUNCH_CHECK();
+        // explicit residual r = b - A x into V_0 (x cast to the basis type into V_1 first)
+        TB* xb = Vbasis + vs;
+        hipLaunchKernelGGL((from_f64_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, x, xb, vs);
+        MBT_LAUNCH_CHECK();
+        // all converged? then skip the residual
+        std::vector<int> conv(R);
+        MBT_HIP(hipMemcpyAsync(conv.data(), st.conv, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        std::vector<int> flag(R);
+        MBT_HIP(hipMemcpyAsync(flag.data(), st.flag, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        MBT_HIP(hipStreamSynchronize(s));
+        bool all = true;
+        for (int r = 0; r < R; ++r) all = all && (conv[r] || flag[r]);
+        if (all) break;
+        apply(xb, Vbasis);
+        res.matvecs += prm.matvecs_per_apply;
+        hipLaunchKernelGGL((residual_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, b, Vbasis, vs);
+        MBT_LAUNCH_CHECK();
+    }
+    MBT_HIP(hipMemcpyAsync(res.iters.data(), st.iters, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipMemcpyAsync(res.conv.data(), st.conv, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipMemcpyAsync(res.flag.data(), st.flag, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipStreamSynchronize(s));
+    return res;
+}
+
+template GmresResult gmres_batched<double2>(const std::function<void(const double2*, double2*)>&, const double2*,
+                                            double2*, double2*, int64_t, int, const GmresParams&, DevArena&, hipStream_t);
+template GmresResult gmres_batched<float2>(const std::function<void(const float2*, float2*)>&, const float2*, double2*,
+                                           float2*, int64_t, int, const GmresParams&, DevArena&, hipStream_t);
+
+}  // namespace mbt

@@ -1,0 +1,110 @@
+// Host runtime objects shared by the C-ABI entry points and the server (internal).
+#pragma once
+
+#include <chrono>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mbt.h"
+#include "common.h"
+#include "gmres.h"
+
+namespace mbt {
+
+// Owning device buffer (hipMalloc / hipFree on the owner's device).
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void alloc(size_t b) {
+        release();
+        if (b) {
+            hipError_t e = hipMalloc(&p, b);
+            if (e != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                throw Error(-2, "hipMalloc of " + std::to_string(b) + " bytes failed");
+            }
+            bytes = b;
+        }
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Per (geometry, frequency) device data: blocks, their spectra, preconditioner inverses.
+struct OpData {
+    Geom g;
+    double s = 0, k = 0;
+    DBuf T, Chat, tw, PkInv, PaInv;            // FP64
+    DBuf Chat32, tw32, PkInv32, PaInv32;       // FP32 copies for reduced-precision inner solves
+    bool has_pa = false, has32 = false;
+    size_t bytes() const {
+        return T.bytes + Chat.bytes + tw.bytes + PkInv.bytes + PaInv.bytes + Chat32.bytes + tw32.bytes +
+               PkInv32.bytes + PaInv32.bytes;
+    }
+};
+
+// A stream with its own workspace; the context has one, each server slot another.
+struct Worker {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DBuf ws;
+    int* host_count = nullptr;   // pinned
+    explicit Worker(int dev);
+    ~Worker();
+    void ensure(size_t bytes);
+};
+
+struct SolveOut {
+    std::vector<int> iters;
+    int cycles = 0, outer = 0, nconv = 0, nflag = 0;
+    int64_t matvecs = 0;
+    double relres_max = 0;
+};
+
+}  // namespace mbt
+
+struct mbt_array {
+    mbt::Geom g;
+    mbt_dipole elem;
+    mbt_lattice lat;
+};
+
+struct mbt_ctx {
+    int device = 0;
+    size_t budget = 0;
+    std::unique_ptr<mbt::Worker> main;
+    std::mutex cache_mu;
+    std::map<std::string, std::shared_ptr<mbt::OpData>> cache;
+    std::list<std::string> lru;
+    size_t cache_bytes = 0, cache_limit = 0;
+    std::mutex api_mu;   // serialises entry points that use the context's own worker
+};
+
+namespace mbt {
+
+Geom make_geom(const mbt_dipole& d, const mbt_lattice& l);
+void validate_opts(const mbt_solve_opts& o);
+std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_pa, bool need32, Worker& wk);
+size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o);
+int choose_chunk(mbt_ctx* ctx, const Geom& g, int R, const mbt_solve_opts& o);
+// Solves Z X = V for R device columns (layout [n][r]); X receives FP64 currents.
+SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, int R, double2* X, Worker& wk,
+                   DevArena& arena);
+// All-port solve for one frequency; Ydev (P x nports column-major) filled on the device.
+SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t* ports, int nports,
+                    const mbt_solve_opts& o, double2* Ydev, Worker& wk, mbt_stats* st);
+
+}  // namespace mbt

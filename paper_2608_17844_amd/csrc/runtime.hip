@@ -1,0 +1,958 @@
+// C-ABI entry points and the host runtime: contexts, the per-(array, frequency)
+// operator cache, the batched solve drivers (FP64, and reduced precision with
+// FP64 iterative refinement), port extraction and the test hooks.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+#include "extract.h"
+
+using namespace mbt;
+
+namespace {
+
+thread_local std::string g_err;
+
+mbt_status set_err(int code, const std::string& m) {
+    g_err = m;
+    return (mbt_status)code;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+#define API_BEGIN \
+    g_err.clear(); \
+    try {
+#define API_END                                                                    \
+    }                                                                              \
+    catch (const mbt::Error& e) { return set_err(e.code, e.what()); }              \
+    catch (const std::bad_alloc&) { return set_err(MBT_ENOMEM, "host allocation failed"); } \
+    catch (const std::exception& e) { return set_err(MBT_EDEVICE, e.what()); }     \
+    return MBT_OK;
+
+namespace mbt {
+
+// ------------------------------------------------------------------ workers
+Worker::Worker(int dev) : device(dev) {
+    MBT_HIP(hipSetDevice(dev));
+    MBT_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    MBT_HIP(hipHostMalloc((void**)&host_count, sizeof(int) * 16, hipHostMallocDefault));
+}
+
+Worker::~Worker() {
+    (void)hipSetDevice(device);
+    if (stream) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipStreamDestroy(stream);
+    }
+    ws.release();
+    if (host_count) (void)hipHostFree(host_count);
+}
+
+void Worker::ensure(size_t bytes) {
+    if (ws.bytes >= bytes) return;
+    MBT_HIP(hipStreamSynchronize(stream));
+    ws.alloc(bytes + (bytes >> 4));
+}
+
+// ------------------------------------------------------------------ geometry and options
+static int pow2_at_least(int n, int lo) {
+    int p = lo;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+Geom make_geom(const mbt_dipole& d, const mbt_lattice& l) {
+    MBT_REQUIRE(d.nbases >= 1 && d.nbases % 2 == 1, "nbases must be odd and >= 1");
+    MBT_REQUIRE(d.nbases <= 32, "nbases above 32 is not supported");
+    MBT_REQUIRE(d.radius > 0 && d.length > 0 && std::isfinite(d.radius) && std::isfinite(d.length),
+                "dipole length and radius must be positive");
+    MBT_REQUIRE(l.nx >= 1 && l.ny >= 1 && l.nx <= 64 && l.ny <= 64, "lattice size must be within 1..64 per axis");
+    MBT_REQUIRE(l.dx > 0 && l.dy > 0 && std::isfinite(l.dx) && std::isfinite(l.dy), "lattice spacing must be positive");
+    Geom g;
+    g.nx = l.nx;
+    g.ny = l.ny;
+    g.M = d.nbases;
+    g.dx = l.dx;
+    g.dy = l.dy;
+    g.L = d.length;
+    g.a = d.radius;
+    g.P = l.nx * l.ny;
+    g.N = (int64_t)g.P * g.M;
+    g.Lx = pow2_at_least(l.nx, 8);
+    g.Ly = pow2_at_least(l.ny, 8);
+    g.Px = 2 * g.Lx;
+    g.Py = 2 * g.Ly;
+    g.nox = 2 * l.nx - 1;
+    g.noy = 2 * l.ny - 1;
+    g.pc = (g.M - 1) / 2;
+    return g;
+}
+
+void validate_opts(const mbt_solve_opts& o) {
+    MBT_REQUIRE(o.prec == MBT_FP64 || o.prec == MBT_FP32, "precision not supported (FP64 or FP32)");
+    MBT_REQUIRE(o.pc == MBT_PC_NORMAL_EQ || o.pc == MBT_PC_ELEMENT_BLOCK, "unknown preconditioner");
+    MBT_REQUIRE(o.restart >= 1 && o.restart <= 63, "restart must be in 1..63");
+    MBT_REQUIRE(o.tol > 0 && o.tol < 1, "tol must be in (0, 1)");
+    MBT_REQUIRE(o.max_cycles >= 1, "max_cycles must be >= 1");
+    MBT_REQUIRE(o.prec == MBT_FP64 || (o.refine_max >= 1 && o.refine_tol > 0), "refinement options invalid");
+    MBT_REQUIRE(o.rhs_chunk >= 0, "rhs_chunk must be >= 0");
+}
+
+static double inner_tol(const mbt_solve_opts& o) {
+    if (o.inner_tol > 0) return o.inner_tol;
+    return o.prec == MBT_FP32 ? 1e-4 : 1e-2;
+}
+
+// ------------------------------------------------------------------ operator cache
+static std::string op_key(const Geom& g, double s) {
+    std::ostringstream os;
+    os.precision(17);
+    os << g.nx << ',' << g.ny << ',' << g.M << ',' << g.dx << ',' << g.dy << ',' << g.L << ',' << g.a << ',' << s;
+    return os.str();
+}
+
+static void build_pa(OpData& op, Worker& wk) {
+    const Geom& g = op.g;
+    const int64_t MM = (int64_t)g.M * g.M;
+    DBuf G, Pb, info;
+    G.alloc(sizeof(double2) * g.noff() * MM);
+    Pb.alloc(sizeof(double2) * g.P * MM);
+    info.alloc(sizeof(int) * g.P);
+    gram_blocks(g, op.T.as<double2>(), G.as<double2>(), wk.stream);
+    window_sum(g, G.as<double2>(), Pb.as<double2>(), wk.stream);
+    op.PaInv.alloc(sizeof(double2) * g.P * MM);
+    batched_inverse(Pb.as<double2>(), op.PaInv.as<double2>(), g.M, g.P, true, info.as<int>(), wk.stream);
+    std::vector<int> hi(g.P);
+    MBT_HIP(hipMemcpyAsync(hi.data(), info.p, sizeof(int) * g.P, hipMemcpyDeviceToHost, wk.stream));
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    for (int v : hi) MBT_REQUIRE(v == 0, "normal-equation preconditioner block is not positive definite");
+    op.has_pa = true;
+}
+
+static void build_32(OpData& op, Worker& wk) {
+    const Geom& g = op.g;
+    const int64_t MM = (int64_t)g.M * g.M;
+    op.Chat32.alloc(sizeof(float2) * g.bins() * MM);
+    convert<double2, float2>(op.Chat.as<double2>(), op.Chat32.as<float2>(), g.bins() * MM, wk.stream);
+    op.tw32.alloc(sizeof(float2) * (g.Px + g.Py));
+    convert<double2, float2>(op.tw.as<double2>(), op.tw32.as<float2>(), g.Px + g.Py, wk.stream);
+    op.PkInv32.alloc(sizeof(float2) * MM);
+    convert<double2, float2>(op.PkInv.as<double2>(), op.PkInv32.as<float2>(), MM, wk.stream);
+    if (op.has_pa) {
+        op.PaInv32.alloc(sizeof(float2) * g.P * MM);
+        convert<double2, float2>(op.PaInv.as<double2>(), op.PaInv32.as<float2>(), g.P * MM, wk.stream);
+    }
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    op.has32 = true;
+}
+
+static std::shared_ptr<OpData> build_op(const Geom& g, double s, Worker& wk) {
+    auto op = std::make_shared<OpData>();
+    op->g = g;
+    op->s = s;
+    op->k = 2.0 * M_PI * s;
+    const int64_t MM = (int64_t)g.M * g.M;
+    op->T.alloc(sizeof(double2) * g.noff() * MM);
+    fill_blocks(g, op->k, op->T.as<double2>(), wk.stream);
+    op->Chat.alloc(sizeof(double2) * g.bins() * MM);
+    {
+        DBuf scratch;
+        scratch.alloc(sizeof(double2) * ((int64_t)g.noy * g.Px * MM + g.Px + g.Py));
+        embed_blocks_fft(g, op->T.as<double2>(), op->Chat.as<double2>(), 1.0 / (double)g.bins(), scratch.as<double2>(),
+                         wk.stream);
+        MBT_HIP(hipStreamSynchronize(wk.stream));
+    }
+    op->tw.alloc(sizeof(double2) * (g.Px + g.Py));
+    make_twiddles(g.Px, op->tw.as<double2>(), wk.stream);
+    make_twiddles(g.Py, op->tw.as<double2>() + g.Px, wk.stream);
+    // P_K: inverse of the self block (offset 0)
+    DBuf info;
+    info.alloc(sizeof(int));
+    op->PkInv.alloc(sizeof(double2) * MM);
+    const int64_t center = (int64_t)(g.ny - 1) * g.nox + (g.nx - 1);
+    batched_inverse(op->T.as<double2>() + center * MM, op->PkInv.as<double2>(), g.M, 1, false, info.as<int>(), wk.stream);
+    int hinfo = 0;
+    MBT_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, wk.stream));
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    MBT_REQUIRE(hinfo == 0, "element self block is singular");
+    return op;
+}
+
+std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_pa, bool need32, Worker& wk) {
+    MBT_REQUIRE(s > 0 && std::isfinite(s), "freq_ratio must be positive");
+    const std::string key = op_key(g, s);
+    std::shared_ptr<OpData> op;
+    {
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        auto it = ctx->cache.find(key);
+        if (it != ctx->cache.end()) {
+            op = it->second;
+            ctx->lru.remove(key);
+            ctx->lru.push_front(key);
+        }
+    }
+    if (!op) {
+        op = build_op(g, s, wk);
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        auto it = ctx->cache.find(key);
+        if (it != ctx->cache.end()) {
+            op = it->second;   // another worker built it meanwhile
+        } else {
+            ctx->cache[key] = op;
+            ctx->lru.push_front(key);
+            ctx->cache_bytes += op->bytes();
+        }
+    }
+    // extend under the cache lock so concurrent workers do not race on the same entry
+    if ((need_pa && !op->has_pa) || (need32 && (!op->has32 || (need_pa && !op->PaInv32.p)))) {
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        const size_t before = op->bytes();
+        if (need_pa && !op->has_pa) build_pa(*op, wk);
+        if (need32 && (!op->has32 || (op->has_pa && !op->PaInv32.p))) build_32(*op, wk);
+        ctx->cache_bytes += op->bytes() - before;
+    }
+    // evict least recently used entries beyond the limit (entries in use stay alive through shared_ptr)
+    {
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        while (ctx->cache_bytes > ctx->cache_limit && ctx->lru.size() > 1) {
+            const std::string victim = ctx->lru.back();
+            ctx->lru.pop_back();
+            auto it = ctx->cache.find(victim);
+            if (it != ctx->cache.end()) {
+                ctx->cache_bytes -= it->second->bytes();
+                ctx->cache.erase(it);
+            }
+        }
+    }
+    return op;
+}
+
+// ------------------------------------------------------------------ operator application
+template <typename T> struct OpV {
+    const Geom* g;
+    const cplx<T>* Chat;
+    const cplx<T>* pinv;
+    int64_t pstride;
+    const cplx<T>* twx;
+    const cplx<T>* twy;
+    cplx<T>* Xh;
+    cplx<T>* Yh;
+    cplx<T>* tmp;
+    int R;
+    int pc;
+    hipStream_t s;
+};
+
+template <typename T> static OpV<T> make_view(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s);
+
+template <> OpV<double> make_view<double>(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s) {
+    OpV<double> v;
+    v.g = &op.g;
+    v.Chat = op.Chat.as<double2>();
+    v.pinv = pc == MBT_PC_NORMAL_EQ ? op.PaInv.as<double2>() : op.PkInv.as<double2>();
+    v.pstride = pc == MBT_PC_NORMAL_EQ ? (int64_t)op.g.M * op.g.M : 0;
+    v.twx = op.tw.as<double2>();
+    v.twy = op.tw.as<double2>() + op.g.Px;
+    v.Xh = (double2*)Xh;
+    v.Yh = (double2*)Yh;
+    v.tmp = (double2*)tmp;
+    v.R = R;
+    v.pc = pc;
+    v.s = s;
+    return v;
+}
+
+template <> OpV<float> make_view<float>(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s) {
+    OpV<float> v;
+    v.g = &op.g;
+    v.Chat = op.Chat32.as<float2>();
+    v.pinv = pc == MBT_PC_NORMAL_EQ ? op.PaInv32.as<float2>() : op.PkInv32.as<float2>();
+    v.pstride = pc == MBT_PC_NORMAL_EQ ? (int64_t)op.g.M * op.g.M : 0;
+    v.twx = op.tw32.as<float2>();
+    v.twy = op.tw32.as<float2>() + op.g.Px;
+    v.Xh = (float2*)Xh;
+    v.Yh = (float2*)Yh;
+    v.tmp = (float2*)tmp;
+    v.R = R;
+    v.pc = pc;
+    v.s = s;
+    return v;
+}
+
+// y = Z x (opz 0) or Z^H x (opz 1) by FFT over the lattice, per-bin products, inverse FFT and crop
+template <typename T> static void zmul(const OpV<T>& o, int opz, const cplx<T>* x, cplx<T>* y) {
+    const Geom& g = *o.g;
+    const int64_t B = (int64_t)g.M * o.R;
+    fft_fwd_pad<T>(g, x, o.Xh, B, o.twx, o.twy, o.s);
+    cgemm_batched<T>(o.Chat, (int64_t)g.M * g.M, o.Xh, o.Yh, g.M, o.R, g.bins(), opz, o.s);
+    fft_inv_crop<T>(g, o.Yh, y, B, o.twx, o.twy, o.s);
+}
+
+template <typename T> static void pinv(const OpV<T>& o, const cplx<T>* x, cplx<T>* y) {
+    cgemm_batched<T>(o.pinv, o.pstride, x, y, o.g->M, o.R, o.g->P, 0, o.s);
+}
+
+// preconditioned operator: P_K^{-1} Z  or  P^{-1} Z^H Z
+template <typename T> static void apply_A(const OpV<T>& o, const cplx<T>* x, cplx<T>* y) {
+    zmul<T>(o, 0, x, o.tmp);
+    if (o.pc == MBT_PC_NORMAL_EQ) zmul<T>(o, 1, o.tmp, o.tmp);
+    pinv<T>(o, o.tmp, y);
+}
+
+// preconditioned right-hand side: P_K^{-1} v  or  P^{-1} Z^H v
+template <typename T> static void apply_rhs(const OpV<T>& o, const cplx<T>* v, cplx<T>* b) {
+    if (o.pc == MBT_PC_NORMAL_EQ) {
+        zmul<T>(o, 1, v, o.tmp);
+        pinv<T>(o, o.tmp, b);
+    } else {
+        pinv<T>(o, v, b);
+    }
+}
+
+// ------------------------------------------------------------------ solve drivers
+size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o) {
+    const size_t NR = (size_t)g.N * R;
+    const size_t tb = o.prec == MBT_FP64 ? 16 : 8;
+    size_t b = 0;
+    b += (size_t)(o.restart + 1) * NR * tb;            // Krylov basis
+    b += 2 * (size_t)g.bins() * g.M * R * 16;          // spectral buffers (FP64-sized, shared)
+    b += NR * 16;                                      // operator temp
+    b += NR * tb;                                      // preconditioned rhs
+    b += 2 * NR * 16;                                  // V, X
+    b += NR * 16;                                      // FP64 residual
+    if (o.prec != MBT_FP64) b += NR * 16 + NR * 8;     // d, r32
+    b += gmres_state_bytes(g.N, R, o.restart);
+    b += (size_t)R * 64 + ((size_t)g.N / 256 + 2) * R * 8 + (size_t)g.P * R * 16 + (1 << 20);
+    return b;
+}
+
+int choose_chunk(mbt_ctx* ctx, const Geom& g, int R, const mbt_solve_opts& o) {
+    if (o.rhs_chunk > 0) return std::min(R, o.rhs_chunk);
+    int c = R;
+    while (c > 1 && solve_bytes(g, c, o) > ctx->budget) c = (c + 1) / 2;
+    if (solve_bytes(g, c, o) > ctx->budget) throw Error(-2, "one right-hand side does not fit the device-memory budget");
+    return c;
+}
+
+static void norms_host(const double2* X, int64_t N, int R, DevArena& arena, std::vector<double>& out, hipStream_t s) {
+    const size_t mark = arena.off;
+    const int nchunk = (int)((N + 255) / 256);
+    double* part = arena.get<double>((size_t)nchunk * R);
+    double* dn = arena.get<double>(R);
+    column_norms(X, N, R, part, dn, s);
+    out.resize(R);
+    MBT_HIP(hipMemcpyAsync(out.data(), dn, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipStreamSynchronize(s));
+    arena.off = mark;
+}
+
+SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, int R, double2* X, Worker& wk,
+                   DevArena& arena) {
+    const Geom& g = op.g;
+    const int64_t NR = g.N * R;
+    const int m = o.restart;
+    hipStream_t s = wk.stream;
+    SolveOut out;
+    out.iters.assign(R, 0);
+    void* Xh = arena.get<double2>((size_t)g.bins() * g.M * R);
+    void* Yh = arena.get<double2>((size_t)g.bins() * g.M * R);
+    double2* tmp = arena.get<double2>(NR);
+    GmresParams prm;
+    prm.restart = m;
+    prm.max_cycles = o.max_cycles;
+    prm.matvecs_per_apply = o.pc == MBT_PC_NORMAL_EQ ? 2 : 1;
+    prm.host_count = wk.host_count;
+    std::vector<double> vn;
+    norms_host(V, g.N, R, arena, vn, s);
+
+    if (o.prec == MBT_FP64) {
+        double2* basis = arena.get<double2>((size_t)(m + 1) * NR);
+        double2* b = arena.get<double2>(NR);
+        OpV<double> ov = make_view<double>(op, o.pc, Xh, Yh, tmp, R, s);
+        apply_rhs<double>(ov, V, b);
+        out.matvecs += o.pc == MBT_PC_NORMAL_EQ ? 1 : 0;
+        prm.tol = o.tol;
+        std::function<void(const double2*, double2*)> f = [&](const double2* x, double2* y) { apply_A<double>(ov, x, y); };
+        GmresResult gr = gmres_batched<double2>(f, b, X, basis, g.N, R, prm, arena, s);
+        out.iters = gr.iters;
+        out.cycles = gr.cycles;
+        out.matvecs += gr.matvecs;
+        out.outer = 1;
+        for (int r = 0; r < R; ++r) {
+            out.nconv += gr.conv[r] ? 1 : 0;
+            out.nflag += gr.flag[r] ? 1 : 0;
+        }
+    } else {
+        float2* basis = arena.get<float2>((size_t)(m + 1) * NR);
+        float2* b32 = arena.get<float2>(NR);
+        float2* r32 = arena.get<float2>(NR);
+        double2* r64 = arena.get<double2>(NR);
+        double2* d = arena.get<double2>(NR);
+        double* mask = arena.get<double>(R);
+        OpV<double> ov = make_view<double>(op, o.pc, Xh, Yh, tmp, R, s);
+        OpV<float> ov32 = make_view<float>(op, o.pc, Xh, Yh, tmp, R, s);
+        std::function<void(const float2*, float2*)> f = [&](const float2* x, float2* y) { apply_A<float>(ov32, x, y); };
+        prm.tol = inner_tol(o);
+        zero_d(X, NR, s);
+        std::vector<int> done(R, 0), flagged(R, 0);
+        for (int outer = 0; outer < o.refine_max; ++outer) {
+            if (outer == 0) {
+                convert<double2, double2>(V, r64, NR, s);
+            } else {
+                zmul<double>(ov, 0, X, tmp);
+                out.matvecs += 1;
+                sub_d(V, tmp, r64, NR, s);
+            }
+            std::vector<double> rn;
+            norms_host(r64, g.N, R, arena, rn, s);
+            std::vector<double> hmask(R);
+            int left = 0;
+            for (int r = 0; r < R; ++r) {
+                const double rel = vn[r] > 0 ? rn[r] / vn[r] : 0.0;
+                done[r] = (rel <= o.refine_tol) || flagged[r];
+                hmask[r] = done[r] ? 0.0 : 1.0;
+                left += done[r] ? 0 : 1;
+            }
+            if (left == 0) break;
+            MBT_HIP(hipMemcpyAsync(mask, hmask.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+            scale_columns_d(r64, mask, g.N, R, s);
+            convert<double2, float2>(r64, r32, NR, s);
+            apply_rhs<float>(ov32, r32, b32);
+            out.matvecs += o.pc == MBT_PC_NORMAL_EQ ? 1 : 0;
+            GmresResult gr = gmres_batched<float2>(f, b32, d, basis, g.N, R, prm, arena, s);
+            add_to_f64<double2>(X, d, NR, s);
+            out.outer = outer + 1;
+            out.cycles += gr.cycles;
+            out.matvecs += gr.matvecs;
+            for (int r = 0; r < R; ++r) {
+                out.iters[r] += gr.iters[r];
+                if (gr.flag[r]) flagged[r] = 1;
+            }
+        }
+        // final verdict on the FP64 residual
+        zmul<double>(ov, 0, X, tmp);
+        out.matvecs += 1;
+        sub_d(V, tmp, r64, NR, s);
+        std::vector<double> rn;
+        norms_host(r64, g.N, R, arena, rn, s);
+        for (int r = 0; r < R; ++r) {
+            const double rel = vn[r] > 0 ? rn[r] / vn[r] : 0.0;
+            out.nconv += (rel <= o.refine_tol && !flagged[r]) ? 1 : 0;
+            out.nflag += flagged[r];
+            out.relres_max = std::max(out.relres_max, rel);
+        }
+        return out;
+    }
+    // FP64 path: true residual ||V - Z X|| / ||V||
+    {
+        OpV<double> ov = make_view<double>(op, o.pc, Xh, Yh, tmp, R, s);
+        double2* r64 = arena.get<double2>(NR);
+        zmul<double>(ov, 0, X, tmp);
+        out.matvecs += 1;
+        sub_d(V, tmp, r64, NR, s);
+        std::vector<double> rn;
+        norms_host(r64, g.N, R, arena, rn, s);
+        for (int r = 0; r < R; ++r) out.relres_max = std::max(out.relres_max, vn[r] > 0 ? rn[r] / vn[r] : 0.0);
+    }
+    return out;
+}
+
+SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t* ports, int nports,
+                    const mbt_solve_opts& o, double2* Ydev, Worker& wk, mbt_stats* st) {
+    const Geom& g = arr->g;
+    const double t0 = now_s();
+    auto op = get_op(ctx, g, s, o.pc == MBT_PC_NORMAL_EQ, o.prec != MBT_FP64, wk);
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    const double t1 = now_s();
+    const int chunk = choose_chunk(ctx, g, nports, o);
+    const size_t need = solve_bytes(g, chunk, o) + sizeof(int32_t) * nports + 4096;
+    wk.ensure(need);
+    DevArena arena;
+    arena.base = wk.ws.as<char>();
+    arena.cap = wk.ws.bytes;
+    int32_t* dports = arena.get<int32_t>(nports);
+    MBT_HIP(hipMemcpyAsync(dports, ports, sizeof(int32_t) * nports, hipMemcpyHostToDevice, wk.stream));
+    SolveOut total;
+    total.iters.assign(nports, 0);
+    const size_t base_mark = arena.off;
+    for (int c0 = 0; c0 < nports; c0 += chunk) {
+        const int R = std::min(chunk, nports - c0);
+        arena.off = base_mark;
+        double2* V = arena.get<double2>((size_t)g.N * R);
+        double2* X = arena.get<double2>((size_t)g.N * R);
+        scatter_ports(g, dports + c0, R, V, wk.stream);
+        SolveOut so = solve_rhs(*op, o, V, R, X, wk, arena);
+        gather_ports(g, X, R, Ydev + (int64_t)c0 * g.P, wk.stream);
+        for (int r = 0; r < R; ++r) total.iters[c0 + r] = so.iters[r];
+        total.cycles = std::max(total.cycles, so.cycles);
+        total.outer = std::max(total.outer, so.outer);
+        total.nconv += so.nconv;
+        total.nflag += so.nflag;
+        total.matvecs += so.matvecs;
+        total.relres_max = std::max(total.relres_max, so.relres_max);
+    }
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    const double t2 = now_s();
+    if (st) {
+        st->nrhs = nports;
+        st->nconverged = total.nconv;
+        st->cycles = total.cycles;
+        st->outer_steps = total.outer;
+        st->iters_min = nports ? *std::min_element(total.iters.begin(), total.iters.end()) : 0;
+        st->iters_max = nports ? *std::max_element(total.iters.begin(), total.iters.end()) : 0;
+        st->iters_total = 0;
+        for (int v : total.iters) st->iters_total += v;
+        st->matvecs = total.matvecs;
+        st->true_relres_max = total.relres_max;
+        st->t_setup = t1 - t0;
+        st->t_solve = t2 - t1;
+        st->t_extract = 0;
+    }
+    return total;
+}
+
+}  // namespace mbt
+
+// ================================================================== C ABI
+namespace {
+
+mbt_status finish_status(const SolveOut& so) {
+    if (so.nflag > 0) return set_err(MBT_EBREAKDOWN, "non-finite value in the Krylov recurrence for some right-hand sides");
+    if (so.nconv < (int)so.iters.size()) return set_err(MBT_ENOCONV, "some right-hand sides did not converge");
+    return MBT_OK;
+}
+
+struct DevScope {
+    explicit DevScope(int dev) { MBT_HIP(hipSetDevice(dev)); }
+};
+
+std::vector<int32_t> port_list(const mbt_array* arr, const int32_t* ports, int32_t nports) {
+    std::vector<int32_t> pl;
+    if (ports == nullptr) {
+        MBT_REQUIRE(nports == -1 || nports == arr->g.P, "ports == NULL requires nports == -1");
+        pl.resize(arr->g.P);
+        for (int i = 0; i < arr->g.P; ++i) pl[i] = i;
+    } else {
+        MBT_REQUIRE(nports >= 1, "nports must be >= 1");
+        pl.assign(ports, ports + nports);
+        for (int32_t p : pl) MBT_REQUIRE(p >= 0 && p < arr->g.P, "port index out of range");
+    }
+    return pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mbt_default_opts(mbt_solve_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->prec = MBT_FP64;
+    o->pc = MBT_PC_ELEMENT_BLOCK;
+    o->restart = 50;
+    o->tol = 1e-10;
+    o->max_cycles = 400;
+    o->refine_max = 3;
+    o->refine_tol = 1e-9;
+    o->inner_tol = 0;
+    o->rhs_chunk = 0;
+    o->flags = 0;
+}
+
+const char* mbt_last_error(void) { return g_err.c_str(); }
+
+const char* mbt_version(void) { return "mbt 0.1 (gfx950; FP64 + FP32 MFMA paths)"; }
+
+mbt_status mbt_ctx_create(int32_t dev, size_t budget, mbt_ctx** out) {
+    API_BEGIN
+    MBT_REQUIRE(out != nullptr, "out is NULL");
+    int n = 0;
+    MBT_HIP(hipGetDeviceCount(&n));
+    MBT_REQUIRE(dev >= 0 && dev < n, "no such HIP device");
+    MBT_HIP(hipSetDevice(dev));
+    std::unique_ptr<mbt_ctx> c(new mbt_ctx());
+    c->device = dev;
+    size_t freeb = 0, totalb = 0;
+    MBT_HIP(hipMemGetInfo(&freeb, &totalb));
+    c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
+    c->cache_limit = c->budget / 8;
+    c->main.reset(new Worker(dev));
+    *out = c.release();
+    API_END
+}
+
+void mbt_ctx_destroy(mbt_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    ctx->cache.clear();
+    ctx->main.reset();
+    delete ctx;
+}
+
+mbt_status mbt_array_create_dipole(mbt_ctx* ctx, const mbt_dipole* e, const mbt_lattice* l, mbt_array** out) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && e && l && out, "NULL argument");
+    std::unique_ptr<mbt_array> a(new mbt_array());
+    a->g = make_geom(*e, *l);
+    a->elem = *e;
+    a->lat = *l;
+    *out = a.release();
+    API_END
+}
+
+void mbt_array_destroy(mbt_array* a) { delete a; }
+
+mbt_status mbt_array_info(const mbt_array* a, int64_t* N, int32_t* P, int32_t* gx, int32_t* gy) {
+    API_BEGIN
+    MBT_REQUIRE(a != nullptr, "array is NULL");
+    if (N) *N = a->g.N;
+    if (P) *P = a->g.P;
+    if (gx) *gx = a->g.Px;
+    if (gy) *gy = a->g.Py;
+    API_END
+}
+
+size_t mbt_footprint(const mbt_array* a, int32_t nrhs, const mbt_solve_opts* o) {
+    if (!a || !o || nrhs < 1) return 0;
+    try {
+        const Geom& g = a->g;
+        const size_t MM = (size_t)g.M * g.M;
+        size_t opb = (size_t)g.noff() * MM * 16 + (size_t)g.bins() * MM * 16 + (size_t)g.P * MM * 16 * 2;
+        if (o->prec != MBT_FP64) opb += (size_t)g.bins() * MM * 8 + (size_t)g.P * MM * 8;
+        return solve_bytes(g, nrhs, *o) + opb;
+    } catch (...) {
+        return 0;
+    }
+}
+
+mbt_status mbt_port_admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t* ports, int32_t nports,
+                               const mbt_solve_opts* opts, double* Y, int32_t* iters, mbt_stats* st) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && opts && Y, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    validate_opts(*opts);
+    MBT_REQUIRE(s > 0 && std::isfinite(s), "freq_ratio must be positive");
+    std::vector<int32_t> pl = port_list(arr, ports, nports);
+    const int np = (int)pl.size();
+    DBuf Yd;
+    Yd.alloc(sizeof(double2) * arr->g.P * np);
+    SolveOut so = admittance(ctx, arr, s, pl.data(), np, *opts, Yd.as<double2>(), *ctx->main, st);
+    MBT_HIP(hipMemcpy(Y, Yd.p, sizeof(double2) * arr->g.P * np, hipMemcpyDeviceToHost));
+    if (iters) std::copy(so.iters.begin(), so.iters.end(), iters);
+    return finish_status(so);
+    API_END
+}
+
+mbt_status mbt_port_admittance_dev(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t* ports, int32_t nports,
+                                   const mbt_solve_opts* opts, void* Ydev, void* stream, int32_t* iters, mbt_stats* st) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && opts && Ydev, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    validate_opts(*opts);
+    std::vector<int32_t> pl = port_list(arr, ports, nports);
+    hipStream_t user = (hipStream_t)stream;
+    if (user) {
+        // order the solve after prior work on the caller's stream
+        hipEvent_t ev;
+        MBT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        MBT_HIP(hipEventRecord(ev, user));
+        MBT_HIP(hipStreamWaitEvent(ctx->main->stream, ev, 0));
+        MBT_HIP(hipEventDestroy(ev));
+    }
+    SolveOut so = admittance(ctx, arr, s, pl.data(), (int)pl.size(), *opts, (double2*)Ydev, *ctx->main, st);
+    if (iters) std::copy(so.iters.begin(), so.iters.end(), iters);
+    return finish_status(so);
+    API_END
+}
+
+static mbt_status solve_impl(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_solve_opts* opts,
+                             const double* theta, const double* phi, int32_t nscan, double z0, double* Zp, double* Za,
+                             double* Gamma, double* Gamma_wave, mbt_stats* st) {
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    validate_opts(*opts);
+    MBT_REQUIRE(s > 0 && std::isfinite(s), "freq_ratio must be positive");
+    MBT_REQUIRE(nscan >= 0 && (nscan == 0 || (theta && phi && Za && Gamma)), "scan arrays missing");
+    MBT_REQUIRE(z0 > 0, "z0 must be positive");
+    const Geom& g = arr->g;
+    const int P = g.P;
+    std::vector<int32_t> pl = port_list(arr, nullptr, -1);
+    DBuf Yd, Zd, Sd, Wd, aux;
+    Yd.alloc(sizeof(double2) * P * P);
+    SolveOut so = admittance(ctx, arr, s, pl.data(), P, *opts, Yd.as<double2>(), *ctx->main, st);
+    const double t0 = now_s();
+    hipStream_t str = ctx->main->stream;
+    Zd.alloc(sizeof(double2) * P * P);
+    aux.alloc(sizeof(double2) * P + sizeof(int) * (P + 8) + sizeof(double) * 2 * std::max(nscan, 1) +
+              sizeof(double2) * 3 * std::max(nscan, 1) + 1024);
+    char* ab = aux.as<char>();
+    double2* colbuf = (double2*)ab;
+    int* piv = (int*)(ab + sizeof(double2) * P);
+    int* flag = piv + P;
+    double* dth = (double*)(((uintptr_t)(flag + 8) + 255) & ~(uintptr_t)255);
+    double* dph = dth + std::max(nscan, 1);
+    double2* dout = (double2*)(dph + std::max(nscan, 1));
+    gj_inverse(Yd.as<double2>(), Zd.as<double2>(), P, colbuf, piv, flag, str);
+    if (nscan > 0) {
+        Sd.alloc(sizeof(double2) * P * P);
+        Wd.alloc(sizeof(double2) * P * P);
+        if (Gamma_wave) s_matrix(Zd.as<double2>(), Sd.as<double2>(), Wd.as<double2>(), P, z0, colbuf, piv, flag, str);
+        MBT_HIP(hipMemcpyAsync(dth, theta, sizeof(double) * nscan, hipMemcpyHostToDevice, str));
+        MBT_HIP(hipMemcpyAsync(dph, phi, sizeof(double) * nscan, hipMemcpyHostToDevice, str));
+        const int c = (g.ny / 2) * g.nx + g.nx / 2;
+        scans(g, 2.0 * M_PI * s, Zd.as<double2>(), Gamma_wave ? Sd.as<double2>() : nullptr, c, dth, dph, nscan, z0, dout,
+              dout + nscan, Gamma_wave ? dout + 2 * nscan : nullptr, str);
+        MBT_HIP(hipMemcpyAsync(Za, dout, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
+        MBT_HIP(hipMemcpyAsync(Gamma, dout + nscan, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
+        if (Gamma_wave)
+            MBT_HIP(hipMemcpyAsync(Gamma_wave, dout + 2 * nscan, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
+    }
+    if (Zp) MBT_HIP(hipMemcpyAsync(Zp, Zd.p, sizeof(double2) * P * P, hipMemcpyDeviceToHost, str));
+    MBT_HIP(hipStreamSynchronize(str));
+    if (st) st->t_extract = now_s() - t0;
+    return finish_status(so);
+}
+
+mbt_status mbt_port_impedance(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_solve_opts* opts, double* Zp,
+                              mbt_stats* st) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && opts && Zp, "NULL argument");
+    return solve_impl(ctx, arr, s, opts, nullptr, nullptr, 0, 50.0, Zp, nullptr, nullptr, nullptr, st);
+    API_END
+}
+
+mbt_status mbt_solve(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_solve_opts* opts, const double* theta,
+                     const double* phi, int32_t nscan, double z0, double* Zp, double* Za, double* Gamma,
+                     double* Gamma_wave, mbt_stats* st) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && opts, "NULL argument");
+    return solve_impl(ctx, arr, s, opts, theta, phi, nscan, z0, Zp, Za, Gamma, Gamma_wave, st);
+    API_END
+}
+
+mbt_status mbt_active(mbt_ctx* ctx, const mbt_array* arr, double s, const double* Zp, int32_t center,
+                      const double* theta, const double* phi, int32_t nscan, double z0, double* Za, double* Gamma,
+                      double* Gamma_wave) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && Zp && theta && phi && Za && Gamma, "NULL argument");
+    MBT_REQUIRE(nscan >= 1, "nscan must be >= 1");
+    MBT_REQUIRE(s > 0 && z0 > 0, "freq_ratio and z0 must be positive");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    const Geom& g = arr->g;
+    const int P = g.P;
+    const int c = center < 0 ? (g.ny / 2) * g.nx + g.nx / 2 : center;
+    MBT_REQUIRE(c < P, "center out of range");
+    hipStream_t str = ctx->main->stream;
+    DBuf Zd, Sd, Wd, aux;
+    Zd.alloc(sizeof(double2) * P * P);
+    aux.alloc(sizeof(double2) * P + sizeof(int) * (P + 8) + sizeof(double) * 2 * nscan + sizeof(double2) * 3 * nscan + 1024);
+    char* ab = aux.as<char>();
+    double2* colbuf = (double2*)ab;
+    int* piv = (int*)(ab + sizeof(double2) * P);
+    int* flag = piv + P;
+    double* dth = (double*)(((uintptr_t)(flag + 8) + 255) & ~(uintptr_t)255);
+    double* dph = dth + nscan;
+    double2* dout = (double2*)(dph + nscan);
+    MBT_HIP(hipMemcpyAsync(Zd.p, Zp, sizeof(double2) * P * P, hipMemcpyHostToDevice, str));
+    if (Gamma_wave) {
+        Sd.alloc(sizeof(double2) * P * P);
+        Wd.alloc(sizeof(double2) * P * P);
+        s_matrix(Zd.as<double2>(), Sd.as<double2>(), Wd.as<double2>(), P, z0, colbuf, piv, flag, str);
+    }
+    MBT_HIP(hipMemcpyAsync(dth, theta, sizeof(double) * nscan, hipMemcpyHostToDevice, str));
+    MBT_HIP(hipMemcpyAsync(dph, phi, sizeof(double) * nscan, hipMemcpyHostToDevice, str));
+    scans(g, 2.0 * M_PI * s, Zd.as<double2>(), Gamma_wave ? Sd.as<double2>() : nullptr, c, dth, dph, nscan, z0, dout,
+          dout + nscan, Gamma_wave ? dout + 2 * nscan : nullptr, str);
+    MBT_HIP(hipMemcpyAsync(Za, dout, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
+    MBT_HIP(hipMemcpyAsync(Gamma, dout + nscan, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
+    if (Gamma_wave) MBT_HIP(hipMemcpyAsync(Gamma_wave, dout + 2 * nscan, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
+    MBT_HIP(hipStreamSynchronize(str));
+    API_END
+}
+
+// ------------------------------------------------------------------ test hooks
+mbt_status mbt_dbg_fill_blocks(mbt_ctx* ctx, const mbt_array* arr, double s, double* T) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && T, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    auto op = get_op(ctx, arr->g, s, false, false, *ctx->main);
+    MBT_HIP(hipMemcpy(T, op->T.p, op->T.bytes, hipMemcpyDeviceToHost));
+    API_END
+}
+
+mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t prec, int32_t opz, const double* x,
+                          int32_t R, double* y) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && x && y && R >= 1, "bad argument");
+    MBT_REQUIRE(opz >= 0 && opz <= 2, "op must be 0, 1 or 2");
+    MBT_REQUIRE(prec == MBT_FP64 || prec == MBT_FP32, "precision not supported");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    const Geom& g = arr->g;
+    Worker& wk = *ctx->main;
+    auto op = get_op(ctx, g, s, false, prec == MBT_FP32, wk);
+    const int64_t NR = g.N * R;
+    DBuf hx, dx, dy, Xh, Yh, tmp, f1, f2;
+    hx.alloc(sizeof(double2) * NR);
+    dx.alloc(sizeof(double2) * NR);
+    dy.alloc(sizeof(double2) * NR);
+    Xh.alloc(sizeof(double2) * g.bins() * g.M * R);
+    Yh.alloc(sizeof(double2) * g.bins() * g.M * R);
+    tmp.alloc(sizeof(double2) * NR);
+    MBT_HIP(hipMemcpyAsync(hx.p, x, sizeof(double2) * NR, hipMemcpyHostToDevice, wk.stream));
+    transpose_nr(hx.as<double2>(), dx.as<double2>(), g.N, R, true, wk.stream);
+    if (prec == MBT_FP64) {
+        OpV<double> ov = make_view<double>(*op, MBT_PC_ELEMENT_BLOCK, Xh.p, Yh.p, tmp.p, R, wk.stream);
+        if (opz == 2) {
+            zmul<double>(ov, 0, dx.as<double2>(), tmp.as<double2>());
+            zmul<double>(ov, 1, tmp.as<double2>(), dy.as<double2>());
+        } else {
+            zmul<double>(ov, opz, dx.as<double2>(), dy.as<double2>());
+        }
+    } else {
+        f1.alloc(sizeof(float2) * NR);
+        f2.alloc(sizeof(float2) * NR);
+        OpV<float> ov = make_view<float>(*op, MBT_PC_ELEMENT_BLOCK, Xh.p, Yh.p, tmp.p, R, wk.stream);
+        convert<double2, float2>(dx.as<double2>(), f1.as<float2>(), NR, wk.stream);
+        if (opz == 2) {
+            zmul<float>(ov, 0, f1.as<float2>(), ov.tmp);
+            zmul<float>(ov, 1, ov.tmp, f2.as<float2>());
+        } else {
+            zmul<float>(ov, opz, f1.as<float2>(), f2.as<float2>());
+        }
+        convert<float2, double2>(f2.as<float2>(), dy.as<double2>(), NR, wk.stream);
+    }
+    transpose_nr(dy.as<double2>(), hx.as<double2>(), g.N, R, false, wk.stream);
+    MBT_HIP(hipMemcpyAsync(y, hx.p, sizeof(double2) * NR, hipMemcpyDeviceToHost, wk.stream));
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    API_END
+}
+
+mbt_status mbt_dbg_precond_apply(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t pc, const double* x, int32_t R,
+                                 double* y) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && x && y && R >= 1, "bad argument");
+    MBT_REQUIRE(pc == MBT_PC_NORMAL_EQ || pc == MBT_PC_ELEMENT_BLOCK, "unknown preconditioner");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    const Geom& g = arr->g;
+    Worker& wk = *ctx->main;
+    auto op = get_op(ctx, g, s, pc == MBT_PC_NORMAL_EQ, false, wk);
+    const int64_t NR = g.N * R;
+    DBuf hx, dx, dy;
+    hx.alloc(sizeof(double2) * NR);
+    dx.alloc(sizeof(double2) * NR);
+    dy.alloc(sizeof(double2) * NR);
+    MBT_HIP(hipMemcpyAsync(hx.p, x, sizeof(double2) * NR, hipMemcpyHostToDevice, wk.stream));
+    transpose_nr(hx.as<double2>(), dx.as<double2>(), g.N, R, true, wk.stream);
+    OpV<double> ov = make_view<double>(*op, pc, nullptr, nullptr, nullptr, R, wk.stream);
+    pinv<double>(ov, dx.as<double2>(), dy.as<double2>());
+    transpose_nr(dy.as<double2>(), hx.as<double2>(), g.N, R, false, wk.stream);
+    MBT_HIP(hipMemcpyAsync(y, hx.p, sizeof(double2) * NR, hipMemcpyDeviceToHost, wk.stream));
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    API_END
+}
+
+mbt_status mbt_dbg_precond_blocks(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t pc, double* Pb) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && Pb, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    const Geom& g = arr->g;
+    Worker& wk = *ctx->main;
+    auto op = get_op(ctx, g, s, false, false, wk);
+    const int64_t MM = (int64_t)g.M * g.M;
+    if (pc == MBT_PC_ELEMENT_BLOCK) {
+        const int64_t center = (int64_t)(g.ny - 1) * g.nox + (g.nx - 1);
+        MBT_HIP(hipMemcpy(Pb, op->T.as<double2>() + center * MM, sizeof(double2) * MM, hipMemcpyDeviceToHost));
+    } else {
+        DBuf G, P;
+        G.alloc(sizeof(double2) * g.noff() * MM);
+        P.alloc(sizeof(double2) * g.P * MM);
+        gram_blocks(g, op->T.as<double2>(), G.as<double2>(), wk.stream);
+        window_sum(g, G.as<double2>(), P.as<double2>(), wk.stream);
+        MBT_HIP(hipMemcpyAsync(Pb, P.p, sizeof(double2) * g.P * MM, hipMemcpyDeviceToHost, wk.stream));
+        MBT_HIP(hipStreamSynchronize(wk.stream));
+    }
+    API_END
+}
+
+mbt_status mbt_dbg_solve(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_solve_opts* opts, const double* V,
+                         int32_t R, double* I, int32_t* iters, mbt_stats* st) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && opts && V && I && R >= 1, "bad argument");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    validate_opts(*opts);
+    const Geom& g = arr->g;
+    Worker& wk = *ctx->main;
+    const double t0 = now_s();
+    auto op = get_op(ctx, g, s, opts->pc == MBT_PC_NORMAL_EQ, opts->prec != MBT_FP64, wk);
+    const int64_t NR = g.N * R;
+    wk.ensure(solve_bytes(g, R, *opts) + 3 * sizeof(double2) * NR);
+    DevArena arena;
+    arena.base = wk.ws.as<char>();
+    arena.cap = wk.ws.bytes;
+    double2* hx = arena.get<double2>(NR);
+    double2* dV = arena.get<double2>(NR);
+    double2* dX = arena.get<double2>(NR);
+    MBT_HIP(hipMemcpyAsync(hx, V, sizeof(double2) * NR, hipMemcpyHostToDevice, wk.stream));
+    transpose_nr(hx, dV, g.N, R, true, wk.stream);
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    const double t1 = now_s();
+    SolveOut so = solve_rhs(*op, *opts, dV, R, dX, wk, arena);
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    const double t2 = now_s();
+    transpose_nr(dX, hx, g.N, R, false, wk.stream);
+    MBT_HIP(hipMemcpyAsync(I, hx, sizeof(double2) * NR, hipMemcpyDeviceToHost, wk.stream));
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    if (iters) std::copy(so.iters.begin(), so.iters.end(), iters);
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->nrhs = R;
+        st->nconverged = so.nconv;
+        st->cycles = so.cycles;
+        st->outer_steps = so.outer;
+        st->iters_min = *std::min_element(so.iters.begin(), so.iters.end());
+        st->iters_max = *std::max_element(so.iters.begin(), so.iters.end());
+        for (int v : so.iters) st->iters_total += v;
+        st->matvecs = so.matvecs;
+        st->true_relres_max = so.relres_max;
+        st->t_setup = t1 - t0;
+        st->t_solve = t2 - t1;
+    }
+    return finish_status(so);
+    API_END
+}
+
+mbt_status mbt_dbg_inverse(mbt_ctx* ctx, const double* A, int32_t n, double* Ainv) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && A && Ainv && n >= 1, "bad argument");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    hipStream_t str = ctx->main->stream;
+    DBuf Ad, Od, aux;
+    Ad.alloc(sizeof(double2) * n * n);
+    Od.alloc(sizeof(double2) * n * n);
+    aux.alloc(sizeof(double2) * n + sizeof(int) * (n + 8));
+    MBT_HIP(hipMemcpyAsync(Ad.p, A, sizeof(double2) * n * n, hipMemcpyHostToDevice, str));
+    gj_inverse(Ad.as<double2>(), Od.as<double2>(), n, aux.as<double2>(), (int*)(aux.as<double2>() + n),
+               (int*)(aux.as<double2>() + n) + n, str);
+    MBT_HIP(hipMemcpyAsync(Ainv, Od.p, sizeof(double2) * n * n, hipMemcpyDeviceToHost, str));
+    MBT_HIP(hipStreamSynchronize(str));
+    API_END
+}
+
+}  // extern "C"

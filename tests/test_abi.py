@@ -1,0 +1,58 @@
+"""The C-ABI library loads without a GPU, exports every entry point that
+include/mbt.h declares, and rejects bad arguments on the host before any
+device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2608_17844_amd import mbt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mbt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mbt_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mbt.LIB_PATH):
+        pytest.skip("libmbt.so not built")
+    return mbt.lib()
+
+
+def test_header_declares_the_binding_surface():
+    assert set(_declared()) == set(mbt.exported_symbols())
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_default_options_and_version(lib):
+    o = mbt.mbt_default_opts()
+    assert (o.prec, o.pc, o.restart, o.tol, o.max_cycles, o.refine_max) == (0, 1, 50, 1e-10, 400, 3)
+    assert b"gfx950" in lib.mbt_version()
+
+
+def test_null_and_invalid_arguments_rejected_on_host(lib):
+    h = ctypes.c_void_p()
+    d = mbt.mbt_dipole(0.5, 0.005, 15)
+    l = mbt.mbt_lattice(5, 5, 0.5, 0.5)
+    assert lib.mbt_array_create_dipole(None, ctypes.byref(d), ctypes.byref(l), ctypes.byref(h)) == mbt.MBT_EINVAL
+    assert b"NULL" in lib.mbt_last_error()
+    st = lib.mbt_port_admittance(None, None, 1.0, None, -1, None, None, None, None)
+    assert st == mbt.MBT_EINVAL
+    assert lib.mbt_footprint(None, 1, None) == 0
+
+
+def test_struct_layouts_match_header_sizes():
+    assert ctypes.sizeof(mbt.mbt_dipole) == 24
+    assert ctypes.sizeof(mbt.mbt_lattice) == 24
+    assert ctypes.sizeof(mbt.mbt_solve_opts) == 56
+    assert ctypes.sizeof(mbt.mbt_stats) == 72
