@@ -83,8 +83,13 @@ typedef struct {
     double refine_tol;    /* reduced precision: outer stop on ||V - Z I|| / ||V||, default 1e-9 */
     double inner_tol;     /* reduced precision: inner relative tolerance (0 = by precision) */
     int32_t rhs_chunk;    /* RHS per batched solve (0 = all at once, within the budget) */
-    int32_t flags;        /* reserved, 0 */
+    int32_t flags;        /* MBT_FLAG_* bits, default 0 */
 } mbt_solve_opts;
+
+/* mbt_solve_opts.flags: rebuild blocks, spectra and preconditioner for this
+ * call instead of using (and filling) the context's per-(array, frequency)
+ * cache; used to time the complete path. */
+#define MBT_FLAG_NO_CACHE 1
 
 typedef struct {
     int32_t nrhs;             /* RHS solved */
@@ -209,6 +214,31 @@ void mbt_result_free(mbt_result* res);
 double mbt_server_clock(const mbt_server* srv);
 /* Finishes in-flight requests, then stops the loop. */
 void mbt_server_destroy(mbt_server* srv);
+
+/* ---------------------------------------------------------------- kernel timing
+ * Process-wide HIP-event timing of one kernel class, recorded on the stream
+ * each kernel is launched on, with the class's algorithmic bytes and flops per
+ * launch (what the method must move: e.g. for an Arnoldi pass the basis
+ * vectors read plus the work vector read and written; for the forward lattice
+ * FFT the spatial input read plus the spectrum written).  Used to report
+ * achieved bandwidth against the HBM roofline.  Not thread-safe with
+ * concurrent solves; intended for benchmarks. */
+typedef enum {
+    MBT_K_NONE = 0,
+    MBT_K_ARNOLDI_DOTS = 1,         /* h = V^H w */
+    MBT_K_ARNOLDI_UPDATE_DOTS = 2,  /* w -= V h; h2 = V^H w */
+    MBT_K_ARNOLDI_UPDATE_NORM = 3,  /* w -= V h2; ||w|| */
+    MBT_K_FFT_FWD = 4,              /* zero-padded forward lattice FFT */
+    MBT_K_FFT_INV = 5,              /* inverse lattice FFT and crop */
+    MBT_K_BIN_PRODUCT = 6,          /* per-bin block products (MFMA) */
+    MBT_K_PRECOND_APPLY = 7         /* block-diagonal preconditioner apply (MFMA) */
+} mbt_kernel;
+
+/* Starts (and clears) timing of `kernel` (MBT_K_NONE stops timing). */
+mbt_status mbt_prof_start(int32_t kernel);
+/* Totals since mbt_prof_start: summed event time (ms), launches, algorithmic
+ * bytes and flops.  Synchronises the recorded events. */
+mbt_status mbt_prof_read(double* ms_total, int64_t* launches, double* bytes, double* flops);
 
 /* ---------------------------------------------------------------- test hooks
  * Expose single steps of the path for parity tests; same ABI conventions. */

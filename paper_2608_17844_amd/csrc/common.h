@@ -74,6 +74,32 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::mbt::Error(-1, std::string(msg));   \
     } while (0)
 
+// ------------------------------------------------------------------ kernel timing
+// Brackets one launch with HIP events on its stream when its class is the one
+// selected by mbt_prof_start; records the launch's algorithmic bytes/flops.
+enum KernelClass {
+    kKArnoldiDots = 1,
+    kKArnoldiUpdateDots = 2,
+    kKArnoldiUpdateNorm = 3,
+    kKFftFwd = 4,
+    kKFftInv = 5,
+    kKBinProduct = 6,
+    kKPrecondApply = 7
+};
+class ProfScope {
+  public:
+    ProfScope(int kernel, double bytes, double flops, hipStream_t s);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+
+  private:
+    bool on_ = false;
+    hipEvent_t a_{}, b_{};
+    hipStream_t s_;
+    double bytes_, flops_;
+};
+
 // ------------------------------------------------------------------ geometry
 struct Geom {
     int nx = 0, ny = 0, M = 0;     // lattice size, bases per element

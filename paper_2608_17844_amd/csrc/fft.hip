@@ -152,28 +152,40 @@ __device__ __forceinline__ void lds_fft_axis(cplx<T>* tile, const cplx<T>* __res
     }
 }
 
-constexpr int kNT = 256;
+constexpr int kNT = 512;
 
+// Each workgroup owns W adjacent columns: the whole (ny x nx) input of those
+// columns is read once into registers (NOWN values per thread), and the four
+// parity sub-transforms are run from there through one LDS tile.
 template <typename T, int LX, int LY, int W>
 __global__ __launch_bounds__(kNT) void fft_fwd_pad_kernel(const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Xh,
                                                           int nx, int ny, int64_t B, const cplx<T>* __restrict__ twx,
                                                           const cplx<T>* __restrict__ twy) {
     using C = cplx<T>;
     constexpr int PX = 2 * LX, NTILE = LX * LY * W;
+    constexpr int NOWN = (NTILE + kNT - 1) / kNT;
     __shared__ C tile[NTILE];
     const int64_t c0 = (int64_t)blockIdx.x * W;
+    C xin[NOWN];
+#pragma unroll
+    for (int i = 0; i < NOWN; ++i) {
+        const int t = threadIdx.x + i * kNT;
+        const int w = t % W, ix = (t / W) % LX, iy = t / (W * LX);
+        const int64_t c = c0 + w;
+        xin[i] = (t < NTILE && ix < nx && iy < ny && c < B) ? X[(int64_t)(iy * nx + ix) * B + c] : mk<T>(0, 0);
+    }
     for (int par = 0; par < 4; ++par) {
         const int al = par >> 1, be = par & 1;
-        for (int t = threadIdx.x; t < NTILE; t += kNT) {
-            const int w = t % W, ix = (t / W) % LX, iy = t / (W * LX);
-            const int64_t c = c0 + w;
-            C v = mk<T>(0, 0);
-            if (ix < nx && iy < ny && c < B) {
-                v = X[(int64_t)(iy * nx + ix) * B + c];
+#pragma unroll
+        for (int i = 0; i < NOWN; ++i) {
+            const int t = threadIdx.x + i * kNT;
+            if (t < NTILE) {
+                const int ix = (t / W) % LX, iy = t / (W * LX);
+                C v = xin[i];
                 if (al && iy) v = cmul(v, twy[iy]);
                 if (be && ix) v = cmul(v, twx[ix]);
+                tile[t] = v;
             }
-            tile[t] = v;
         }
         __syncthreads();
         lds_fft_axis<T, LX, false, false, kNT, LY, LX * W, W, W>(tile, twx);
@@ -293,8 +305,11 @@ __global__ void embed_y_kernel(const double2* __restrict__ tmp, double2* __restr
     }
 }
 
+// Columns per workgroup: fill a 128 KB LDS tile (one workgroup per CU), at
+// most 16 columns.  At the 64x64 grid this gives 128 contiguous bytes per
+// lattice point in FP64 (8 columns) and in FP32 (16 columns).
 template <typename T> constexpr int tile_w(int lx, int ly) {
-    int w = (int)(65536 / (lx * ly * (int)sizeof(cplx<T>)));
+    int w = (int)(131072 / (lx * ly * (int)sizeof(cplx<T>)));
     return w > 16 ? 16 : (w < 1 ? 1 : w);
 }
 

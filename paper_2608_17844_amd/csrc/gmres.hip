@@ -32,94 +32,179 @@ namespace mbt {
 
 namespace {
 
-constexpr int kWaves = 4;
-constexpr int kMaxG = 16;              // basis vectors per wave -> restart <= 63
-constexpr int kMaxVec = kWaves * kMaxG;
+constexpr int kMaxVec = 64;            // basis vectors per pass -> restart <= 63
 
 __device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
 __device__ __forceinline__ double2 ld2(const float2* p) { float2 v = *p; return make_double2(v.x, v.y); }
 __device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
 __device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
 
+// RPL consecutive complex values (RHS columns) per lane, widened to FP64.
+// FP32 pairs are moved with one 16-byte access.
+template <int RPL> __device__ __forceinline__ void ldp(const double2* p, double2 (&o)[RPL]) {
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) o[k] = p[k];
+}
+template <int RPL> __device__ __forceinline__ void ldp(const float2* p, double2 (&o)[RPL]) {
+    if constexpr (RPL == 2) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        o[0] = make_double2(v.x, v.y);
+        o[1] = make_double2(v.z, v.w);
+    } else {
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) o[k] = ld2(p + k);
+    }
+}
+template <int RPL> __device__ __forceinline__ void stp(double2* p, const double2 (&v)[RPL]) {
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) p[k] = v[k];
+}
+template <int RPL> __device__ __forceinline__ void stp(float2* p, const double2 (&v)[RPL]) {
+    if constexpr (RPL == 2) {
+        *reinterpret_cast<float4*>(p) = make_float4((float)v[0].x, (float)v[0].y, (float)v[1].x, (float)v[1].y);
+    } else {
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) st2(p + k, v[k]);
+    }
+}
+
+// One pass over the basis V_0..V_{nvec-1} (rows of one chunk, 64*RPL RHS columns
+// per workgroup).  The NW waves of a workgroup read the same rows and columns
+// and split the basis vectors (wave w takes i = w, w+NW, ..., G per wave); a
+// lane owns RPL adjacent RHS columns.
 // MODE 0: h[i] = sum_n conj(V_i[n]) w[n]                         (partials per chunk)
 // MODE 1: w <- w - sum_i coef_i V_i ; h2[i] = sum_n conj(V_i) w   (partials per chunk)
 // MODE 2: w <- w - sum_i coef_i V_i ; ||w||^2                      (partials per chunk)
 // MODE 3: out <- out + sum_i coef_i V_i  (out is FP64; solution update)
-template <typename TB, typename TO, int MODE>
-__global__ __launch_bounds__(256) void arnoldi_kernel(const TB* __restrict__ V, int64_t vstride, int nvec,
-                                                      const double2* __restrict__ coef, TO* w, int64_t N, int R,
-                                                      int64_t rows_per_chunk, double2* __restrict__ partial) {
-    __shared__ double2 xch[2][kWaves][64];
+template <typename TB, typename TO, int MODE, int NW, int G, int RPL>
+__global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__ V, int64_t vstride, int nvec,
+                                                          const double2* __restrict__ coef, TO* w, int64_t N, int R,
+                                                          int64_t rows_per_chunk, double2* __restrict__ partial) {
+    __shared__ double2 xch[2][NW][64 * RPL];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int r = blockIdx.x * 64 + lane;
-    const bool live = r < R;
+    const int r0 = (blockIdx.x * 64 + lane) * RPL;
+    const bool live = r0 < R;            // R is a multiple of RPL
     const int64_t chunk = blockIdx.y;
     const int64_t n0 = chunk * rows_per_chunk;
     const int64_t n1 = min(N, n0 + rows_per_chunk);
 
-    double2 acc[kMaxG];
-    double2 cf[kMaxG];
+    double2 acc[G][RPL];
+    double2 cf[G][RPL];
 #pragma unroll
-    for (int g = 0; g < kMaxG; ++g) {
-        acc[g] = make_double2(0, 0);
-        const int i = wave + kWaves * g;
-        cf[g] = (MODE != 0 && live && i < nvec) ? coef[(int64_t)i * R + r] : make_double2(0, 0);
+    for (int g = 0; g < G; ++g) {
+        const int i = wave + NW * g;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            acc[g][k] = make_double2(0, 0);
+            cf[g][k] = (MODE != 0 && live && i < nvec) ? coef[(int64_t)i * R + r0 + k] : make_double2(0, 0);
+        }
     }
-    double nrm = 0.0;
+    double nrm[RPL];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) nrm[k] = 0.0;
     int buf = 0;
     for (int64_t n = n0; n < n1; ++n) {
-        const int64_t off = n * R + r;
-        if (MODE == 0) {
-            if (live) {
-                const double2 wv = ld2(w + off);
+        const int64_t off = n * R + r0;
+        double2 wv[RPL];
+        double2 vv[G][RPL];
+        if (live) {
+            ldp<RPL>(w + off, wv);
 #pragma unroll
-                for (int g = 0; g < kMaxG; ++g) {
-                    const int i = wave + kWaves * g;
-                    if (i < nvec) acc[g] = cadd(acc[g], cmulc(ld2(V + i * vstride + off), wv));
+            for (int g = 0; g < G; ++g) {
+                const int i = wave + NW * g;
+                if (i < nvec) {
+                    ldp<RPL>(V + i * vstride + off, vv[g]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) vv[g][k] = make_double2(0, 0);
                 }
+            }
+        }
+        if constexpr (MODE == 0) {
+            if (live) {
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) acc[g][k] = cadd(acc[g][k], cmulc(vv[g][k], wv[k]));
             }
         } else {
-            double2 vv[kMaxG];
-            double2 u = make_double2(0, 0);
-            double2 wv = make_double2(0, 0);
+            double2 u[RPL];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) u[k] = make_double2(0, 0);
             if (live) {
-                wv = ld2(w + off);
 #pragma unroll
-                for (int g = 0; g < kMaxG; ++g) {
-                    const int i = wave + kWaves * g;
-                    vv[g] = (i < nvec) ? ld2(V + i * vstride + off) : make_double2(0, 0);
-                    u = cadd(u, cmul(cf[g], vv[g]));
-                }
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) u[k] = cadd(u[k], cmul(cf[g][k], vv[g][k]));
             }
-            xch[buf][wave][lane] = u;
-            __syncthreads();
-            double2 tot = xch[buf][0][lane];
 #pragma unroll
-            for (int k = 1; k < kWaves; ++k) tot = cadd(tot, xch[buf][k][lane]);
+            for (int k = 0; k < RPL; ++k) xch[buf][wave][lane * RPL + k] = u[k];
+            __syncthreads();
+            double2 nw[RPL];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                double2 tot = xch[buf][0][lane * RPL + k];
+#pragma unroll
+                for (int q = 1; q < NW; ++q) tot = cadd(tot, xch[buf][q][lane * RPL + k]);
+                nw[k] = (MODE == 3) ? cadd(wv[k], tot) : csub(wv[k], tot);
+            }
             buf ^= 1;
             if (live) {
-                const double2 nw = (MODE == 3) ? cadd(wv, tot) : csub(wv, tot);
-                if (MODE == 1) {
+                if constexpr (MODE == 1) {
 #pragma unroll
-                    for (int g = 0; g < kMaxG; ++g) acc[g] = cadd(acc[g], cmulc(vv[g], nw));
-                } else if (MODE == 2) {
-                    nrm += nw.x * nw.x + nw.y * nw.y;
+                    for (int g = 0; g < G; ++g)
+#pragma unroll
+                        for (int k = 0; k < RPL; ++k) acc[g][k] = cadd(acc[g][k], cmulc(vv[g][k], nw[k]));
+                } else if constexpr (MODE == 2) {
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) nrm[k] += nw[k].x * nw[k].x + nw[k].y * nw[k].y;
                 }
-                if (wave == 0) st2(w + off, nw);
+                if (wave == 0) stp<RPL>(w + off, nw);
             }
         }
     }
     if (!live) return;
-    if (MODE == 0 || MODE == 1) {
+    if constexpr (MODE == 0 || MODE == 1) {
 #pragma unroll
-        for (int g = 0; g < kMaxG; ++g) {
-            const int i = wave + kWaves * g;
-            if (i < nvec) partial[(chunk * nvec + i) * R + r] = acc[g];
+        for (int g = 0; g < G; ++g) {
+            const int i = wave + NW * g;
+            if (i < nvec)
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) partial[(chunk * nvec + i) * R + r0 + k] = acc[g][k];
         }
-    } else if (MODE == 2) {
-        if (wave == 0) partial[chunk * R + r] = make_double2(nrm, 0.0);
+    } else if constexpr (MODE == 2) {
+        if (wave == 0)
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) partial[chunk * R + r0 + k] = make_double2(nrm[k], 0.0);
     }
+}
+
+template <typename TB, typename TO, int MODE, int RPL>
+void launch_pass_rpl(const TB* V, int64_t vs, int nvec, const double2* coef, TO* w, int64_t N, int R, int64_t rpc,
+                     int nchunk, double2* partial, hipStream_t s) {
+    const dim3 grid((unsigned)((R / RPL + 63) / 64), (unsigned)nchunk);
+    if (nvec <= 4)
+        hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 4, 1, RPL>), grid, dim3(256), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
+    else if (nvec <= 8)
+        hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 4, 2, RPL>), grid, dim3(256), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
+    else if (nvec <= 16)
+        hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 4, 4, RPL>), grid, dim3(256), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
+    else if (nvec <= 32)
+        hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 8, 4, RPL>), grid, dim3(512), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
+    else
+        hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 8, 8, RPL>), grid, dim3(512), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
+    MBT_LAUNCH_CHECK();
+}
+
+// FP32 bases with an even number of columns move two RHS per 16-byte access.
+template <typename TB, typename TO, int MODE>
+void launch_pass(const TB* V, int64_t vs, int nvec, const double2* coef, TO* w, int64_t N, int R, int64_t rpc,
+                 int nchunk, double2* partial, hipStream_t s) {
+    if (sizeof(TB) == 8 && R % 2 == 0)
+        launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s);
+    else
+        launch_pass_rpl<TB, TO, MODE, 1>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s);
 }
 
 // out[i][r] = sum over chunks of partial[chunk][i][r], in chunk order
@@ -317,7 +402,8 @@ inline unsigned ew_grid(int64_t n) {
 
 }  // namespace
 
-int64_t gmres_rows_per_chunk(int64_t N) { return std::max<int64_t>(32, (N + 127) / 128); }
+// Row chunks depend on N only, so a RHS's reduction order never depends on the batch.
+int64_t gmres_rows_per_chunk(int64_t N) { return std::max<int64_t>(32, (N + 255) / 256); }
 int gmres_nchunk(int64_t N) { return (int)((N + gmres_rows_per_chunk(N) - 1) / gmres_rows_per_chunk(N)); }
 
 size_t gmres_state_bytes(int64_t N, int R, int m) {
@@ -368,7 +454,6 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     res.conv.assign(R, 0);
     res.flag.assign(R, 0);
 
-    const dim3 gA((R + 63) / 64, nchunk), bA(256);
     const dim3 gR((R + 255) / 256), bR(256);
     int* h_count = prm.host_count;
 
@@ -403,13 +488,24 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
             apply(vj, w);
             res.matvecs += prm.matvecs_per_apply;
             const int nvec = j + 1;
-            hipLaunchKernelGGL((arnoldi_kernel<TB, TB, 0>), gA, bA, 0, s, Vbasis, vs, nvec, nullptr, w, N, R, rpc, partial);
+            // algorithmic traffic of a pass: nvec basis vectors and w read (+ w written by the updates)
+            const double vbytes = (double)vs * sizeof(TB);
+            {
+                ProfScope ps(kKArnoldiDots, (nvec + 1) * vbytes, 8.0 * nvec * vs, s);
+                launch_pass<TB, TB, 0>(Vbasis, vs, nvec, nullptr, w, N, R, rpc, nchunk, partial, s);
+            }
             hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nvec * R + 255) / 256)), bR, 0, s,
                                partial, nchunk, nvec, R, h1);
-            hipLaunchKernelGGL((arnoldi_kernel<TB, TB, 1>), gA, bA, 0, s, Vbasis, vs, nvec, h1, w, N, R, rpc, partial);
+            {
+                ProfScope ps(kKArnoldiUpdateDots, (nvec + 2) * vbytes, 16.0 * nvec * vs, s);
+                launch_pass<TB, TB, 1>(Vbasis, vs, nvec, h1, w, N, R, rpc, nchunk, partial, s);
+            }
             hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nvec * R + 255) / 256)), bR, 0, s,
                                partial, nchunk, nvec, R, h2);
-            hipLaunchKernelGGL((arnoldi_kernel<TB, TB, 2>), gA, bA, 0, s, Vbasis, vs, nvec, h2, w, N, R, rpc, partial);
+            {
+                ProfScope ps(kKArnoldiUpdateNorm, (nvec + 2) * vbytes, 8.0 * nvec * vs, s);
+                launch_pass<TB, TB, 2>(Vbasis, vs, nvec, h2, w, N, R, rpc, nchunk, partial, s);
+            }
             hipLaunchKernelGGL(finalize_kernel, gR, bR, 0, s, st, h1, h2, partial, nchunk, R, j, m);
             hipLaunchKernelGGL((scale_cols_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, w, st.scale, N, R);
             MBT_LAUNCH_CHECK();
@@ -418,8 +514,7 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
         // y = R^{-1} g ; x += V y
         hipLaunchKernelGGL(cycle_solve_kernel, gR, bR, 0, s, st, R, m, y);
         MBT_LAUNCH_CHECK();
-        hipLaunchKernelGGL((arnoldi_kernel<TB, double2, 3>), gA, bA, 0, s, Vbasis, vs, steps, y, x, N, R, rpc, partial);
-        MBT_LAUNCH_CHECK();
+        launch_pass<TB, double2, 3>(Vbasis, vs, steps, y, x, N, R, rpc, nchunk, partial, s);
         // explicit residual r = b - A x into V_0 (x cast to the basis type into V_1 first)
         TB* xb = Vbasis + vs;
         hipLaunchKernelGGL((from_f64_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, x, xb, vs);

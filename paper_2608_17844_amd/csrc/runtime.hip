@@ -104,6 +104,7 @@ void validate_opts(const mbt_solve_opts& o) {
     MBT_REQUIRE(o.max_cycles >= 1, "max_cycles must be >= 1");
     MBT_REQUIRE(o.prec == MBT_FP64 || (o.refine_max >= 1 && o.refine_tol > 0), "refinement options invalid");
     MBT_REQUIRE(o.rhs_chunk >= 0, "rhs_chunk must be >= 0");
+    MBT_REQUIRE((o.flags & ~MBT_FLAG_NO_CACHE) == 0, "unknown flags");
 }
 
 static double inner_tol(const mbt_solve_opts& o) {
@@ -291,12 +292,27 @@ template <> OpV<float> make_view<float>(const OpData& op, int pc, void* Xh, void
 template <typename T> static void zmul(const OpV<T>& o, int opz, const cplx<T>* x, cplx<T>* y) {
     const Geom& g = *o.g;
     const int64_t B = (int64_t)g.M * o.R;
-    fft_fwd_pad<T>(g, x, o.Xh, B, o.twx, o.twy, o.s);
-    cgemm_batched<T>(o.Chat, (int64_t)g.M * g.M, o.Xh, o.Yh, g.M, o.R, g.bins(), opz, o.s);
-    fft_inv_crop<T>(g, o.Yh, y, B, o.twx, o.twy, o.s);
+    const double sc = sizeof(cplx<T>);
+    const double spat = (double)g.N * o.R * sc, spec = (double)g.bins() * g.M * o.R * sc;
+    {
+        ProfScope ps(kKFftFwd, spat + spec, 0.0, o.s);
+        fft_fwd_pad<T>(g, x, o.Xh, B, o.twx, o.twy, o.s);
+    }
+    {
+        ProfScope ps(kKBinProduct, 2 * spec + (double)g.bins() * g.M * g.M * sc, 8.0 * g.bins() * g.M * g.M * o.R, o.s);
+        cgemm_batched<T>(o.Chat, (int64_t)g.M * g.M, o.Xh, o.Yh, g.M, o.R, g.bins(), opz, o.s);
+    }
+    {
+        ProfScope ps(kKFftInv, spat + spec, 0.0, o.s);
+        fft_inv_crop<T>(g, o.Yh, y, B, o.twx, o.twy, o.s);
+    }
 }
 
 template <typename T> static void pinv(const OpV<T>& o, const cplx<T>* x, cplx<T>* y) {
+    const double sc = sizeof(cplx<T>);
+    const double blocks = o.pstride ? (double)o.g->P : 1.0;
+    ProfScope ps(kKPrecondApply, 2.0 * o.g->N * o.R * sc + blocks * o.g->M * o.g->M * sc,
+                 8.0 * o.g->P * o.g->M * o.g->M * o.R, o.s);
     cgemm_batched<T>(o.pinv, o.pstride, x, y, o.g->M, o.R, o.g->P, 0, o.s);
 }
 
@@ -469,7 +485,14 @@ SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t*
                     const mbt_solve_opts& o, double2* Ydev, Worker& wk, mbt_stats* st) {
     const Geom& g = arr->g;
     const double t0 = now_s();
-    auto op = get_op(ctx, g, s, o.pc == MBT_PC_NORMAL_EQ, o.prec != MBT_FP64, wk);
+    std::shared_ptr<OpData> op;
+    if (o.flags & MBT_FLAG_NO_CACHE) {
+        op = build_op(g, s, wk);
+        if (o.pc == MBT_PC_NORMAL_EQ) build_pa(*op, wk);
+        if (o.prec != MBT_FP64) build_32(*op, wk);
+    } else {
+        op = get_op(ctx, g, s, o.pc == MBT_PC_NORMAL_EQ, o.prec != MBT_FP64, wk);
+    }
     MBT_HIP(hipStreamSynchronize(wk.stream));
     const double t1 = now_s();
     const int chunk = choose_chunk(ctx, g, nports, o);

@@ -20,6 +20,7 @@ MBT_OK, MBT_EINVAL, MBT_ENOMEM, MBT_ENOCONV, MBT_EDEVICE, MBT_EBUSY, MBT_EBREAKD
     0, -1, -2, -3, -4, -5, -6, -7
 MBT_FP64, MBT_FP32, MBT_BF16, MBT_FP16 = 0, 1, 2, 3
 MBT_PC_NORMAL_EQ, MBT_PC_ELEMENT_BLOCK = 0, 1
+MBT_FLAG_NO_CACHE = 1
 STATUS_NAMES = {0: "MBT_OK", -1: "MBT_EINVAL", -2: "MBT_ENOMEM", -3: "MBT_ENOCONV", -4: "MBT_EDEVICE",
                 -5: "MBT_EBUSY", -6: "MBT_EBREAKDOWN", -7: "MBT_ETIMEOUT"}
 
@@ -124,6 +125,8 @@ def lib():
             "mbt_dbg_solve": (S, [_vp, _vp, ctypes.c_double, ctypes.POINTER(mbt_solve_opts), _dp, ctypes.c_int32,
                                   _dp, _ip, ctypes.POINTER(mbt_stats)]),
             "mbt_dbg_inverse": (S, [_vp, _dp, ctypes.c_int32, _dp]),
+            "mbt_prof_start": (S, [ctypes.c_int32]),
+            "mbt_prof_read": (S, [_dp, ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -141,7 +144,7 @@ def exported_symbols() -> list:
         "mbt_port_admittance", "mbt_port_admittance_dev", "mbt_port_impedance", "mbt_solve", "mbt_active",
         "mbt_server_create", "mbt_server_submit", "mbt_server_wait", "mbt_result_free", "mbt_server_clock",
         "mbt_server_destroy", "mbt_dbg_fill_blocks", "mbt_dbg_matvec", "mbt_dbg_precond_apply",
-        "mbt_dbg_precond_blocks", "mbt_dbg_solve", "mbt_dbg_inverse",
+        "mbt_dbg_precond_blocks", "mbt_dbg_solve", "mbt_dbg_inverse", "mbt_prof_start", "mbt_prof_read",
     ]
 
 
@@ -335,3 +338,24 @@ def mbt_dbg_inverse(ctx: int, A: np.ndarray) -> np.ndarray:
     out = np.zeros_like(Af, order="F")
     _check(lib().mbt_dbg_inverse(ctx, _cd(Af), Af.shape[0], _cd(out)))
     return out
+
+
+# ------------------------------------------------------------------ kernel timing
+
+MBT_K_NONE, MBT_K_ARNOLDI_DOTS, MBT_K_ARNOLDI_UPDATE_DOTS, MBT_K_ARNOLDI_UPDATE_NORM = 0, 1, 2, 3
+MBT_K_FFT_FWD, MBT_K_FFT_INV, MBT_K_BIN_PRODUCT, MBT_K_PRECOND_APPLY = 4, 5, 6, 7
+KERNEL_NAMES = {1: "arnoldi_dots", 2: "arnoldi_update_dots", 3: "arnoldi_update_norm", 4: "fft_fwd_pad",
+                5: "fft_inv_crop", 6: "bin_product", 7: "precond_apply"}
+
+
+def mbt_prof_start(kernel: int) -> None:
+    _check(lib().mbt_prof_start(kernel))
+
+
+def mbt_prof_read() -> dict:
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    by = ctypes.c_double()
+    fl = ctypes.c_double()
+    _check(lib().mbt_prof_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by), ctypes.byref(fl)))
+    return {"ms": ms.value, "launches": n.value, "bytes": by.value, "flops": fl.value}
