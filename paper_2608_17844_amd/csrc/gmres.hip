@@ -68,6 +68,34 @@ template <int RPL> __device__ __forceinline__ void stp(float2* p, const double2 
     }
 }
 
+// Raw (storage-format) pack of RPL adjacent complex values, kept in registers
+// between the load of the next row and its use; widened to FP64 at use.
+template <typename T, int RPL> struct Raw;
+template <> struct Raw<double2, 1> {
+    double2 v;
+    __device__ __forceinline__ void load(const double2* p) { v = *p; }
+    __device__ __forceinline__ void zero() { v = make_double2(0, 0); }
+    __device__ __forceinline__ double2 get(int) const { return v; }
+};
+template <> struct Raw<double2, 2> {
+    double2 v[2];
+    __device__ __forceinline__ void load(const double2* p) { v[0] = p[0]; v[1] = p[1]; }
+    __device__ __forceinline__ void zero() { v[0] = v[1] = make_double2(0, 0); }
+    __device__ __forceinline__ double2 get(int k) const { return v[k]; }
+};
+template <> struct Raw<float2, 1> {
+    float2 v;
+    __device__ __forceinline__ void load(const float2* p) { v = *p; }
+    __device__ __forceinline__ void zero() { v = make_float2(0, 0); }
+    __device__ __forceinline__ double2 get(int) const { return make_double2(v.x, v.y); }
+};
+template <> struct Raw<float2, 2> {
+    float4 v;
+    __device__ __forceinline__ void load(const float2* p) { v = *reinterpret_cast<const float4*>(p); }
+    __device__ __forceinline__ void zero() { v = make_float4(0, 0, 0, 0); }
+    __device__ __forceinline__ double2 get(int k) const { return k ? make_double2(v.z, v.w) : make_double2(v.x, v.y); }
+};
+
 // One pass over the basis V_0..V_{nvec-1} (rows of one chunk, 64*RPL RHS columns
 // per workgroup).  The NW waves of a workgroup read the same rows and columns
 // and split the basis vectors (wave w takes i = w, w+NW, ..., G per wave); a
@@ -104,29 +132,34 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 #pragma unroll
     for (int k = 0; k < RPL; ++k) nrm[k] = 0.0;
     int buf = 0;
+    // rows are software-pipelined: the loads of row n+1 are issued before the
+    // arithmetic (and the cross-wave exchange) of row n
+    Raw<TB, RPL> cur[G], nxt[G];
+    Raw<TO, RPL> cw, nw_raw;
+    auto load_row = [&](int64_t n, Raw<TB, RPL>(&v)[G], Raw<TO, RPL>& wr) {
+        const int64_t off = n * R + r0;
+        wr.load(w + off);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = wave + NW * g;
+            if (i < nvec) v[g].load(V + i * vstride + off);
+            else v[g].zero();
+        }
+    };
+    if (live && n0 < n1) load_row(n0, cur, cw);
     for (int64_t n = n0; n < n1; ++n) {
         const int64_t off = n * R + r0;
+        if (live && n + 1 < n1) load_row(n + 1, nxt, nw_raw);
+        // values are widened at each use from the raw registers (no widened copies live across the barrier)
         double2 wv[RPL];
-        double2 vv[G][RPL];
-        if (live) {
-            ldp<RPL>(w + off, wv);
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int i = wave + NW * g;
-                if (i < nvec) {
-                    ldp<RPL>(V + i * vstride + off, vv[g]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < RPL; ++k) vv[g][k] = make_double2(0, 0);
-                }
-            }
-        }
+        for (int k = 0; k < RPL; ++k) wv[k] = cw.get(k);
         if constexpr (MODE == 0) {
             if (live) {
 #pragma unroll
                 for (int g = 0; g < G; ++g)
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) acc[g][k] = cadd(acc[g][k], cmulc(vv[g][k], wv[k]));
+                    for (int k = 0; k < RPL; ++k) acc[g][k] = cadd(acc[g][k], cmulc(cur[g].get(k), wv[k]));
             }
         } else {
             double2 u[RPL];
@@ -136,7 +169,7 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 #pragma unroll
                 for (int g = 0; g < G; ++g)
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) u[k] = cadd(u[k], cmul(cf[g][k], vv[g][k]));
+                    for (int k = 0; k < RPL; ++k) u[k] = cadd(u[k], cmul(cf[g][k], cur[g].get(k)));
             }
 #pragma unroll
             for (int k = 0; k < RPL; ++k) xch[buf][wave][lane * RPL + k] = u[k];
@@ -155,7 +188,7 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 #pragma unroll
                     for (int g = 0; g < G; ++g)
 #pragma unroll
-                        for (int k = 0; k < RPL; ++k) acc[g][k] = cadd(acc[g][k], cmulc(vv[g][k], nw[k]));
+                        for (int k = 0; k < RPL; ++k) acc[g][k] = cadd(acc[g][k], cmulc(cur[g].get(k), nw[k]));
                 } else if constexpr (MODE == 2) {
 #pragma unroll
                     for (int k = 0; k < RPL; ++k) nrm[k] += nw[k].x * nw[k].x + nw[k].y * nw[k].y;
@@ -163,6 +196,9 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
                 if (wave == 0) stp<RPL>(w + off, nw);
             }
         }
+#pragma unroll
+        for (int g = 0; g < G; ++g) cur[g] = nxt[g];
+        cw = nw_raw;
     }
     if (!live) return;
     if constexpr (MODE == 0 || MODE == 1) {
@@ -201,10 +237,14 @@ void launch_pass_rpl(const TB* V, int64_t vs, int nvec, const double2* coef, TO*
 template <typename TB, typename TO, int MODE>
 void launch_pass(const TB* V, int64_t vs, int nvec, const double2* coef, TO* w, int64_t N, int R, int64_t rpc,
                  int nchunk, double2* partial, hipStream_t s) {
-    if (sizeof(TB) == 8 && R % 2 == 0)
-        launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s);
-    else
-        launch_pass_rpl<TB, TO, MODE, 1>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s);
+    if constexpr (sizeof(TB) == 8) {
+        // the update-and-dot pass over more than 32 vectors keeps one RHS per lane (register budget)
+        if (R % 2 == 0 && !(MODE == 1 && nvec > 32)) {
+            launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s);
+            return;
+        }
+    }
+    launch_pass_rpl<TB, TO, MODE, 1>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s);
 }
 
 // out[i][r] = sum over chunks of partial[chunk][i][r], in chunk order
