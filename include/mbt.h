@@ -90,6 +90,11 @@ typedef struct {
  * call instead of using (and filling) the context's per-(array, frequency)
  * cache; used to time the complete path. */
 #define MBT_FLAG_NO_CACHE 1
+/* mbt_solve_opts.flags: orthogonalise the Arnoldi basis by classical
+ * Gram-Schmidt applied twice in three sweeps over the basis (CGS2) instead of
+ * the default delayed reorthogonalisation (DCGS2, two sweeps; same iterates in
+ * exact arithmetic). */
+#define MBT_FLAG_CGS2 2
 
 typedef struct {
     int32_t nrhs;             /* RHS solved */

@@ -184,14 +184,110 @@ def gmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, restart: i
     return res
 
 
+def _rotate_column(H, cs, sn, g, j):
+    """Apply the previous rotations to column j of H, form rotation j, update g."""
+    for i in range(j):
+        a_, b_ = H[i, j], H[i + 1, j]
+        H[i, j] = cs[i] * a_ + sn[i] * b_
+        H[i + 1, j] = -np.conj(sn[i]) * a_ + cs[i] * b_
+    cs[j], sn[j] = givens(H[j, j], H[j + 1, j])
+    H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+    H[j + 1, j] = 0.0
+    g[j + 1] = -np.conj(sn[j]) * g[j]
+    g[j] = cs[j] * g[j]
+
+
+def gmres_dcgs2(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, restart: int = 50,
+                tol: float = 1e-10, max_cycles: int = 400) -> GmresResult:
+    """GMRES(m) with delayed classical Gram-Schmidt reorthogonalisation (DCGS2,
+    Swirydowicz, Langou, Ananthan, Yang and Thomas, "Low synchronization
+    Gram-Schmidt and GMRES algorithms", Numer. Linear Algebra Appl. 2021).
+
+    The operator is applied to the candidate u_k (the once-projected, not yet
+    reorthogonalised or normalised next vector).  One sweep then gives
+    s = V^H u, z = V^H w, ||u||^2 and u^H w; the reorthogonalisation of u
+    (coefficients s, norm nu = sqrt(||u||^2 - ||s||^2)) completes Hessenberg
+    column k-1, and the projection of A v_k = (w - V Hbar s)/nu is obtained from
+    z by the Arnoldi relation, so that one update sweep writes both v_k and the
+    next candidate.  In exact arithmetic the iterates equal those of CGS2-GMRES;
+    the stopping rule and x0 are the same as in gmres()."""
+    n = b.shape[0]
+    m = restart
+    x = np.zeros(n, dtype=np.complex128)
+    bnorm = np.linalg.norm(b)
+    res = GmresResult(x, 0, False, 0)
+    if bnorm == 0.0:
+        res.converged = True
+        return res
+    r = b.copy()
+    beta = np.linalg.norm(r)
+    for cycle in range(max_cycles):
+        res.restart_residuals.append(beta)
+        if beta <= tol * bnorm:
+            res.converged = True
+            break
+        res.cycles = cycle + 1
+        V = np.zeros((m + 1, n), dtype=np.complex128)
+        Hraw = np.zeros((m + 1, m), dtype=np.complex128)    # unrotated Hessenberg
+        Hrot = np.zeros((m + 1, m), dtype=np.complex128)    # rotated copy (upper triangular part used)
+        cs = np.zeros(m)
+        sn = np.zeros(m, dtype=np.complex128)
+        g = np.zeros(m + 1, dtype=np.complex128)
+        u = r / beta
+        k = 0
+        steps = 0
+        av_norm = 1.0     # ||A v_{k-1}||, for the Arnoldi norm ratio diagnostic
+        while True:
+            w = apply_A(u) if k < m else None
+            Vf = V[:k]
+            s = Vf.conj() @ u
+            alpha = np.vdot(u, u).real
+            nu = np.sqrt(max(alpha - np.vdot(s, s).real, 0.0))
+            if k == 0:
+                g[0] = beta * nu
+            else:
+                Hraw[:k, k - 1] += s
+                Hraw[k, k - 1] = nu
+                Hrot[:k + 1, k - 1] = Hraw[:k + 1, k - 1]
+                _rotate_column(Hrot, cs, sn, g, k - 1)
+                res.iters += 1
+                res.history.append(abs(g[k]))
+                res.arnoldi_ratio.append(nu / av_norm if av_norm > 0 else 0.0)
+                steps = k
+                if abs(g[k]) <= tol * bnorm or nu == 0.0 or k == m:
+                    break
+            z = Vf.conj() @ w
+            bet = np.vdot(u, w)
+            V[k] = (u - Vf.T @ s) / nu
+            t = Hraw[:k + 1, :k] @ s
+            h = np.zeros(k + 1, dtype=np.complex128)
+            h[:k] = (z - t[:k]) / nu
+            h[k] = ((bet - np.vdot(s, z)) / nu - t[k]) / nu
+            c = t / nu + h
+            u = w / nu - V[:k + 1].T @ c
+            Hraw[:k + 1, k] = h
+            av_norm = np.linalg.norm(u + V[:k + 1].T @ h)
+            k += 1
+        y = sla.solve_triangular(Hrot[:steps, :steps], g[:steps], lower=False)
+        x = x + V[:steps].T @ y
+        if abs(g[steps]) <= tol * bnorm:
+            res.converged = True
+            break
+        r = b - apply_A(x)
+        beta = np.linalg.norm(r)
+    res.x = x
+    return res
+
+
 def gmres_all(system: PreconditionedSystem, V: np.ndarray, restart: int = 50, tol: float = 1e-10,
-              max_cycles: int = 400):
+              max_cycles: int = 400, orth: str = "cgs2"):
     """Independent GMRES for every column of V; returns (I, per-RHS results)."""
+    solver = gmres if orth == "cgs2" else gmres_dcgs2
     B = system.rhs(V)
     I = np.zeros_like(V)
     results = []
     for j in range(V.shape[1]):
-        r = gmres(system.apply, B[:, j], restart, tol, max_cycles)
+        r = solver(system.apply, B[:, j], restart, tol, max_cycles)
         I[:, j] = r.x
         results.append(r)
     return I, results

@@ -44,6 +44,7 @@ struct GmresParams {
     double tol = 1e-10;
     int max_cycles = 400;
     int matvecs_per_apply = 1;
+    bool dcgs2 = true;           // delayed reorthogonalisation (two sweeps); false: classical CGS2 (three)
     int* host_count = nullptr;   // pinned host int for the active-count readback
 };
 

@@ -216,6 +216,339 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
     }
 }
 
+// ------------------------------------------------------------------ delayed reorthogonalisation (DCGS2)
+// Dot sweep: with u the candidate (slot k) and w = A u (slot k+1),
+//   s_i = V_i^H u, z_i = V_i^H w (i < k), alpha = u^H u, beta = u^H w.
+// Partials per chunk: [s_0..s_{k-1}, z_0..z_{k-1}, alpha, beta].
+template <typename TB, int NW, int G, int RPL, bool HASW>
+__global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TB* __restrict__ V, int64_t vstride, int k,
+                                                             const TB* __restrict__ u, const TB* __restrict__ w,
+                                                             int64_t N, int R, int64_t rows_per_chunk,
+                                                             double2* __restrict__ partial) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r0 = (blockIdx.x * 64 + lane) * RPL;
+    const bool live = r0 < R;
+    const int64_t chunk = blockIdx.y;
+    const int64_t n0 = chunk * rows_per_chunk;
+    const int64_t n1 = min(N, n0 + rows_per_chunk);
+    const int nred = 2 * k + 2;
+    double2 as[G][RPL], az[G][RPL], aa[RPL], ab[RPL];
+#pragma unroll
+    for (int k2 = 0; k2 < RPL; ++k2) {
+        aa[k2] = ab[k2] = make_double2(0, 0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) as[g][k2] = az[g][k2] = make_double2(0, 0);
+    }
+    Raw<TB, RPL> cur[G], nxt[G], cu, nu_, cw, nw_;
+    auto load_row = [&](int64_t n, Raw<TB, RPL>(&v)[G], Raw<TB, RPL>& ur, Raw<TB, RPL>& wr) {
+        const int64_t off = n * R + r0;
+        ur.load(u + off);
+        if (HASW) wr.load(w + off);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = wave + NW * g;
+            if (i < k) v[g].load(V + i * vstride + off);
+            else v[g].zero();
+        }
+    };
+    if (live && n0 < n1) load_row(n0, cur, cu, cw);
+    for (int64_t n = n0; n < n1; ++n) {
+        if (live && n + 1 < n1) load_row(n + 1, nxt, nu_, nw_);
+        if (live) {
+#pragma unroll
+            for (int k2 = 0; k2 < RPL; ++k2) {
+                const double2 uv = cu.get(k2);
+                const double2 wv = HASW ? cw.get(k2) : make_double2(0, 0);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const double2 vv = cur[g].get(k2);
+                    as[g][k2] = cadd(as[g][k2], cmulc(vv, uv));
+                    if (HASW) az[g][k2] = cadd(az[g][k2], cmulc(vv, wv));
+                }
+                if (wave == 0) {
+                    aa[k2].x += uv.x * uv.x + uv.y * uv.y;
+                    if (HASW) ab[k2] = cadd(ab[k2], cmulc(uv, wv));
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) cur[g] = nxt[g];
+        cu = nu_;
+        cw = nw_;
+    }
+    if (!live) return;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int i = wave + NW * g;
+        if (i < k)
+#pragma unroll
+            for (int k2 = 0; k2 < RPL; ++k2) {
+                partial[(chunk * nred + i) * R + r0 + k2] = as[g][k2];
+                partial[(chunk * nred + k + i) * R + r0 + k2] = az[g][k2];
+            }
+    }
+    if (wave == 0)
+#pragma unroll
+        for (int k2 = 0; k2 < RPL; ++k2) {
+            partial[(chunk * nred + 2 * k) * R + r0 + k2] = aa[k2];
+            partial[(chunk * nred + 2 * k + 1) * R + r0 + k2] = ab[k2];
+        }
+}
+
+// Update sweep: v_k = (u - sum_{i<k} s_i V_i) / nu  (into slot k, over u),
+//               u_{k+1} = w / nu - sum_{i<k} c_i V_i - c_k v_k  (into slot k+1, over w).
+template <typename TB, int NW, int G, int RPL>
+__global__ __launch_bounds__(NW * 64) void dcgs2_update_kernel(const TB* __restrict__ V, int64_t vstride, int k,
+                                                               TB* u, TB* w, const double2* __restrict__ cs,
+                                                               const double2* __restrict__ cc,
+                                                               const double* __restrict__ inv_nu, int64_t N, int R,
+                                                               int64_t rows_per_chunk) {
+    __shared__ double2 xch[2][NW][2 * 64 * RPL];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r0 = (blockIdx.x * 64 + lane) * RPL;
+    const bool live = r0 < R;
+    const int64_t chunk = blockIdx.y;
+    const int64_t n0 = chunk * rows_per_chunk;
+    const int64_t n1 = min(N, n0 + rows_per_chunk);
+    double2 fs[G][RPL], fc[G][RPL], ck[RPL];
+    double inu[RPL];
+#pragma unroll
+    for (int k2 = 0; k2 < RPL; ++k2) {
+        inu[k2] = live ? inv_nu[r0 + k2] : 0.0;
+        ck[k2] = live ? cc[(int64_t)k * R + r0 + k2] : make_double2(0, 0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = wave + NW * g;
+            fs[g][k2] = (live && i < k) ? cs[(int64_t)i * R + r0 + k2] : make_double2(0, 0);
+            fc[g][k2] = (live && i < k) ? cc[(int64_t)i * R + r0 + k2] : make_double2(0, 0);
+        }
+    }
+    Raw<TB, RPL> cur[G], nxt[G], cu, nu_, cw, nw_;
+    auto load_row = [&](int64_t n, Raw<TB, RPL>(&v)[G], Raw<TB, RPL>& ur, Raw<TB, RPL>& wr) {
+        const int64_t off = n * R + r0;
+        ur.load(u + off);
+        wr.load(w + off);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = wave + NW * g;
+            if (i < k) v[g].load(V + i * vstride + off);
+            else v[g].zero();
+        }
+    };
+    if (live && n0 < n1) load_row(n0, cur, cu, cw);
+    int buf = 0;
+    for (int64_t n = n0; n < n1; ++n) {
+        const int64_t off = n * R + r0;
+        if (live && n + 1 < n1) load_row(n + 1, nxt, nu_, nw_);
+#pragma unroll
+        for (int k2 = 0; k2 < RPL; ++k2) {
+            double2 a = make_double2(0, 0), c = make_double2(0, 0);
+            if (live) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const double2 vv = cur[g].get(k2);
+                    a = cadd(a, cmul(fs[g][k2], vv));
+                    c = cadd(c, cmul(fc[g][k2], vv));
+                }
+            }
+            xch[buf][wave][2 * (lane * RPL + k2)] = a;
+            xch[buf][wave][2 * (lane * RPL + k2) + 1] = c;
+        }
+        __syncthreads();
+        if (live && wave == 0) {
+            double2 vk[RPL], un[RPL];
+#pragma unroll
+            for (int k2 = 0; k2 < RPL; ++k2) {
+                double2 a = xch[buf][0][2 * (lane * RPL + k2)], c = xch[buf][0][2 * (lane * RPL + k2) + 1];
+#pragma unroll
+                for (int q = 1; q < NW; ++q) {
+                    a = cadd(a, xch[buf][q][2 * (lane * RPL + k2)]);
+                    c = cadd(c, xch[buf][q][2 * (lane * RPL + k2) + 1]);
+                }
+                const double2 d = csub(cu.get(k2), a);
+                vk[k2] = make_double2(d.x * inu[k2], d.y * inu[k2]);
+                const double2 wv = cw.get(k2);
+                un[k2] = csub(csub(make_double2(wv.x * inu[k2], wv.y * inu[k2]), c), cmul(ck[k2], vk[k2]));
+            }
+            stp<RPL>(u + off, vk);
+            stp<RPL>(w + off, un);
+        }
+        buf ^= 1;
+#pragma unroll
+        for (int g = 0; g < G; ++g) cur[g] = nxt[g];
+        cu = nu_;
+        cw = nw_;
+    }
+}
+
+// Per-RHS bookkeeping of DCGS2 step k (red: reduced [s, z, alpha, beta]):
+// completes Hessenberg column k-1 (raw and rotated), Givens, convergence; then
+// the coefficients of the update sweep and the first projection of column k.
+__global__ void dcgs2_finalize_kernel(GmresState st, double2* __restrict__ Hraw, const double2* __restrict__ red,
+                                      int R, int k, int m, double2* __restrict__ cs_out, double2* __restrict__ cc_out,
+                                      double* __restrict__ inv_nu) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int64_t ldH = (int64_t)(m + 1) * R;
+    auto RED = [&](int i) { return red[(int64_t)i * R + r]; };
+    if (!st.active[r]) {
+        inv_nu[r] = 0.0;
+        for (int i = 0; i <= k; ++i) {
+            if (i < k) cs_out[(int64_t)i * R + r] = make_double2(0, 0);
+            cc_out[(int64_t)i * R + r] = make_double2(0, 0);
+        }
+        return;
+    }
+    double ss = 0;
+    for (int i = 0; i < k; ++i) {
+        const double2 s = RED(i);
+        ss += s.x * s.x + s.y * s.y;
+    }
+    const double alpha = RED(2 * k).x;
+    const double nu = sqrt(fmax(alpha - ss, 0.0));
+    bool stop = false;
+    if (k == 0) {
+        st.g[r] = make_double2(st.beta[r] * nu, 0.0);
+    } else {
+        double2* Hc = Hraw + (int64_t)(k - 1) * ldH;
+        double2* Hj = st.H + (int64_t)(k - 1) * ldH;
+        for (int i = 0; i < k; ++i) Hc[(int64_t)i * R + r] = cadd(Hc[(int64_t)i * R + r], RED(i));
+        Hc[(int64_t)k * R + r] = make_double2(nu, 0.0);
+        for (int i = 0; i <= k; ++i) Hj[(int64_t)i * R + r] = Hc[(int64_t)i * R + r];
+        const int j = k - 1;
+        for (int i = 0; i < j; ++i) {
+            const double c = st.cs[(int64_t)i * R + r];
+            const double2 s = st.sn[(int64_t)i * R + r];
+            const double2 a = Hj[(int64_t)i * R + r], b = Hj[(int64_t)(i + 1) * R + r];
+            Hj[(int64_t)i * R + r] = cadd(make_double2(c * a.x, c * a.y), cmul(s, b));
+            Hj[(int64_t)(i + 1) * R + r] = csub(make_double2(c * b.x, c * b.y), cmulc(s, a));
+        }
+        const double2 h1v = Hj[(int64_t)j * R + r];
+        double c;
+        double2 s;
+        const double a1 = hypot(h1v.x, h1v.y);
+        if (a1 == 0.0) {
+            c = 0.0;
+            s = make_double2(1.0, 0.0);
+        } else {
+            const double t = hypot(a1, nu);
+            c = a1 / t;
+            s = make_double2(h1v.x / a1 * nu / t, h1v.y / a1 * nu / t);
+        }
+        st.cs[(int64_t)j * R + r] = c;
+        st.sn[(int64_t)j * R + r] = s;
+        Hj[(int64_t)j * R + r] = cadd(make_double2(c * h1v.x, c * h1v.y), make_double2(s.x * nu, s.y * nu));
+        Hj[(int64_t)(j + 1) * R + r] = make_double2(0, 0);
+        const double2 gj = st.g[(int64_t)j * R + r];
+        const double2 gn = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+        st.g[(int64_t)j * R + r] = make_double2(c * gj.x, c * gj.y);
+        st.g[(int64_t)(j + 1) * R + r] = gn;
+        st.iters[r] += 1;
+        st.kcyc[r] = k;
+        const double res = hypot(gn.x, gn.y);
+        if (!(nu == nu) || isinf(nu) || !(res == res)) {
+            st.flag[r] = 1;
+            stop = true;
+        } else if (res <= st.tol * st.bnorm[r] || nu == 0.0 || k == m) {
+            stop = true;
+        }
+    }
+    if (stop || k == m || nu == 0.0) {
+        st.active[r] = 0;
+        inv_nu[r] = 0.0;
+        for (int i = 0; i <= k; ++i) {
+            if (i < k) cs_out[(int64_t)i * R + r] = make_double2(0, 0);
+            cc_out[(int64_t)i * R + r] = make_double2(0, 0);
+        }
+        return;
+    }
+    // t = Hbar_{k-1} s (rows 0..k), h = projections of A v_k, c = t/nu + h
+    const double in = 1.0 / nu;
+    double2 sz = make_double2(0, 0);
+    for (int i = 0; i < k; ++i) sz = cadd(sz, cmulc(RED(i), RED(k + i)));
+    const double2 bet = RED(2 * k + 1);
+    double2* Hk = Hraw + (int64_t)k * ldH;
+    for (int i = 0; i <= k; ++i) {
+        double2 t = make_double2(0, 0);
+        for (int l = (i > 0 ? i - 1 : 0); l < k; ++l)   // Hbar is upper Hessenberg: H[i][l] = 0 for l < i-1
+            t = cadd(t, cmul(Hraw[(int64_t)l * ldH + (int64_t)i * R + r], RED(l)));
+        double2 h;
+        if (i < k) {
+            const double2 d = csub(RED(k + i), t);
+            h = make_double2(d.x * in, d.y * in);
+        } else {
+            const double2 q = csub(bet, sz);
+            h = make_double2((q.x * in - t.x) * in, (q.y * in - t.y) * in);
+        }
+        Hk[(int64_t)i * R + r] = h;
+        cc_out[(int64_t)i * R + r] = make_double2(t.x * in + h.x, t.y * in + h.y);
+        if (i < k) cs_out[(int64_t)i * R + r] = RED(i);
+    }
+    inv_nu[r] = in;
+}
+
+template <typename TB, int RPL, bool HASW>
+void launch_dcgs2_dots_rpl(const TB* V, int64_t vs, int k, const TB* u, const TB* w, int64_t N, int R, int64_t rpc,
+                           int nchunk, double2* partial, hipStream_t s) {
+    const dim3 grid((unsigned)((R / RPL + 63) / 64), (unsigned)nchunk);
+    if (k <= 4)
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 1, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, u, w, N, R, rpc, partial);
+    else if (k <= 8)
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 2, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, u, w, N, R, rpc, partial);
+    else if (k <= 16)
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 4, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, u, w, N, R, rpc, partial);
+    else if (k <= 32)
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 8, 4, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, u, w, N, R, rpc, partial);
+    else
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 8, 8, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, u, w, N, R, rpc, partial);
+    MBT_LAUNCH_CHECK();
+}
+
+template <typename TB, int RPL>
+void launch_dcgs2_update_rpl(const TB* V, int64_t vs, int k, TB* u, TB* w, const double2* cs, const double2* cc,
+                             const double* inv_nu, int64_t N, int R, int64_t rpc, int nchunk, hipStream_t s) {
+    const dim3 grid((unsigned)((R / RPL + 63) / 64), (unsigned)nchunk);
+    if (k <= 4)
+        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 4, 1, RPL>), grid, dim3(256), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
+    else if (k <= 8)
+        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 4, 2, RPL>), grid, dim3(256), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
+    else if (k <= 16)
+        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 4, 4, RPL>), grid, dim3(256), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
+    else if (k <= 32)
+        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 8, 4, RPL>), grid, dim3(512), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
+    else
+        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 8, 8, RPL>), grid, dim3(512), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
+    MBT_LAUNCH_CHECK();
+}
+
+template <typename TB>
+void launch_dcgs2_dots(const TB* V, int64_t vs, int k, const TB* u, const TB* w, int64_t N, int R, int64_t rpc,
+                       int nchunk, double2* partial, hipStream_t s) {
+    if constexpr (sizeof(TB) == 8) {
+        if (R % 2 == 0 && k <= 32) {
+            if (w) launch_dcgs2_dots_rpl<TB, 2, true>(V, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+            else launch_dcgs2_dots_rpl<TB, 2, false>(V, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+            return;
+        }
+    }
+    if (w) launch_dcgs2_dots_rpl<TB, 1, true>(V, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+    else launch_dcgs2_dots_rpl<TB, 1, false>(V, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+}
+
+template <typename TB>
+void launch_dcgs2_update(const TB* V, int64_t vs, int k, TB* u, TB* w, const double2* cs, const double2* cc,
+                         const double* inv_nu, int64_t N, int R, int64_t rpc, int nchunk, hipStream_t s) {
+    if constexpr (sizeof(TB) == 8) {
+        if (R % 2 == 0 && k <= 32) {
+            launch_dcgs2_update_rpl<TB, 2>(V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc, nchunk, s);
+            return;
+        }
+    }
+    launch_dcgs2_update_rpl<TB, 1>(V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc, nchunk, s);
+}
+
 template <typename TB, typename TO, int MODE, int RPL>
 void launch_pass_rpl(const TB* V, int64_t vs, int nvec, const double2* coef, TO* w, int64_t N, int R, int64_t rpc,
                      int nchunk, double2* partial, hipStream_t s) {
@@ -455,8 +788,11 @@ size_t gmres_state_bytes(int64_t N, int R, int m) {
     s += sizeof(double2) * (size_t)(m + 1) * R;                // g
     s += sizeof(double2) * (size_t)(m + 1) * R * 2;            // h1, h2
     s += sizeof(double2) * (size_t)m * R;                      // y
-    s += sizeof(double2) * (size_t)nchunk * (m + 1) * R;       // partials
+    s += sizeof(double2) * (size_t)nchunk * (2 * m + 2) * R;   // partials
     s += sizeof(double) * (size_t)R * 4 + sizeof(int) * (size_t)R * 6 + 64;
+    // delayed reorthogonalisation: unrotated Hessenberg, reduced sweep, coefficients, 1/nu
+    s += sizeof(double2) * (size_t)(m + 1) * (m + 1) * R + sizeof(double2) * (size_t)(2 * m + 2) * R +
+         sizeof(double2) * (size_t)(2 * m + 1) * R + sizeof(double) * (size_t)R + 4 * 256;
     return s;
 }
 
@@ -487,7 +823,19 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     double2* h1 = arena.get<double2>((size_t)(m + 1) * R);
     double2* h2 = arena.get<double2>((size_t)(m + 1) * R);
     double2* y = arena.get<double2>((size_t)m * R);
-    double2* partial = arena.get<double2>((size_t)nchunk * (m + 1) * R);
+    double2* partial = arena.get<double2>((size_t)nchunk * (2 * m + 2) * R);
+    double2* Hraw = nullptr;
+    double2* red = nullptr;
+    double2* coef_s = nullptr;
+    double2* coef_c = nullptr;
+    double* inv_nu = nullptr;
+    if (prm.dcgs2) {
+        Hraw = arena.get<double2>((size_t)(m + 1) * (m + 1) * R);
+        red = arena.get<double2>((size_t)(2 * m + 2) * R);
+        coef_s = arena.get<double2>((size_t)m * R);
+        coef_c = arena.get<double2>((size_t)(m + 1) * R);
+        inv_nu = arena.get<double>(R);
+    }
 
     GmresResult res;
     res.iters.assign(R, 0);
@@ -521,7 +869,34 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
         hipLaunchKernelGGL((scale_cols_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, Vbasis, st.scale, N, R);
         MBT_LAUNCH_CHECK();
         int steps = 0;
-        for (int j = 0; j < m; ++j) {
+        // delayed reorthogonalisation: slot k holds the candidate u_k, slot k+1 receives w = A u_k;
+        // one dot sweep and one update sweep per step (the last step needs only the dots of u_m)
+        for (int k = 0; prm.dcgs2 && k <= m; ++k) {
+            const bool hasw = k < m;
+            TB* u = Vbasis + (int64_t)k * vs;
+            TB* w = hasw ? Vbasis + (int64_t)(k + 1) * vs : nullptr;
+            if (hasw) {
+                apply(u, w);
+                res.matvecs += prm.matvecs_per_apply;
+            }
+            const double vbytes = (double)vs * sizeof(TB);
+            {
+                ProfScope ps(kKArnoldiDots, (k + (hasw ? 2 : 1)) * vbytes, 8.0 * (2 * k + 2) * vs, s);
+                launch_dcgs2_dots<TB>(Vbasis, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+            }
+            const int nred = 2 * k + 2;
+            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nred * R + 255) / 256)), bR, 0, s,
+                               partial, nchunk, nred, R, red);
+            hipLaunchKernelGGL(dcgs2_finalize_kernel, gR, bR, 0, s, st, Hraw, red, R, k, m, coef_s, coef_c, inv_nu);
+            MBT_LAUNCH_CHECK();
+            steps = k;
+            if (k == m || count_active() == 0) break;
+            {
+                ProfScope ps(kKArnoldiUpdateDots, (k + 2) * vbytes + 2 * vbytes, 16.0 * k * vs, s);
+                launch_dcgs2_update<TB>(Vbasis, vs, k, u, w, coef_s, coef_c, inv_nu, N, R, rpc, nchunk, s);
+            }
+        }
+        for (int j = 0; !prm.dcgs2 && j < m; ++j) {
             steps = j + 1;
             TB* vj = Vbasis + (int64_t)j * vs;
             TB* w = Vbasis + (int64_t)(j + 1) * vs;

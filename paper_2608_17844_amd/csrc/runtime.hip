@@ -104,7 +104,7 @@ void validate_opts(const mbt_solve_opts& o) {
     MBT_REQUIRE(o.max_cycles >= 1, "max_cycles must be >= 1");
     MBT_REQUIRE(o.prec == MBT_FP64 || (o.refine_max >= 1 && o.refine_tol > 0), "refinement options invalid");
     MBT_REQUIRE(o.rhs_chunk >= 0, "rhs_chunk must be >= 0");
-    MBT_REQUIRE((o.flags & ~MBT_FLAG_NO_CACHE) == 0, "unknown flags");
+    MBT_REQUIRE((o.flags & ~(MBT_FLAG_NO_CACHE | MBT_FLAG_CGS2)) == 0, "unknown flags");
 }
 
 static double inner_tol(const mbt_solve_opts& o) {
@@ -386,6 +386,7 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
     prm.max_cycles = o.max_cycles;
     prm.matvecs_per_apply = o.pc == MBT_PC_NORMAL_EQ ? 2 : 1;
     prm.host_count = wk.host_count;
+    prm.dcgs2 = !(o.flags & MBT_FLAG_CGS2);
     std::vector<double> vn;
     norms_host(V, g.N, R, arena, vn, s);
 

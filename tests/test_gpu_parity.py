@@ -150,16 +150,18 @@ def _iteration_parity(gpu_iters, ref):
 
 
 @pytest.mark.parametrize("pc", ["element_block", "normal_eq"])
-def test_gmres_iteration_parity_and_admittance_cfg_5x5(ctx, make_array, cfg1, cfg1_oracle, pc):
+@pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
+def test_gmres_iteration_parity_and_admittance_cfg_5x5(ctx, make_array, cfg1, cfg1_oracle, pc, orth):
     from paper_2608_17844_amd import mbt
     lat, dip = cfg1.lattice, cfg1.dipole
-    _say("gmres parity", pc)
+    _say("gmres parity", pc, orth)
     a = make_array(lat, dip)
     code = mbt.MBT_PC_ELEMENT_BLOCK if pc == "element_block" else mbt.MBT_PC_NORMAL_EQ
-    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=code, restart=50, tol=1e-10)
+    flags = mbt.MBT_FLAG_CGS2 if orth == "cgs2" else 0
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=code, restart=50, tol=1e-10, flags=flags)
     Y, iters, st = mbt.mbt_port_admittance(ctx, a, 1.0, None, opts)
     sysm = og.PreconditionedSystem(cfg1_oracle.Z, lat, dip, pc)
-    _, res = og.gmres_all(sysm, mom.excitation(lat, dip), restart=50, tol=1e-10)
+    _, res = og.gmres_all(sysm, mom.excitation(lat, dip), restart=50, tol=1e-10, orth=orth)
     mism = [(j, int(iters[j]), res[j].iters) for j in range(len(res)) if not _iteration_parity(int(iters[j]), res[j])]
     assert not mism, mism
     err = np.linalg.norm(Y - cfg1_oracle.Yp) / np.linalg.norm(cfg1_oracle.Yp)
