@@ -251,6 +251,164 @@ __global__ __launch_bounds__(kNT) void fft_inv_crop_kernel(const cplx<T>* __rest
     }
 }
 
+// ------------------------------------------------------------------ register-resident FP32 transforms
+// Radix-2 decimation-in-time FFT of length L held in one thread's registers
+// (all indices compile-time).  tw is the table of the 2L-point grid, so
+// W_len^k = tw[k * 2L / len]; the inverse uses conjugated twiddles (unscaled).
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void fft_reg(cplx<T> (&v)[L], const cplx<T>* __restrict__ tw) {
+    using C = cplx<T>;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        int j = 0;
+#pragma unroll
+        for (int b = 0; (1 << b) < L; ++b)
+            if (i & (1 << b)) j |= (L >> 1) >> b;
+        if (i < j) {
+            const C t = v[i];
+            v[i] = v[j];
+            v[j] = t;
+        }
+    }
+#pragma unroll
+    for (int len = 2; len <= L; len <<= 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            C wk = mk<T>(1, 0);
+            if (k) {
+                wk = tw[k * (2 * L / len)];
+                if (INV) wk.y = -wk.y;
+            }
+#pragma unroll
+            for (int st = 0; st < L; st += len) {
+                const C a = v[st + k];
+                const C b = k ? cmul(v[st + k + half], wk) : v[st + k + half];
+                v[st + k] = cadd(a, b);
+                v[st + k + half] = csub(a, b);
+            }
+        }
+    }
+}
+
+// Zero-padded forward transform with the sub-transforms in registers.  A
+// workgroup owns W adjacent columns.  Phase 1: thread (row iy, column w)
+// transforms its row for both x-parities (the row data is shared; the parity
+// only twiddles the input).  The row spectra pass through one LDS tile.
+// Phase 2: thread (bin b, column w) transforms its column for both
+// y-parities and writes the four parity bins.  Two LDS round trips per block.
+template <int LX, int LY, int W>
+__global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_fwd_reg_kernel(const float2* __restrict__ X,
+                                                                              float2* __restrict__ Xh, int nx, int ny,
+                                                                              int64_t B, const float2* __restrict__ twx,
+                                                                              const float2* __restrict__ twy) {
+    using C = float2;
+    constexpr int PX = 2 * LX;
+    // rows of the tile are padded by one W-slot so that the rows that one
+    // half-wave touches at once fall on different LDS banks
+    constexpr int RS = LX * W + W;
+    __shared__ C tile[LY * RS];
+    const int w = threadIdx.x % W, r = threadIdx.x / W;
+    const int64_t c = (int64_t)blockIdx.x * W + w;
+    const bool cv = c < B;
+    C row[LX];
+    if (r < LY) {
+#pragma unroll
+        for (int ix = 0; ix < LX; ++ix)
+            row[ix] = (cv && r < ny && ix < nx) ? X[(int64_t)(r * nx + ix) * B + c] : mk<float>(0, 0);
+    }
+#pragma unroll
+    for (int be = 0; be < 2; ++be) {
+        if (r < LY) {
+            C f[LX];
+#pragma unroll
+            for (int ix = 0; ix < LX; ++ix) f[ix] = (be && ix) ? cmul(row[ix], twx[ix]) : row[ix];
+            fft_reg<float, LX, false>(f, twx);
+#pragma unroll
+            for (int b = 0; b < LX; ++b) tile[r * RS + b * W + w] = f[b];
+        }
+        __syncthreads();
+        if (r < LX) {
+#pragma unroll
+            for (int al = 0; al < 2; ++al) {
+                // the column is read from LDS once per y-parity: holding it in
+                // registers beside the row would exceed the register budget
+                C g[LY];
+#pragma unroll
+                for (int iy = 0; iy < LY; ++iy) {
+                    const C t = tile[iy * RS + r * W + w];
+                    g[iy] = (al && iy) ? cmul(t, twy[iy]) : t;
+                }
+                fft_reg<float, LY, false>(g, twy);
+                if (cv) {
+#pragma unroll
+                    for (int a = 0; a < LY; ++a) Xh[((int64_t)(2 * a + al) * PX + (2 * r + be)) * B + c] = g[a];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Cropped inverse with the sub-transforms in registers (mirror of the forward).
+// Phase A: thread (bin b, column w) inverse-transforms the two y-parity
+// columns of bin b and sums them with their twiddles.  Phase B: thread (row iy,
+// column w) inverse-transforms the row and accumulates the x-parity with its
+// twiddle; only rows iy < ny and columns ix < nx are written.
+template <int LX, int LY, int W>
+__global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_inv_reg_kernel(const float2* __restrict__ Yh,
+                                                                              float2* __restrict__ Y, int nx, int ny,
+                                                                              int64_t B, const float2* __restrict__ twx,
+                                                                              const float2* __restrict__ twy) {
+    using C = float2;
+    constexpr int PX = 2 * LX;
+    // rows of the tile are padded by one W-slot so that the rows that one
+    // half-wave touches at once fall on different LDS banks
+    constexpr int RS = LX * W + W;
+    __shared__ C tile[LY * RS];
+    const int w = threadIdx.x % W, r = threadIdx.x / W;
+    const int64_t c = (int64_t)blockIdx.x * W + w;
+    const bool cv = c < B;
+    C out[LX];
+#pragma unroll
+    for (int ix = 0; ix < LX; ++ix) out[ix] = mk<float>(0, 0);
+#pragma unroll
+    for (int be = 0; be < 2; ++be) {
+        if (r < LX) {
+            C acc[LY];
+#pragma unroll
+            for (int iy = 0; iy < LY; ++iy) acc[iy] = mk<float>(0, 0);
+#pragma unroll
+            for (int al = 0; al < 2; ++al) {
+                C g[LY];
+#pragma unroll
+                for (int a = 0; a < LY; ++a)
+                    g[a] = cv ? Yh[((int64_t)(2 * a + al) * PX + (2 * r + be)) * B + c] : mk<float>(0, 0);
+                fft_reg<float, LY, true>(g, twy);
+#pragma unroll
+                for (int iy = 0; iy < LY; ++iy) acc[iy] = cadd(acc[iy], (al && iy) ? cmul(g[iy], cconj(twy[iy])) : g[iy]);
+            }
+#pragma unroll
+            for (int iy = 0; iy < LY; ++iy) tile[iy * RS + r * W + w] = acc[iy];
+        }
+        __syncthreads();
+        if (r < LY) {
+            C h[LX];
+#pragma unroll
+            for (int b = 0; b < LX; ++b) h[b] = tile[r * RS + b * W + w];
+            fft_reg<float, LX, true>(h, twx);
+#pragma unroll
+            for (int ix = 0; ix < LX; ++ix) out[ix] = cadd(out[ix], (be && ix) ? cmul(h[ix], cconj(twx[ix])) : h[ix]);
+        }
+        __syncthreads();
+    }
+    if (cv && r < ny) {
+#pragma unroll
+        for (int ix = 0; ix < LX; ++ix)
+            if (ix < nx) Y[(int64_t)(r * nx + ix) * B + c] = out[ix];
+    }
+}
+
 // ------------------------------------------------------------------ twiddles and block spectra
 __global__ void twiddle_kernel(int P, double2* tw) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,6 +477,17 @@ void launch_fft_t(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, con
     constexpr int W = tile_w<T>(LX, LY);
     const int64_t blocks = (B + W - 1) / W;
     MBT_REQUIRE(blocks < (1LL << 31), "fft: batch too large");
+    if constexpr (sizeof(T) == 4 && LX <= 32 && LY <= 32) {
+        constexpr int NT = (LX > LY ? LX : LY) * W;
+        if (FWD)
+            hipLaunchKernelGGL((fft_fwd_reg_kernel<LX, LY, W>), dim3((unsigned)blocks), dim3(NT), 0, s, in, out, g.nx,
+                               g.ny, B, twx, twy);
+        else
+            hipLaunchKernelGGL((fft_inv_reg_kernel<LX, LY, W>), dim3((unsigned)blocks), dim3(NT), 0, s, in, out, g.nx,
+                               g.ny, B, twx, twy);
+        MBT_LAUNCH_CHECK();
+        return;
+    }
     if (FWD)
         hipLaunchKernelGGL((fft_fwd_pad_kernel<T, LX, LY, W>), dim3((unsigned)blocks), dim3(kNT), 0, s, in, out,
                            g.nx, g.ny, B, twx, twy);
