@@ -384,21 +384,16 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_update_kernel(const TB* __restr
 }
 
 // Per-RHS bookkeeping of DCGS2 step k (red: reduced [s, z, alpha, beta]):
-// completes Hessenberg column k-1 (raw and rotated), Givens, convergence; then
-// the coefficients of the update sweep and the first projection of column k.
+// completes Hessenberg column k-1 (raw and rotated), Givens, convergence.
+// inv_nu[r] = 1/nu for a RHS that takes another step, 0 for one that stops.
 __global__ void dcgs2_finalize_kernel(GmresState st, double2* __restrict__ Hraw, const double2* __restrict__ red,
-                                      int R, int k, int m, double2* __restrict__ cs_out, double2* __restrict__ cc_out,
-                                      double* __restrict__ inv_nu) {
+                                      int R, int k, int m, double* __restrict__ inv_nu) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
     const int64_t ldH = (int64_t)(m + 1) * R;
     auto RED = [&](int i) { return red[(int64_t)i * R + r]; };
     if (!st.active[r]) {
         inv_nu[r] = 0.0;
-        for (int i = 0; i <= k; ++i) {
-            if (i < k) cs_out[(int64_t)i * R + r] = make_double2(0, 0);
-            cc_out[(int64_t)i * R + r] = make_double2(0, 0);
-        }
         return;
     }
     double ss = 0;
@@ -458,35 +453,44 @@ __global__ void dcgs2_finalize_kernel(GmresState st, double2* __restrict__ Hraw,
     if (stop || k == m || nu == 0.0) {
         st.active[r] = 0;
         inv_nu[r] = 0.0;
-        for (int i = 0; i <= k; ++i) {
-            if (i < k) cs_out[(int64_t)i * R + r] = make_double2(0, 0);
-            cc_out[(int64_t)i * R + r] = make_double2(0, 0);
-        }
         return;
     }
-    // t = Hbar_{k-1} s (rows 0..k), h = projections of A v_k, c = t/nu + h
-    const double in = 1.0 / nu;
-    double2 sz = make_double2(0, 0);
-    for (int i = 0; i < k; ++i) sz = cadd(sz, cmulc(RED(i), RED(k + i)));
-    const double2 bet = RED(2 * k + 1);
-    double2* Hk = Hraw + (int64_t)k * ldH;
-    for (int i = 0; i <= k; ++i) {
-        double2 t = make_double2(0, 0);
-        for (int l = (i > 0 ? i - 1 : 0); l < k; ++l)   // Hbar is upper Hessenberg: H[i][l] = 0 for l < i-1
-            t = cadd(t, cmul(Hraw[(int64_t)l * ldH + (int64_t)i * R + r], RED(l)));
-        double2 h;
-        if (i < k) {
-            const double2 d = csub(RED(k + i), t);
-            h = make_double2(d.x * in, d.y * in);
-        } else {
-            const double2 q = csub(bet, sz);
-            h = make_double2((q.x * in - t.x) * in, (q.y * in - t.y) * in);
-        }
-        Hk[(int64_t)i * R + r] = h;
-        cc_out[(int64_t)i * R + r] = make_double2(t.x * in + h.x, t.y * in + h.y);
-        if (i < k) cs_out[(int64_t)i * R + r] = RED(i);
+    inv_nu[r] = 1.0 / nu;
+}
+
+// Coefficients of the DCGS2 update sweep of step k, one thread per (row i, RHS r):
+// t = Hbar_{k-1} s (rows 0..k), h = projections of A v_k (raw column k of H),
+// c = t/nu + h; the coefficients of a RHS that stops are zero.
+__global__ void dcgs2_coef_kernel(double2* __restrict__ Hraw, const double2* __restrict__ red, int R, int k, int m,
+                                  const double* __restrict__ inv_nu, double2* __restrict__ cs_out,
+                                  double2* __restrict__ cc_out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (r >= R) return;
+    const double in = inv_nu[r];
+    if (in == 0.0) {
+        if (i < k) cs_out[(int64_t)i * R + r] = make_double2(0, 0);
+        cc_out[(int64_t)i * R + r] = make_double2(0, 0);
+        return;
     }
-    inv_nu[r] = in;
+    const int64_t ldH = (int64_t)(m + 1) * R;
+    auto RED = [&](int j) { return red[(int64_t)j * R + r]; };
+    double2 t = make_double2(0, 0);
+    for (int l = (i > 0 ? i - 1 : 0); l < k; ++l)   // Hbar is upper Hessenberg: H[i][l] = 0 for l < i-1
+        t = cadd(t, cmul(Hraw[(int64_t)l * ldH + (int64_t)i * R + r], RED(l)));
+    double2 h;
+    if (i < k) {
+        const double2 d = csub(RED(k + i), t);
+        h = make_double2(d.x * in, d.y * in);
+        cs_out[(int64_t)i * R + r] = RED(i);
+    } else {
+        double2 sz = make_double2(0, 0);
+        for (int l = 0; l < k; ++l) sz = cadd(sz, cmulc(RED(l), RED(k + l)));
+        const double2 q = csub(RED(2 * k + 1), sz);
+        h = make_double2((q.x * in - t.x) * in, (q.y * in - t.y) * in);
+    }
+    Hraw[(int64_t)k * ldH + (int64_t)i * R + r] = h;
+    cc_out[(int64_t)i * R + r] = make_double2(t.x * in + h.x, t.y * in + h.y);
 }
 
 template <typename TB, int RPL, bool HASW>
@@ -802,6 +806,7 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     const int m = prm.restart;
     MBT_REQUIRE(m >= 1 && m + 1 <= kMaxVec, "gmres: restart must be in 1..63");
     const int64_t rpc = gmres_rows_per_chunk(N);
+    const size_t arena_mark = arena.off;   // the recurrence state is released on return
     const int nchunk = gmres_nchunk(N);
     const int64_t vs = N * R;   // basis vector stride
 
@@ -887,10 +892,13 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
             const int nred = 2 * k + 2;
             hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nred * R + 255) / 256)), bR, 0, s,
                                partial, nchunk, nred, R, red);
-            hipLaunchKernelGGL(dcgs2_finalize_kernel, gR, bR, 0, s, st, Hraw, red, R, k, m, coef_s, coef_c, inv_nu);
+            hipLaunchKernelGGL(dcgs2_finalize_kernel, gR, bR, 0, s, st, Hraw, red, R, k, m, inv_nu);
             MBT_LAUNCH_CHECK();
             steps = k;
             if (k == m || count_active() == 0) break;
+            hipLaunchKernelGGL(dcgs2_coef_kernel, dim3((R + 255) / 256, k + 1), bR, 0, s, Hraw, red, R, k, m, inv_nu,
+                               coef_s, coef_c);
+            MBT_LAUNCH_CHECK();
             {
                 ProfScope ps(kKArnoldiUpdateDots, (k + 2) * vbytes + 2 * vbytes, 16.0 * k * vs, s);
                 launch_dcgs2_update<TB>(Vbasis, vs, k, u, w, coef_s, coef_c, inv_nu, N, R, rpc, nchunk, s);
@@ -952,6 +960,7 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     MBT_HIP(hipMemcpyAsync(res.conv.data(), st.conv, sizeof(int) * R, hipMemcpyDeviceToHost, s));
     MBT_HIP(hipMemcpyAsync(res.flag.data(), st.flag, sizeof(int) * R, hipMemcpyDeviceToHost, s));
     MBT_HIP(hipStreamSynchronize(s));
+    arena.off = arena_mark;
     return res;
 }
 

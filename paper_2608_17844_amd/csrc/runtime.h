@@ -56,15 +56,22 @@ struct OpData {
     }
 };
 
-// A stream with its own workspace; the context has one, each server slot another.
+// A stream with its own persistent device buffers; the context has one, each
+// server slot another.  ws holds the solve workspace, xs the extraction
+// buffers; both only grow (a grown buffer is reused by later calls, so steady
+// state issues no device allocation or free).
 struct Worker {
     int device = 0;
     hipStream_t stream = nullptr;
-    DBuf ws;
+    DBuf ws, xs;
     int* host_count = nullptr;   // pinned
     explicit Worker(int dev);
     ~Worker();
     void ensure(size_t bytes);
+    void ensure_x(size_t bytes);
+    size_t held() const { return ws.bytes + xs.bytes; }
+    // size a buffer grows to when `need` bytes are requested
+    static size_t grown(size_t have, size_t need) { return have >= need ? have : need + (need >> 4); }
 };
 
 struct SolveOut {
@@ -99,12 +106,25 @@ Geom make_geom(const mbt_dipole& d, const mbt_lattice& l);
 void validate_opts(const mbt_solve_opts& o);
 std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_pa, bool need32, Worker& wk);
 size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o);
-int choose_chunk(mbt_ctx* ctx, const Geom& g, int R, const mbt_solve_opts& o);
+// Largest RHS batch (<= R) whose solve workspace fits `budget` bytes.
+int choose_chunk(size_t budget, const Geom& g, int R, const mbt_solve_opts& o);
+// Device bytes of the extraction buffers of one frequency (Y_p, Z_p, S, work, scans).
+size_t extract_bytes(int P, int nscan);
 // Solves Z X = V for R device columns (layout [n][r]); X receives FP64 currents.
 SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, int R, double2* X, Worker& wk,
                    DevArena& arena);
 // All-port solve for one frequency; Ydev (P x nports column-major) filled on the device.
 SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t* ports, int nports,
-                    const mbt_solve_opts& o, double2* Ydev, Worker& wk, mbt_stats* st);
+                    const mbt_solve_opts& o, double2* Ydev, Worker& wk, mbt_stats* st, size_t budget);
+// The whole path for one frequency on worker wk: all-port solve, Z_p = Y_p^{-1},
+// S and the center-element scan quantities; outputs are host arrays (any may
+// be NULL except when nscan > 0, where Za and Gamma are required).
+SolveOut solve_frequency(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_solve_opts& o, size_t budget,
+                         const double* theta, const double* phi, int nscan, double z0, double* Zp, double* Za,
+                         double* Gamma, double* Gamma_wave, Worker& wk, mbt_stats* st);
+// Status of a finished solve (MBT_OK, MBT_ENOCONV or MBT_EBREAKDOWN).
+int solve_status(const SolveOut& so);
+// Sets the calling thread's message returned by mbt_last_error.
+void set_last_error(const std::string& m);
 
 }  // namespace mbt

@@ -27,6 +27,8 @@ double now_s() {
 
 }  // namespace
 
+void mbt::set_last_error(const std::string& m) { g_err = m; }
+
 #define API_BEGIN \
     g_err.clear(); \
     try {
@@ -59,7 +61,13 @@ Worker::~Worker() {
 void Worker::ensure(size_t bytes) {
     if (ws.bytes >= bytes) return;
     MBT_HIP(hipStreamSynchronize(stream));
-    ws.alloc(bytes + (bytes >> 4));
+    ws.alloc(grown(0, bytes));
+}
+
+void Worker::ensure_x(size_t bytes) {
+    if (xs.bytes >= bytes) return;
+    MBT_HIP(hipStreamSynchronize(stream));
+    xs.alloc(grown(0, bytes));
 }
 
 // ------------------------------------------------------------------ geometry and options
@@ -350,12 +358,24 @@ size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o) {
     return b;
 }
 
-int choose_chunk(mbt_ctx* ctx, const Geom& g, int R, const mbt_solve_opts& o) {
+int choose_chunk(size_t budget, const Geom& g, int R, const mbt_solve_opts& o) {
     if (o.rhs_chunk > 0) return std::min(R, o.rhs_chunk);
     int c = R;
-    while (c > 1 && solve_bytes(g, c, o) > ctx->budget) c = (c + 1) / 2;
-    if (solve_bytes(g, c, o) > ctx->budget) throw Error(-2, "one right-hand side does not fit the device-memory budget");
+    while (c > 1 && solve_bytes(g, c, o) > budget) c = (c + 1) / 2;
+    if (solve_bytes(g, c, o) > budget) throw Error(-2, "one right-hand side does not fit the device-memory budget");
     return c;
+}
+
+size_t extract_bytes(int P, int nscan) {
+    const size_t ns = (size_t)std::max(nscan, 1);
+    return 4 * sizeof(double2) * (size_t)P * P + sizeof(double2) * P + sizeof(int) * ((size_t)P + 8) +
+           sizeof(double) * 2 * ns + sizeof(double2) * 3 * ns + 1024;
+}
+
+int solve_status(const SolveOut& so) {
+    if (so.nflag > 0) return MBT_EBREAKDOWN;
+    if (so.nconv < (int)so.iters.size()) return MBT_ENOCONV;
+    return MBT_OK;
 }
 
 static void norms_host(const double2* X, int64_t N, int R, DevArena& arena, std::vector<double>& out, hipStream_t s) {
@@ -483,7 +503,7 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
 }
 
 SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t* ports, int nports,
-                    const mbt_solve_opts& o, double2* Ydev, Worker& wk, mbt_stats* st) {
+                    const mbt_solve_opts& o, double2* Ydev, Worker& wk, mbt_stats* st, size_t budget) {
     const Geom& g = arr->g;
     const double t0 = now_s();
     std::shared_ptr<OpData> op;
@@ -496,7 +516,7 @@ SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t*
     }
     MBT_HIP(hipStreamSynchronize(wk.stream));
     const double t1 = now_s();
-    const int chunk = choose_chunk(ctx, g, nports, o);
+    const int chunk = choose_chunk(budget, g, nports, o);
     const size_t need = solve_bytes(g, chunk, o) + sizeof(int32_t) * nports + 4096;
     wk.ensure(need);
     DevArena arena;
@@ -543,14 +563,60 @@ SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t*
     return total;
 }
 
+SolveOut solve_frequency(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_solve_opts& o, size_t budget,
+                         const double* theta, const double* phi, int nscan, double z0, double* Zp, double* Za,
+                         double* Gamma, double* Gamma_wave, Worker& wk, mbt_stats* st) {
+    const Geom& g = arr->g;
+    const int P = g.P;
+    const int64_t PP = (int64_t)P * P;
+    std::vector<int32_t> pl(P);
+    for (int i = 0; i < P; ++i) pl[i] = i;
+    // extraction buffers from the worker's persistent area, carved in order:
+    // Y_p, Z_p, S, work (P x P each), a column, pivots + flag, scan angles, scan outputs
+    wk.ensure_x(extract_bytes(P, nscan));
+    const int ns = std::max(nscan, 1);
+    double2* Yd = wk.xs.as<double2>();
+    double2* Zd = Yd + PP;
+    double2* Sd = Zd + PP;
+    double2* Wd = Sd + PP;
+    double2* colbuf = Wd + PP;
+    int* piv = (int*)(colbuf + P);
+    int* flag = piv + P;
+    double* dth = (double*)(((uintptr_t)(flag + 8) + 255) & ~(uintptr_t)255);
+    double* dph = dth + ns;
+    double2* dout = (double2*)(dph + ns);
+    MBT_REQUIRE((char*)(dout + 3 * ns) <= wk.xs.as<char>() + wk.xs.bytes, "extraction buffer overflow");
+    SolveOut so = admittance(ctx, arr, s, pl.data(), P, o, Yd, wk, st, budget);
+    const double t0 = now_s();
+    hipStream_t str = wk.stream;
+    gj_inverse(Yd, Zd, P, colbuf, piv, flag, str);
+    if (nscan > 0) {
+        if (Gamma_wave) s_matrix(Zd, Sd, Wd, P, z0, colbuf, piv, flag, str);
+        MBT_HIP(hipMemcpyAsync(dth, theta, sizeof(double) * nscan, hipMemcpyHostToDevice, str));
+        MBT_HIP(hipMemcpyAsync(dph, phi, sizeof(double) * nscan, hipMemcpyHostToDevice, str));
+        const int c = (g.ny / 2) * g.nx + g.nx / 2;
+        scans(g, 2.0 * M_PI * s, Zd, Gamma_wave ? Sd : nullptr, c, dth, dph, nscan, z0, dout, dout + nscan,
+              Gamma_wave ? dout + 2 * nscan : nullptr, str);
+        MBT_HIP(hipMemcpyAsync(Za, dout, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
+        MBT_HIP(hipMemcpyAsync(Gamma, dout + nscan, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
+        if (Gamma_wave)
+            MBT_HIP(hipMemcpyAsync(Gamma_wave, dout + 2 * nscan, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
+    }
+    if (Zp) MBT_HIP(hipMemcpyAsync(Zp, Zd, sizeof(double2) * PP, hipMemcpyDeviceToHost, str));
+    MBT_HIP(hipStreamSynchronize(str));
+    if (st) st->t_extract = now_s() - t0;
+    return so;
+}
+
 }  // namespace mbt
 
 // ================================================================== C ABI
 namespace {
 
 mbt_status finish_status(const SolveOut& so) {
-    if (so.nflag > 0) return set_err(MBT_EBREAKDOWN, "non-finite value in the Krylov recurrence for some right-hand sides");
-    if (so.nconv < (int)so.iters.size()) return set_err(MBT_ENOCONV, "some right-hand sides did not converge");
+    const int code = solve_status(so);
+    if (code == MBT_EBREAKDOWN) return set_err(code, "non-finite value in the Krylov recurrence for some right-hand sides");
+    if (code == MBT_ENOCONV) return set_err(code, "some right-hand sides did not converge");
     return MBT_OK;
 }
 
@@ -669,7 +735,7 @@ mbt_status mbt_port_admittance(mbt_ctx* ctx, const mbt_array* arr, double s, con
     const int np = (int)pl.size();
     DBuf Yd;
     Yd.alloc(sizeof(double2) * arr->g.P * np);
-    SolveOut so = admittance(ctx, arr, s, pl.data(), np, *opts, Yd.as<double2>(), *ctx->main, st);
+    SolveOut so = admittance(ctx, arr, s, pl.data(), np, *opts, Yd.as<double2>(), *ctx->main, st, ctx->budget);
     MBT_HIP(hipMemcpy(Y, Yd.p, sizeof(double2) * arr->g.P * np, hipMemcpyDeviceToHost));
     if (iters) std::copy(so.iters.begin(), so.iters.end(), iters);
     return finish_status(so);
@@ -693,7 +759,8 @@ mbt_status mbt_port_admittance_dev(mbt_ctx* ctx, const mbt_array* arr, double s,
         MBT_HIP(hipStreamWaitEvent(ctx->main->stream, ev, 0));
         MBT_HIP(hipEventDestroy(ev));
     }
-    SolveOut so = admittance(ctx, arr, s, pl.data(), (int)pl.size(), *opts, (double2*)Ydev, *ctx->main, st);
+    SolveOut so = admittance(ctx, arr, s, pl.data(), (int)pl.size(), *opts, (double2*)Ydev, *ctx->main, st,
+                             ctx->budget);
     if (iters) std::copy(so.iters.begin(), so.iters.end(), iters);
     return finish_status(so);
     API_END
@@ -708,42 +775,8 @@ static mbt_status solve_impl(mbt_ctx* ctx, const mbt_array* arr, double s, const
     MBT_REQUIRE(s > 0 && std::isfinite(s), "freq_ratio must be positive");
     MBT_REQUIRE(nscan >= 0 && (nscan == 0 || (theta && phi && Za && Gamma)), "scan arrays missing");
     MBT_REQUIRE(z0 > 0, "z0 must be positive");
-    const Geom& g = arr->g;
-    const int P = g.P;
-    std::vector<int32_t> pl = port_list(arr, nullptr, -1);
-    DBuf Yd, Zd, Sd, Wd, aux;
-    Yd.alloc(sizeof(double2) * P * P);
-    SolveOut so = admittance(ctx, arr, s, pl.data(), P, *opts, Yd.as<double2>(), *ctx->main, st);
-    const double t0 = now_s();
-    hipStream_t str = ctx->main->stream;
-    Zd.alloc(sizeof(double2) * P * P);
-    aux.alloc(sizeof(double2) * P + sizeof(int) * (P + 8) + sizeof(double) * 2 * std::max(nscan, 1) +
-              sizeof(double2) * 3 * std::max(nscan, 1) + 1024);
-    char* ab = aux.as<char>();
-    double2* colbuf = (double2*)ab;
-    int* piv = (int*)(ab + sizeof(double2) * P);
-    int* flag = piv + P;
-    double* dth = (double*)(((uintptr_t)(flag + 8) + 255) & ~(uintptr_t)255);
-    double* dph = dth + std::max(nscan, 1);
-    double2* dout = (double2*)(dph + std::max(nscan, 1));
-    gj_inverse(Yd.as<double2>(), Zd.as<double2>(), P, colbuf, piv, flag, str);
-    if (nscan > 0) {
-        Sd.alloc(sizeof(double2) * P * P);
-        Wd.alloc(sizeof(double2) * P * P);
-        if (Gamma_wave) s_matrix(Zd.as<double2>(), Sd.as<double2>(), Wd.as<double2>(), P, z0, colbuf, piv, flag, str);
-        MBT_HIP(hipMemcpyAsync(dth, theta, sizeof(double) * nscan, hipMemcpyHostToDevice, str));
-        MBT_HIP(hipMemcpyAsync(dph, phi, sizeof(double) * nscan, hipMemcpyHostToDevice, str));
-        const int c = (g.ny / 2) * g.nx + g.nx / 2;
-        scans(g, 2.0 * M_PI * s, Zd.as<double2>(), Gamma_wave ? Sd.as<double2>() : nullptr, c, dth, dph, nscan, z0, dout,
-              dout + nscan, Gamma_wave ? dout + 2 * nscan : nullptr, str);
-        MBT_HIP(hipMemcpyAsync(Za, dout, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
-        MBT_HIP(hipMemcpyAsync(Gamma, dout + nscan, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
-        if (Gamma_wave)
-            MBT_HIP(hipMemcpyAsync(Gamma_wave, dout + 2 * nscan, sizeof(double2) * nscan, hipMemcpyDeviceToHost, str));
-    }
-    if (Zp) MBT_HIP(hipMemcpyAsync(Zp, Zd.p, sizeof(double2) * P * P, hipMemcpyDeviceToHost, str));
-    MBT_HIP(hipStreamSynchronize(str));
-    if (st) st->t_extract = now_s() - t0;
+    SolveOut so = solve_frequency(ctx, arr, s, *opts, ctx->budget, theta, phi, nscan, z0, Zp, Za, Gamma, Gamma_wave,
+                                  *ctx->main, st);
     return finish_status(so);
 }
 

@@ -290,6 +290,61 @@ def mbt_active(ctx: int, arr: int, freq_ratio: float, Zp: np.ndarray, theta, phi
     return Za, G, Gw
 
 
+# ------------------------------------------------------------------ serving
+
+def mbt_server_create(ctx: int, max_inflight: int = 4, hbm_budget_bytes: int = 0) -> int:
+    h = _vp()
+    _check(lib().mbt_server_create(ctx, max_inflight, hbm_budget_bytes, ctypes.byref(h)))
+    return h.value
+
+
+def mbt_server_submit(srv: int, dipole, lattice, freq_ratio, theta, phi, opts: mbt_solve_opts,
+                      z0: float = 50.0) -> int:
+    f = np.ascontiguousarray(np.atleast_1d(freq_ratio), dtype=np.float64)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    d = mbt_dipole(*dipole) if not isinstance(dipole, mbt_dipole) else dipole
+    la = mbt_lattice(*lattice) if not isinstance(lattice, mbt_lattice) else lattice
+    req = mbt_request(elem=d, lat=la, nfreq=f.size, freq_ratio=_cd(f), nscan=th.size,
+                      theta=_cd(th) if th.size else None, phi=_cd(ph) if th.size else None, z0=z0, opts=opts)
+    t = ctypes.c_uint64()
+    _check(lib().mbt_server_submit(srv, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def mbt_server_wait(srv: int, ticket: int, timeout_ms: int = -1) -> Optional[dict]:
+    """Result of `ticket` as numpy copies (None on MBT_ETIMEOUT); the library result is freed."""
+    rp = ctypes.POINTER(mbt_result)()
+    st = _check(lib().mbt_server_wait(srv, ticket, timeout_ms, ctypes.byref(rp)), (MBT_OK, MBT_ETIMEOUT))
+    if st == MBT_ETIMEOUT:
+        return None
+    try:
+        r = rp.contents
+        nf, P, ns = r.nfreq, r.nports, r.nscan
+
+        def cplx(ptr, n):
+            return np.ctypeslib.as_array(ptr, shape=(2 * n,)).copy().view(np.complex128)
+
+        out = {"status": r.status, "nfreq": nf, "nports": P, "nscan": ns,
+               "Zp": cplx(r.Zp, nf * P * P).reshape(nf, P, P).transpose(0, 2, 1),
+               "Za": cplx(r.Za, nf * ns).reshape(nf, ns) if ns else np.zeros((nf, 0), np.complex128),
+               "Gamma": cplx(r.Gamma, nf * ns).reshape(nf, ns) if ns else np.zeros((nf, 0), np.complex128),
+               "Gamma_wave": cplx(r.Gamma_wave, nf * ns).reshape(nf, ns) if ns else np.zeros((nf, 0), np.complex128),
+               "iters_max": np.ctypeslib.as_array(r.iters_max, shape=(nf,)).copy(),
+               "t_submit": r.t_submit, "t_start": r.t_start, "t_done": r.t_done}
+    finally:
+        lib().mbt_result_free(rp)
+    return out
+
+
+def mbt_server_clock(srv: int) -> float:
+    return lib().mbt_server_clock(srv)
+
+
+def mbt_server_destroy(srv: int) -> None:
+    lib().mbt_server_destroy(srv)
+
+
 # ------------------------------------------------------------------ test hooks
 
 def mbt_dbg_fill_blocks(ctx: int, arr: int, freq_ratio: float, lattice, nbases: int) -> np.ndarray:
