@@ -56,11 +56,15 @@ typedef enum {
 } mbt_status;
 
 /* Precision of the FFT-Toeplitz operator inside the Krylov solve.
- * MBT_FP64: everything FP64.  MBT_FP32 / MBT_BF16 / MBT_FP16: the lattice FFTs
- * and per-bin block products run in reduced precision (FP32 MFMA with FP32
- * accumulation; BF16/FP16 inputs with FP32 accumulation), the Krylov basis is
- * stored in FP32 with FP64 dot products, Givens rotations are FP64, and FP64
- * iterative refinement with an FP64 residual recovers the accuracy. */
+ * MBT_FP64: everything FP64.  MBT_FP32: the lattice FFTs and the per-bin block
+ * products run in FP32 (FP32 MFMA, FP32 accumulation).  MBT_BF16 / MBT_FP16: as
+ * MBT_FP32, but the forward FFT stores the spectrum X^ in 16-bit complex and
+ * the per-bin products take X^ and the block spectra C^ in bfloat16 / binary16
+ * on the 16x16x16 MFMA with FP32 accumulation and FP32 output.  In every
+ * reduced precision the Krylov basis is stored in FP32 with FP64 dot products,
+ * Givens rotations are FP64, the preconditioner apply is FP32, and FP64
+ * iterative refinement with an FP64 residual recovers the accuracy (inner
+ * tolerance by default 1e-4 for FP32, 1e-3 for FP16, 1e-2 for BF16). */
 typedef enum { MBT_FP64 = 0, MBT_FP32 = 1, MBT_BF16 = 2, MBT_FP16 = 3 } mbt_prec;
 
 /* Preconditioning strategy.

@@ -150,7 +150,139 @@ void launch_mp(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, 
     MBT_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------- 16-bit inputs
+// The same real formulation on the 16x16x16 MFMA with 16-bit inputs and FP32
+// accumulation.  A lane supplies four consecutive K values; with K interleaving
+// (q, re/im), K slots 4g..4g+3 of a 16-wide block are the two complex values
+// X[q0][col], X[q0+1][col] (q0 = 8s + 2g), i.e. two packed 32-bit words as they
+// sit in memory.  The A row (p, re) needs (A.re, -A.im) pairs and the row
+// (p, im) the swapped (A.im, A.re) pairs: a sign-bit flip and a half-word
+// rotation of the packed words.
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+
+template <int FMT> __device__ __forceinline__ f4 mfma16(u2 a, u2 b, f4 c) {
+    if constexpr (FMT == kFmtBf16)
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b), c, 0, 0,
+                                                         0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b), c, 0, 0, 0);
+}
+
+template <int FMT, int MP, bool HERM>
+__global__ __launch_bounds__(256) void cgemm16_kernel(const uint32_t* __restrict__ A, int64_t strideA,
+                                                      const uint32_t* __restrict__ X, float2* __restrict__ Y, int M,
+                                                      int R, int groups, int tpw, float osc) {
+    constexpr int NRT = MP / 8;   // 16-row tiles of the 2MP-row real matrix
+    constexpr int NKB = MP / 8;   // 16-wide real K blocks (8 complex q each)
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t b = blockIdx.x / groups;
+    const int grp = blockIdx.x % groups;
+    const int ntiles = (R + 15) >> 4;
+    const int t0 = (grp * 4 + wave) * tpw;
+    if (t0 >= ntiles) return;
+    const int t1 = min(t0 + tpw, ntiles);
+
+    const uint32_t* Ab = A + b * strideA;
+    const uint32_t* Xb = X + b * (int64_t)M * R;
+    float2* Yb = Y + b * (int64_t)M * R;
+    const int g = lane >> 4;
+    const int li = lane & 15;
+
+    // A fragments: row rho = 16t + li of the real matrix is (p, re/im), p = rho/2
+    u2 af[NRT][NKB];
+#pragma unroll
+    for (int t = 0; t < NRT; ++t) {
+        const int rho = 16 * t + li;
+        const int p = rho >> 1;
+        const bool odd = rho & 1;
+#pragma unroll
+        for (int s = 0; s < NKB; ++s) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = 8 * s + 2 * g + h;
+                uint32_t w = 0;
+                if (p < M && q < M) {
+                    w = HERM ? Ab[(int64_t)q * M + p] : Ab[(int64_t)p * M + q];
+                    if (HERM) w ^= 0x80000000u;   // conjugate
+                }
+                af[t][s][h] = odd ? ((w >> 16) | (w << 16)) : (w ^ 0x80000000u);
+            }
+        }
+    }
+
+    u2 bcur[NKB], bnext[NKB];
+    auto load = [&](int tile, u2* dst) {
+        const int col = tile * 16 + li;
+#pragma unroll
+        for (int s = 0; s < NKB; ++s) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = 8 * s + 2 * g + h;
+                dst[s][h] = (q < M && col < R) ? Xb[(int64_t)q * R + col] : 0u;
+            }
+        }
+    };
+    load(t0, bcur);
+    for (int tile = t0; tile < t1; ++tile) {
+        if (tile + 1 < t1) load(tile + 1, bnext);
+        f4 acc[NRT];
+#pragma unroll
+        for (int t = 0; t < NRT; ++t) acc[t] = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NKB; ++s) {
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) acc[t] = mfma16<FMT>(af[t][s], bcur[s], acc[t]);
+        }
+        const int col = tile * 16 + li;
+        if (col < R) {
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) {
+                const int p0 = 8 * t + 2 * g;
+                if (p0 < M) Yb[(int64_t)p0 * R + col] = make_float2(acc[t][0] * osc, acc[t][1] * osc);
+                if (p0 + 1 < M) Yb[(int64_t)(p0 + 1) * R + col] = make_float2(acc[t][2] * osc, acc[t][3] * osc);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NKB; ++s) bcur[s] = bnext[s];
+    }
+}
+
+template <int FMT, int MP>
+void launch16_mp(const uint32_t* A, int64_t strideA, const uint32_t* X, float2* Y, int M, int R, int64_t nbatch,
+                 int op, float osc, hipStream_t s) {
+    const int ntiles = (R + 15) / 16;
+    const int64_t total = nbatch * ntiles;
+    int tpw = (int)std::max<int64_t>(1, std::min<int64_t>(8, total / 32768));
+    tpw = std::min(tpw, ntiles);
+    const int groups = (ntiles + 4 * tpw - 1) / (4 * tpw);
+    const int64_t blocks = nbatch * groups;
+    MBT_REQUIRE(blocks < (1LL << 31), "cgemm: grid too large");
+    if (op == 0)
+        hipLaunchKernelGGL((cgemm16_kernel<FMT, MP, false>), dim3((unsigned)blocks), dim3(256), 0, s, A, strideA, X, Y,
+                           M, R, groups, tpw, osc);
+    else
+        hipLaunchKernelGGL((cgemm16_kernel<FMT, MP, true>), dim3((unsigned)blocks), dim3(256), 0, s, A, strideA, X, Y,
+                           M, R, groups, tpw, osc);
+    MBT_LAUNCH_CHECK();
+}
+
 }  // namespace
+
+template <int FMT>
+void cgemm16_batched(const uint32_t* A, int64_t strideA, const uint32_t* X, float2* Y, int M, int R, int64_t nbatch,
+                     int op, float out_scale, hipStream_t s) {
+    if (nbatch <= 0 || R <= 0) return;
+    if (M <= 16) launch16_mp<FMT, 16>(A, strideA, X, Y, M, R, nbatch, op, out_scale, s);
+    else if (M <= 32) launch16_mp<FMT, 32>(A, strideA, X, Y, M, R, nbatch, op, out_scale, s);
+    else throw Error(-1, "cgemm: block size above 32 is not supported");
+}
+template void cgemm16_batched<kFmtBf16>(const uint32_t*, int64_t, const uint32_t*, float2*, int, int, int64_t, int,
+                                        float, hipStream_t);
+template void cgemm16_batched<kFmtF16>(const uint32_t*, int64_t, const uint32_t*, float2*, int, int, int64_t, int,
+                                       float, hipStream_t);
 
 template <typename T>
 void cgemm_batched(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R, int64_t nbatch,

@@ -53,6 +53,36 @@ template <> __host__ __device__ __forceinline__ float2 from_d2<float2>(double2 a
     return make_float2((float)a.x, (float)a.y);
 }
 
+// ------------------------------------------------------------------ 16-bit complex storage
+// A complex value kept as two 16-bit floats in one 32-bit word, real part in
+// the low half.  kFmtBf16: bfloat16 (8-bit exponent, 7-bit mantissa);
+// kFmtF16: IEEE binary16.  Conversions round to nearest even.
+enum : int { kFmtNone = -1, kFmtBf16 = 0, kFmtF16 = 1 };
+
+template <int FMT> __device__ __forceinline__ uint32_t f32_to_16(float f) {
+    if constexpr (FMT == kFmtBf16) {
+        const uint32_t u = __float_as_uint(f);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // NaN stays NaN
+        return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    } else {
+        const _Float16 h = (_Float16)f;
+        return (uint32_t)__builtin_bit_cast(uint16_t, h);
+    }
+}
+template <int FMT> __device__ __forceinline__ float f16_to_32(uint32_t h) {
+    if constexpr (FMT == kFmtBf16) {
+        return __uint_as_float(h << 16);
+    } else {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+    }
+}
+template <int FMT> __device__ __forceinline__ uint32_t pack16(float2 v) {
+    return f32_to_16<FMT>(v.x) | (f32_to_16<FMT>(v.y) << 16);
+}
+template <int FMT> __device__ __forceinline__ float2 unpack16(uint32_t w) {
+    return make_float2(f16_to_32<FMT>(w & 0xffffu), f16_to_32<FMT>(w >> 16));
+}
+
 // ------------------------------------------------------------------ errors
 struct Error : std::runtime_error {
     int code;
@@ -132,11 +162,24 @@ template <typename T>
 void fft_inv_crop(const Geom& g, const cplx<T>* Yh, cplx<T>* Y, int64_t B, const cplx<T>* twx,
                   const cplx<T>* twy, hipStream_t s);
 
+// Forward lattice FFT with the spectrum stored in 16-bit complex (FMT); the
+// transform itself runs in FP32.  scratch (bins*B float2) is used on grids whose
+// sub-transforms do not fit the register kernels.
+template <int FMT>
+void fft_fwd_pad16(const Geom& g, const float2* X, uint32_t* Xh, int64_t B, const float2* twx, const float2* twy,
+                   float2* scratch, hipStream_t s);
+
 // cgemm.hip: Y_b = op(A_b) X_b for b < nbatch; A_b = A + b*strideA (M x M row-major complex),
 // X_b / Y_b = X/Y + b*M*R (M x R row-major).  op: 0 = A, 1 = A^H.
 template <typename T>
 void cgemm_batched(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R,
                    int64_t nbatch, int op, hipStream_t s);
+
+// Same with A and X in 16-bit complex (FMT), FP32 accumulation and FP32 Y.
+// A holds a scaled copy (scale * A_b): Y is multiplied by out_scale = 1/scale.
+template <int FMT>
+void cgemm16_batched(const uint32_t* A, int64_t strideA, const uint32_t* X, float2* Y, int M, int R, int64_t nbatch,
+                     int op, float out_scale, hipStream_t s);
 
 // precond.hip
 void gram_blocks(const Geom& g, const double2* T, double2* G, hipStream_t s);            // G[d] = T[d]^H T[d]
@@ -159,5 +202,8 @@ void gather_ports(const Geom& g, const double2* I, int R, double2* Y, hipStream_
 void transpose_nr(const double2* src, double2* dst, int64_t N, int R, bool to_device_layout, hipStream_t s);
 void scale_columns_d(double2* X, const double* scale, int64_t N, int R, hipStream_t s);      // X[n][r] *= scale[r]
 void zero_d(double2* p, int64_t n, hipStream_t s);                                             // fill kernel, no memset
+template <int FMT>
+void pack16_d(const double2* src, uint32_t* dst, int64_t n, double scale, hipStream_t s);     // 16-bit of scale*src
+void max_abs_d(const double2* src, int64_t n, double* out, hipStream_t s);                    // max |re|, |im| -> out[0]
 
 }  // namespace mbt

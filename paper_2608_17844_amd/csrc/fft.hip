@@ -297,9 +297,10 @@ __device__ __forceinline__ void fft_reg(cplx<T> (&v)[L], const cplx<T>* __restri
 // only twiddles the input).  The row spectra pass through one LDS tile.
 // Phase 2: thread (bin b, column w) transforms its column for both
 // y-parities and writes the four parity bins.  Two LDS round trips per block.
-template <int LX, int LY, int W>
+// FMT selects the spectrum's storage: FP32 complex, or 16-bit complex words.
+template <int LX, int LY, int W, int FMT>
 __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_fwd_reg_kernel(const float2* __restrict__ X,
-                                                                              float2* __restrict__ Xh, int nx, int ny,
+                                                                              void* __restrict__ Xh_, int nx, int ny,
                                                                               int64_t B, const float2* __restrict__ twx,
                                                                               const float2* __restrict__ twy) {
     using C = float2;
@@ -342,7 +343,13 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_fwd_reg_kernel(co
                 fft_reg<float, LY, false>(g, twy);
                 if (cv) {
 #pragma unroll
-                    for (int a = 0; a < LY; ++a) Xh[((int64_t)(2 * a + al) * PX + (2 * r + be)) * B + c] = g[a];
+                    for (int a = 0; a < LY; ++a) {
+                        const int64_t o = ((int64_t)(2 * a + al) * PX + (2 * r + be)) * B + c;
+                        if constexpr (FMT == kFmtNone)
+                            static_cast<float2*>(Xh_)[o] = g[a];
+                        else
+                            static_cast<uint32_t*>(Xh_)[o] = pack16<FMT>(g[a]);
+                    }
                 }
             }
         }
@@ -480,8 +487,8 @@ void launch_fft_t(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, con
     if constexpr (sizeof(T) == 4 && LX <= 32 && LY <= 32) {
         constexpr int NT = (LX > LY ? LX : LY) * W;
         if (FWD)
-            hipLaunchKernelGGL((fft_fwd_reg_kernel<LX, LY, W>), dim3((unsigned)blocks), dim3(NT), 0, s, in, out, g.nx,
-                               g.ny, B, twx, twy);
+            hipLaunchKernelGGL((fft_fwd_reg_kernel<LX, LY, W, kFmtNone>), dim3((unsigned)blocks), dim3(NT), 0, s, in,
+                               (void*)out, g.nx, g.ny, B, twx, twy);
         else
             hipLaunchKernelGGL((fft_inv_reg_kernel<LX, LY, W>), dim3((unsigned)blocks), dim3(NT), 0, s, in, out, g.nx,
                                g.ny, B, twx, twy);
@@ -521,7 +528,63 @@ void dispatch(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, const c
     }
 }
 
+template <int FMT>
+__global__ void pack16_f_kernel(const float2* __restrict__ src, uint32_t* __restrict__ dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = pack16<FMT>(src[i]);
+}
+
+template <int FMT, int LX, int LY>
+void launch_fwd16(const Geom& g, const float2* X, uint32_t* Xh, int64_t B, const float2* twx, const float2* twy,
+                  float2* scratch, hipStream_t s) {
+    if constexpr (LX <= 32 && LY <= 32) {
+        (void)scratch;
+        constexpr int W = tile_w<float>(LX, LY);
+        constexpr int NT = (LX > LY ? LX : LY) * W;
+        const int64_t blocks = (B + W - 1) / W;
+        MBT_REQUIRE(blocks < (1LL << 31), "fft: batch too large");
+        hipLaunchKernelGGL((fft_fwd_reg_kernel<LX, LY, W, FMT>), dim3((unsigned)blocks), dim3(NT), 0, s, X, (void*)Xh,
+                           g.nx, g.ny, B, twx, twy);
+        MBT_LAUNCH_CHECK();
+    } else {
+        // FP32 transform into scratch, then one packing pass
+        launch_fft_t<float, true, LX, LY>(g, X, scratch, B, twx, twy, s);
+        const int64_t n = g.bins() * B;
+        const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+        hipLaunchKernelGGL((pack16_f_kernel<FMT>), dim3(grid), dim3(256), 0, s, scratch, Xh, n);
+        MBT_LAUNCH_CHECK();
+    }
+}
+
+template <int FMT, int LX>
+void dispatch16_ly(const Geom& g, const float2* X, uint32_t* Xh, int64_t B, const float2* twx, const float2* twy,
+                   float2* scratch, hipStream_t s) {
+    switch (g.Ly) {
+        case 8: launch_fwd16<FMT, LX, 8>(g, X, Xh, B, twx, twy, scratch, s); break;
+        case 16: launch_fwd16<FMT, LX, 16>(g, X, Xh, B, twx, twy, scratch, s); break;
+        case 32: launch_fwd16<FMT, LX, 32>(g, X, Xh, B, twx, twy, scratch, s); break;
+        case 64: launch_fwd16<FMT, LX, 64>(g, X, Xh, B, twx, twy, scratch, s); break;
+        default: throw Error(-1, "fft: unsupported grid (ny > 64)");
+    }
+}
+
 }  // namespace
+
+template <int FMT>
+void fft_fwd_pad16(const Geom& g, const float2* X, uint32_t* Xh, int64_t B, const float2* twx, const float2* twy,
+                   float2* scratch, hipStream_t s) {
+    switch (g.Lx) {
+        case 8: dispatch16_ly<FMT, 8>(g, X, Xh, B, twx, twy, scratch, s); break;
+        case 16: dispatch16_ly<FMT, 16>(g, X, Xh, B, twx, twy, scratch, s); break;
+        case 32: dispatch16_ly<FMT, 32>(g, X, Xh, B, twx, twy, scratch, s); break;
+        case 64: dispatch16_ly<FMT, 64>(g, X, Xh, B, twx, twy, scratch, s); break;
+        default: throw Error(-1, "fft: unsupported grid (nx > 64)");
+    }
+}
+template void fft_fwd_pad16<kFmtBf16>(const Geom&, const float2*, uint32_t*, int64_t, const float2*, const float2*,
+                                      float2*, hipStream_t);
+template void fft_fwd_pad16<kFmtF16>(const Geom&, const float2*, uint32_t*, int64_t, const float2*, const float2*,
+                                     float2*, hipStream_t);
 
 void make_twiddles(int P, double2* tw, hipStream_t s) {
     hipLaunchKernelGGL(twiddle_kernel, dim3((P + 255) / 256), dim3(256), 0, s, P, tw);

@@ -49,10 +49,12 @@ struct OpData {
     double s = 0, k = 0;
     DBuf T, Chat, tw, PkInv, PaInv;            // FP64
     DBuf Chat32, tw32, PkInv32, PaInv32;       // FP32 copies for reduced-precision inner solves
+    DBuf Chat16[2];                            // 16-bit spectra (bfloat16, binary16) for the 16-bit products,
+    double scale16[2] = {1.0, 1.0};            // stored as scale16 * C^ (a power of two)
     bool has_pa = false, has32 = false;
     size_t bytes() const {
         return T.bytes + Chat.bytes + tw.bytes + PkInv.bytes + PaInv.bytes + Chat32.bytes + tw32.bytes +
-               PkInv32.bytes + PaInv32.bytes;
+               PkInv32.bytes + PaInv32.bytes + Chat16[0].bytes + Chat16[1].bytes;
     }
 };
 
@@ -104,7 +106,11 @@ namespace mbt {
 
 Geom make_geom(const mbt_dipole& d, const mbt_lattice& l);
 void validate_opts(const mbt_solve_opts& o);
-std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_pa, bool need32, Worker& wk);
+// Cached operator data; need_pa adds the normal-equation preconditioner, prec
+// adds the copies that a reduced-precision inner solve reads.
+std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_pa, int prec, Worker& wk);
+// 16-bit storage format of a precision (kFmtNone for FP64 and FP32).
+int fmt16_of(int prec);
 size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o);
 // Largest RHS batch (<= R) whose solve workspace fits `budget` bytes.
 int choose_chunk(size_t budget, const Geom& g, int R, const mbt_solve_opts& o);

@@ -105,7 +105,8 @@ Geom make_geom(const mbt_dipole& d, const mbt_lattice& l) {
 }
 
 void validate_opts(const mbt_solve_opts& o) {
-    MBT_REQUIRE(o.prec == MBT_FP64 || o.prec == MBT_FP32, "precision not supported (FP64 or FP32)");
+    MBT_REQUIRE(o.prec == MBT_FP64 || o.prec == MBT_FP32 || o.prec == MBT_BF16 || o.prec == MBT_FP16,
+                "unknown precision");
     MBT_REQUIRE(o.pc == MBT_PC_NORMAL_EQ || o.pc == MBT_PC_ELEMENT_BLOCK, "unknown preconditioner");
     MBT_REQUIRE(o.restart >= 1 && o.restart <= 63, "restart must be in 1..63");
     MBT_REQUIRE(o.tol > 0 && o.tol < 1, "tol must be in (0, 1)");
@@ -117,8 +118,10 @@ void validate_opts(const mbt_solve_opts& o) {
 
 static double inner_tol(const mbt_solve_opts& o) {
     if (o.inner_tol > 0) return o.inner_tol;
-    return o.prec == MBT_FP32 ? 1e-4 : 1e-2;
+    return o.prec == MBT_FP32 ? 1e-4 : o.prec == MBT_FP16 ? 1e-3 : 1e-2;
 }
+
+int fmt16_of(int prec) { return prec == MBT_BF16 ? kFmtBf16 : prec == MBT_FP16 ? kFmtF16 : kFmtNone; }
 
 // ------------------------------------------------------------------ operator cache
 static std::string op_key(const Geom& g, double s) {
@@ -163,6 +166,30 @@ static void build_32(OpData& op, Worker& wk) {
     op.has32 = true;
 }
 
+// 16-bit copy of the block spectra, scaled by a power of two that puts the
+// largest component at 2^14: binary16 then keeps its full relative precision
+// over 2^28 of dynamic range below that (bfloat16 has FP32's range; the same
+// exact scaling does no harm there).
+static void build_16(OpData& op, int fmt, Worker& wk) {
+    const Geom& g = op.g;
+    const int64_t n = g.bins() * g.M * g.M;
+    DBuf dmax;
+    dmax.alloc(sizeof(double));
+    max_abs_d(op.Chat.as<double2>(), n, dmax.as<double>(), wk.stream);
+    double hmax = 0;
+    MBT_HIP(hipMemcpyAsync(&hmax, dmax.p, sizeof(double), hipMemcpyDeviceToHost, wk.stream));
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    MBT_REQUIRE(std::isfinite(hmax), "block spectra are not finite");
+    const double scale = hmax > 0 ? std::ldexp(1.0, 14 - std::ilogb(hmax) - 1) : 1.0;
+    op.Chat16[fmt].alloc(sizeof(uint32_t) * n);
+    if (fmt == kFmtBf16)
+        pack16_d<kFmtBf16>(op.Chat.as<double2>(), op.Chat16[fmt].as<uint32_t>(), n, scale, wk.stream);
+    else
+        pack16_d<kFmtF16>(op.Chat.as<double2>(), op.Chat16[fmt].as<uint32_t>(), n, scale, wk.stream);
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    op.scale16[fmt] = scale;
+}
+
 static std::shared_ptr<OpData> build_op(const Geom& g, double s, Worker& wk) {
     auto op = std::make_shared<OpData>();
     op->g = g;
@@ -195,7 +222,9 @@ static std::shared_ptr<OpData> build_op(const Geom& g, double s, Worker& wk) {
     return op;
 }
 
-std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_pa, bool need32, Worker& wk) {
+std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_pa, int prec, Worker& wk) {
+    const bool need32 = prec != MBT_FP64;
+    const int fmt = fmt16_of(prec);
     MBT_REQUIRE(s > 0 && std::isfinite(s), "freq_ratio must be positive");
     const std::string key = op_key(g, s);
     std::shared_ptr<OpData> op;
@@ -221,11 +250,13 @@ std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_
         }
     }
     // extend under the cache lock so concurrent workers do not race on the same entry
-    if ((need_pa && !op->has_pa) || (need32 && (!op->has32 || (need_pa && !op->PaInv32.p)))) {
+    if ((need_pa && !op->has_pa) || (need32 && (!op->has32 || (need_pa && !op->PaInv32.p))) ||
+        (fmt != kFmtNone && !op->Chat16[fmt].p)) {
         std::lock_guard<std::mutex> lk(ctx->cache_mu);
         const size_t before = op->bytes();
         if (need_pa && !op->has_pa) build_pa(*op, wk);
         if (need32 && (!op->has32 || (op->has_pa && !op->PaInv32.p))) build_32(*op, wk);
+        if (fmt != kFmtNone && !op->Chat16[fmt].p) build_16(*op, fmt, wk);
         ctx->cache_bytes += op->bytes() - before;
     }
     // evict least recently used entries beyond the limit (entries in use stay alive through shared_ptr)
@@ -258,11 +289,17 @@ template <typename T> struct OpV {
     int R;
     int pc;
     hipStream_t s;
+    int fmt = kFmtNone;                  // 16-bit per-bin products (FP32 view only)
+    const uint32_t* Chat16 = nullptr;
+    float out_scale = 1.0f;              // undoes the power-of-two scaling of Chat16
 };
 
-template <typename T> static OpV<T> make_view(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s);
+template <typename T>
+static OpV<T> make_view(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s,
+                        int fmt = kFmtNone);
 
-template <> OpV<double> make_view<double>(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s) {
+template <>
+OpV<double> make_view<double>(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s, int) {
     OpV<double> v;
     v.g = &op.g;
     v.Chat = op.Chat.as<double2>();
@@ -279,8 +316,15 @@ template <> OpV<double> make_view<double>(const OpData& op, int pc, void* Xh, vo
     return v;
 }
 
-template <> OpV<float> make_view<float>(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s) {
+template <>
+OpV<float> make_view<float>(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s, int fmt) {
     OpV<float> v;
+    if (fmt != kFmtNone) {
+        MBT_REQUIRE(op.Chat16[fmt].p != nullptr, "16-bit spectra not built");
+        v.fmt = fmt;
+        v.Chat16 = op.Chat16[fmt].as<uint32_t>();
+        v.out_scale = (float)(1.0 / op.scale16[fmt]);
+    }
     v.g = &op.g;
     v.Chat = op.Chat32.as<float2>();
     v.pinv = pc == MBT_PC_NORMAL_EQ ? op.PaInv32.as<float2>() : op.PkInv32.as<float2>();
@@ -302,6 +346,35 @@ template <typename T> static void zmul(const OpV<T>& o, int opz, const cplx<T>* 
     const int64_t B = (int64_t)g.M * o.R;
     const double sc = sizeof(cplx<T>);
     const double spat = (double)g.N * o.R * sc, spec = (double)g.bins() * g.M * o.R * sc;
+    if constexpr (sizeof(T) == 4) {
+        if (o.fmt != kFmtNone) {
+            // 16-bit spectrum X^ (4 bytes per value), FP32 products Y^
+            uint32_t* xh16 = reinterpret_cast<uint32_t*>(o.Xh);
+            const double spec16 = (double)g.bins() * g.M * o.R * 4.0;
+            {
+                ProfScope ps(kKFftFwd, spat + spec16, 0.0, o.s);
+                if (o.fmt == kFmtBf16)
+                    fft_fwd_pad16<kFmtBf16>(g, x, xh16, B, o.twx, o.twy, o.Yh, o.s);
+                else
+                    fft_fwd_pad16<kFmtF16>(g, x, xh16, B, o.twx, o.twy, o.Yh, o.s);
+            }
+            {
+                ProfScope ps(kKBinProduct, spec16 + spec + (double)g.bins() * g.M * g.M * 4.0,
+                             8.0 * g.bins() * g.M * g.M * o.R, o.s);
+                if (o.fmt == kFmtBf16)
+                    cgemm16_batched<kFmtBf16>(o.Chat16, (int64_t)g.M * g.M, xh16, o.Yh, g.M, o.R, g.bins(), opz,
+                                              o.out_scale, o.s);
+                else
+                    cgemm16_batched<kFmtF16>(o.Chat16, (int64_t)g.M * g.M, xh16, o.Yh, g.M, o.R, g.bins(), opz,
+                                             o.out_scale, o.s);
+            }
+            {
+                ProfScope ps(kKFftInv, spat + spec, 0.0, o.s);
+                fft_inv_crop<T>(g, o.Yh, y, B, o.twx, o.twy, o.s);
+            }
+            return;
+        }
+    }
     {
         ProfScope ps(kKFftFwd, spat + spec, 0.0, o.s);
         fft_fwd_pad<T>(g, x, o.Xh, B, o.twx, o.twy, o.s);
@@ -433,9 +506,10 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
         float2* r32 = arena.get<float2>(NR);
         double2* r64 = arena.get<double2>(NR);
         double2* d = arena.get<double2>(NR);
-        double* mask = arena.get<double>(R);
+        double* mask = arena.get<double>(R);      // 1/||r|| per RHS still refining, 0 once done
+        double* unscale = arena.get<double>(R);   // ||r|| per RHS still refining, 0 once done
         OpV<double> ov = make_view<double>(op, o.pc, Xh, Yh, tmp, R, s);
-        OpV<float> ov32 = make_view<float>(op, o.pc, Xh, Yh, tmp, R, s);
+        OpV<float> ov32 = make_view<float>(op, o.pc, Xh, Yh, tmp, R, s, fmt16_of(o.prec));
         std::function<void(const float2*, float2*)> f = [&](const float2* x, float2* y) { apply_A<float>(ov32, x, y); };
         prm.tol = inner_tol(o);
         zero_d(X, NR, s);
@@ -450,21 +524,26 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
             }
             std::vector<double> rn;
             norms_host(r64, g.N, R, arena, rn, s);
-            std::vector<double> hmask(R);
+            // the correction equation Z d = r is solved for r / ||r|| (unit columns keep the
+            // reduced-precision spectra inside the 16-bit range), then d is scaled back
+            std::vector<double> hmask(2 * R);
             int left = 0;
             for (int r = 0; r < R; ++r) {
                 const double rel = vn[r] > 0 ? rn[r] / vn[r] : 0.0;
-                done[r] = (rel <= o.refine_tol) || flagged[r];
-                hmask[r] = done[r] ? 0.0 : 1.0;
+                done[r] = (rel <= o.refine_tol) || flagged[r] || !(rn[r] > 0);
+                hmask[r] = done[r] ? 0.0 : 1.0 / rn[r];
+                hmask[R + r] = done[r] ? 0.0 : rn[r];
                 left += done[r] ? 0 : 1;
             }
             if (left == 0) break;
             MBT_HIP(hipMemcpyAsync(mask, hmask.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+            MBT_HIP(hipMemcpyAsync(unscale, hmask.data() + R, sizeof(double) * R, hipMemcpyHostToDevice, s));
             scale_columns_d(r64, mask, g.N, R, s);
             convert<double2, float2>(r64, r32, NR, s);
             apply_rhs<float>(ov32, r32, b32);
             out.matvecs += o.pc == MBT_PC_NORMAL_EQ ? 1 : 0;
             GmresResult gr = gmres_batched<float2>(f, b32, d, basis, g.N, R, prm, arena, s);
+            scale_columns_d(d, unscale, g.N, R, s);
             add_to_f64<double2>(X, d, NR, s);
             out.outer = outer + 1;
             out.cycles += gr.cycles;
@@ -511,8 +590,9 @@ SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t*
         op = build_op(g, s, wk);
         if (o.pc == MBT_PC_NORMAL_EQ) build_pa(*op, wk);
         if (o.prec != MBT_FP64) build_32(*op, wk);
+        if (fmt16_of(o.prec) != kFmtNone) build_16(*op, fmt16_of(o.prec), wk);
     } else {
-        op = get_op(ctx, g, s, o.pc == MBT_PC_NORMAL_EQ, o.prec != MBT_FP64, wk);
+        op = get_op(ctx, g, s, o.pc == MBT_PC_NORMAL_EQ, o.prec, wk);
     }
     MBT_HIP(hipStreamSynchronize(wk.stream));
     const double t1 = now_s();
@@ -659,7 +739,7 @@ void mbt_default_opts(mbt_solve_opts* o) {
 
 const char* mbt_last_error(void) { return g_err.c_str(); }
 
-const char* mbt_version(void) { return "mbt 0.1 (gfx950; FP64 + FP32 MFMA paths)"; }
+const char* mbt_version(void) { return "mbt 0.2 (gfx950; FP64, FP32, BF16 and FP16 MFMA per-bin products)"; }
 
 mbt_status mbt_ctx_create(int32_t dev, size_t budget, mbt_ctx** out) {
     API_BEGIN
@@ -717,6 +797,7 @@ size_t mbt_footprint(const mbt_array* a, int32_t nrhs, const mbt_solve_opts* o) 
         const size_t MM = (size_t)g.M * g.M;
         size_t opb = (size_t)g.noff() * MM * 16 + (size_t)g.bins() * MM * 16 + (size_t)g.P * MM * 16 * 2;
         if (o->prec != MBT_FP64) opb += (size_t)g.bins() * MM * 8 + (size_t)g.P * MM * 8;
+        if (fmt16_of(o->prec) != kFmtNone) opb += (size_t)g.bins() * MM * 4;
         return solve_bytes(g, nrhs, *o) + opb;
     } catch (...) {
         return 0;
@@ -844,7 +925,7 @@ mbt_status mbt_dbg_fill_blocks(mbt_ctx* ctx, const mbt_array* arr, double s, dou
     MBT_REQUIRE(ctx && arr && T, "NULL argument");
     std::lock_guard<std::mutex> lk(ctx->api_mu);
     DevScope ds(ctx->device);
-    auto op = get_op(ctx, arr->g, s, false, false, *ctx->main);
+    auto op = get_op(ctx, arr->g, s, false, MBT_FP64, *ctx->main);
     MBT_HIP(hipMemcpy(T, op->T.p, op->T.bytes, hipMemcpyDeviceToHost));
     API_END
 }
@@ -854,12 +935,12 @@ mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t 
     API_BEGIN
     MBT_REQUIRE(ctx && arr && x && y && R >= 1, "bad argument");
     MBT_REQUIRE(opz >= 0 && opz <= 2, "op must be 0, 1 or 2");
-    MBT_REQUIRE(prec == MBT_FP64 || prec == MBT_FP32, "precision not supported");
+    MBT_REQUIRE(prec >= MBT_FP64 && prec <= MBT_FP16, "unknown precision");
     std::lock_guard<std::mutex> lk(ctx->api_mu);
     DevScope ds(ctx->device);
     const Geom& g = arr->g;
     Worker& wk = *ctx->main;
-    auto op = get_op(ctx, g, s, false, prec == MBT_FP32, wk);
+    auto op = get_op(ctx, g, s, false, prec, wk);
     const int64_t NR = g.N * R;
     DBuf hx, dx, dy, Xh, Yh, tmp, f1, f2;
     hx.alloc(sizeof(double2) * NR);
@@ -881,7 +962,7 @@ mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t 
     } else {
         f1.alloc(sizeof(float2) * NR);
         f2.alloc(sizeof(float2) * NR);
-        OpV<float> ov = make_view<float>(*op, MBT_PC_ELEMENT_BLOCK, Xh.p, Yh.p, tmp.p, R, wk.stream);
+        OpV<float> ov = make_view<float>(*op, MBT_PC_ELEMENT_BLOCK, Xh.p, Yh.p, tmp.p, R, wk.stream, fmt16_of(prec));
         convert<double2, float2>(dx.as<double2>(), f1.as<float2>(), NR, wk.stream);
         if (opz == 2) {
             zmul<float>(ov, 0, f1.as<float2>(), ov.tmp);
@@ -906,7 +987,7 @@ mbt_status mbt_dbg_precond_apply(mbt_ctx* ctx, const mbt_array* arr, double s, i
     DevScope ds(ctx->device);
     const Geom& g = arr->g;
     Worker& wk = *ctx->main;
-    auto op = get_op(ctx, g, s, pc == MBT_PC_NORMAL_EQ, false, wk);
+    auto op = get_op(ctx, g, s, pc == MBT_PC_NORMAL_EQ, MBT_FP64, wk);
     const int64_t NR = g.N * R;
     DBuf hx, dx, dy;
     hx.alloc(sizeof(double2) * NR);
@@ -929,7 +1010,7 @@ mbt_status mbt_dbg_precond_blocks(mbt_ctx* ctx, const mbt_array* arr, double s, 
     DevScope ds(ctx->device);
     const Geom& g = arr->g;
     Worker& wk = *ctx->main;
-    auto op = get_op(ctx, g, s, false, false, wk);
+    auto op = get_op(ctx, g, s, false, MBT_FP64, wk);
     const int64_t MM = (int64_t)g.M * g.M;
     if (pc == MBT_PC_ELEMENT_BLOCK) {
         const int64_t center = (int64_t)(g.ny - 1) * g.nox + (g.nx - 1);
@@ -956,7 +1037,7 @@ mbt_status mbt_dbg_solve(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt
     const Geom& g = arr->g;
     Worker& wk = *ctx->main;
     const double t0 = now_s();
-    auto op = get_op(ctx, g, s, opts->pc == MBT_PC_NORMAL_EQ, opts->prec != MBT_FP64, wk);
+    auto op = get_op(ctx, g, s, opts->pc == MBT_PC_NORMAL_EQ, opts->prec, wk);
     const int64_t NR = g.N * R;
     wk.ensure(solve_bytes(g, R, *opts) + 3 * sizeof(double2) * NR);
     DevArena arena;

@@ -18,6 +18,33 @@ __global__ void convert_kernel(const TS* __restrict__ src, TD* __restrict__ dst,
         dst[i] = from_d2<TD>(to_d2(src[i]));
 }
 
+template <int FMT>
+__global__ void pack16_d_kernel(const double2* __restrict__ src, uint32_t* __restrict__ dst, int64_t n,
+                                double scale) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = src[i];
+        dst[i] = pack16<FMT>(make_float2((float)(v.x * scale), (float)(v.y * scale)));
+    }
+}
+
+// largest |re| or |im| over n complex values; one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void max_abs_kernel(const double2* __restrict__ src, int64_t n,
+                                                       double* __restrict__ out) {
+    __shared__ double red[1024];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const double2 v = src[i];
+        m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // V[n][r] = 1 at the port basis of element ports[r], 0 elsewhere (V pre-zeroed)
 __global__ void scatter_ports_kernel(const int32_t* __restrict__ ports, int R, int M, int pc, double2* V) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -123,6 +150,20 @@ void convert(const TS* src, TD* dst, int64_t n, hipStream_t s) {
 template void convert<double2, float2>(const double2*, float2*, int64_t, hipStream_t);
 template void convert<float2, double2>(const float2*, double2*, int64_t, hipStream_t);
 template void convert<double2, double2>(const double2*, double2*, int64_t, hipStream_t);
+
+template <int FMT>
+void pack16_d(const double2* src, uint32_t* dst, int64_t n, double scale, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((pack16_d_kernel<FMT>), dim3(grid_for(n)), dim3(256), 0, s, src, dst, n, scale);
+    MBT_LAUNCH_CHECK();
+}
+template void pack16_d<kFmtBf16>(const double2*, uint32_t*, int64_t, double, hipStream_t);
+template void pack16_d<kFmtF16>(const double2*, uint32_t*, int64_t, double, hipStream_t);
+
+void max_abs_d(const double2* src, int64_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(max_abs_kernel, dim3(1), dim3(1024), 0, s, src, n, out);
+    MBT_LAUNCH_CHECK();
+}
 
 void scatter_ports(const Geom& g, const int32_t* ports, int R, double2* V, hipStream_t s) {
     zero_d(V, g.N * R, s);

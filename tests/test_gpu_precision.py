@@ -1,0 +1,135 @@
+"""Reduced-precision operator on the GPU: the 16-bit per-bin products against
+the dense oracle at the bound their rounding allows, FP64 iterative refinement
+on top of them, and the 21-frequency sweep of the 5x5 array (all frequencies
+of one request served concurrently) against the stored oracle results."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mom
+from paper_2608_17844_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dipole_5x5_m15_21f_reference.npz")
+
+# unit roundoff of the 16-bit formats (round to nearest): 2^-8 (bfloat16), 2^-11 (binary16)
+UNIT = {2: 2.0 ** -8, 3: 2.0 ** -11}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2608_17844_amd import mbt
+    h = mbt.mbt_ctx_create(0)
+    yield h
+    mbt.mbt_ctx_destroy(h)
+
+
+SHAPES = [
+    (W.Lattice(5, 5, 0.5, 0.5), W.Dipole(0.5, 0.005, 15)),
+    (W.Lattice(9, 6, 0.5, 0.55), W.Dipole(0.5, 0.005, 31)),
+    (W.Lattice(17, 3, 0.5, 0.5), W.Dipole(0.48, 0.004, 21)),
+    (W.Lattice(40, 2, 0.5, 0.5), W.Dipole(0.5, 0.005, 7)),   # 128-point grid axis: FP32 transform + packing pass
+]
+
+
+@pytest.mark.parametrize("prec", [2, 3], ids=["bf16", "fp16"])
+@pytest.mark.parametrize("shape", SHAPES, ids=["%dx%d_m%d" % (l.nx, l.ny, d.nbases) for l, d in SHAPES])
+def test_matvec_16bit_products(ctx, shape, prec):
+    """Each input of a per-bin product (C^ and X^) is rounded once to the 16-bit
+    format, so the product is within 2u of the exact one in norm (u the unit
+    roundoff); Z^H Z rounds twice."""
+    from paper_2608_17844_amd import mbt
+    lat, dip = shape
+    a = mbt.mbt_array_create_dipole(ctx, dip, lat)
+    try:
+        Z = mom.fill_dense(lat, dip, 1.0)
+        x = W.random_vectors(Z.shape[0], 37, seed=5)
+        for op in (0, 1, 2):
+            y = mbt.mbt_dbg_matvec(ctx, a, 1.0, x, op=op, prec=prec)
+            ref = Z @ x if op == 0 else (Z.conj().T @ x if op == 1 else Z.conj().T @ (Z @ x))
+            err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+            _say("prec=%d op=%d rel=%.3e" % (prec, op, err))
+            assert err <= 2 * UNIT[prec] * (2 if op == 2 else 1)
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+@pytest.mark.parametrize("pc", [1, 0])
+def test_fp16_products_with_refinement_reach_fp64_accuracy(ctx, cfg1, cfg1_oracle, pc):
+    from paper_2608_17844_amd import mbt
+    a = mbt.mbt_array_create_dipole(ctx, cfg1.dipole, cfg1.lattice)
+    try:
+        opts = mbt.mbt_default_opts(prec=mbt.MBT_FP16, pc=pc, refine_max=10)
+        out = mbt.mbt_solve(ctx, a, 1.0, opts, cfg1.theta, cfg1.phi, cfg1.z0)
+    finally:
+        mbt.mbt_array_destroy(a)
+    ref = cfg1_oracle
+    err = np.linalg.norm(out["Zp"] - ref.Zp) / np.linalg.norm(ref.Zp)
+    _say("fp16 pc=%d outer=%d err=%.2e" % (pc, out["stats"]["outer_steps"], err))
+    assert out["stats"]["true_relres_max"] <= 1e-9
+    assert err <= 1e-8
+    assert np.max(np.abs(out["Gamma"] - ref.Gamma)) <= 1e-7
+
+
+def test_bf16_refinement_contracts(ctx, cfg1, cfg1_oracle):
+    """bfloat16 products leave an operator error near 1e-3; each FP64
+    refinement step must still shrink the error (it converges, slowly)."""
+    from paper_2608_17844_amd import mbt
+    a = mbt.mbt_array_create_dipole(ctx, cfg1.dipole, cfg1.lattice)
+    errs = []
+    try:
+        for rmax in (1, 3, 8):
+            opts = mbt.mbt_default_opts(prec=mbt.MBT_BF16, pc=1, refine_max=rmax)
+            out = mbt.mbt_solve(ctx, a, 1.0, opts, cfg1.theta, cfg1.phi, cfg1.z0, allow_noconv=True)
+            errs.append(np.linalg.norm(out["Zp"] - cfg1_oracle.Zp) / np.linalg.norm(cfg1_oracle.Zp))
+    finally:
+        mbt.mbt_array_destroy(a)
+    _say("bf16 errors after 1, 3, 8 refinement steps:", ["%.2e" % e for e in errs])
+    assert errs[1] < errs[0] and errs[2] < errs[1] / 10
+    assert errs[2] <= 1e-3
+
+
+def test_frequency_sweep_5x5_21_frequencies(ctx):
+    """All 21 frequencies of the sweep as one served request (frequencies run
+    concurrently).  FP64: 1e-9 on Z_p (1e-8 on the ARC) per frequency; FP32
+    with at most three refinement steps: 1e-6 on both.  The 16-bit variants are
+    reported."""
+    from paper_2608_17844_amd import mbt
+    ref = np.load(GOLDEN)
+    w = W.sweep_5x5_21f()
+    assert np.allclose(ref["freqs"], w.freqs)
+    srv = mbt.mbt_server_create(ctx, 4)
+    res = {}
+    try:
+        for prec in (0, 1, 3, 2):
+            opts = mbt.mbt_default_opts(prec=prec, pc=mbt.MBT_PC_ELEMENT_BLOCK, refine_max=3, refine_tol=1e-9)
+            t = mbt.mbt_server_submit(srv, (w.dipole.length, w.dipole.radius, w.dipole.nbases),
+                                      (w.lattice.nx, w.lattice.ny, w.lattice.dx, w.lattice.dy),
+                                      w.freqs, w.theta, w.phi, opts)
+            res[prec] = mbt.mbt_server_wait(srv, t)
+    finally:
+        mbt.mbt_server_destroy(srv)
+    names = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp16"}
+    worst = {}
+    for prec, r in res.items():
+        ez = [np.linalg.norm(r["Zp"][i] - ref["Zp"][i]) / np.linalg.norm(ref["Zp"][i]) for i in range(21)]
+        eg = [np.max(np.abs(r["Gamma"][i] - ref["Gamma"][i])) for i in range(21)]
+        worst[prec] = (max(ez), max(eg))
+        _say("%s: status %d, per-frequency |dZp|/|Zp| max %.2e, |dGamma| max %.2e" % (
+            names[prec], r["status"], max(ez), max(eg)))
+        _say("   ", " ".join("%.1e" % e for e in ez))
+    assert res[0]["status"] == mbt.MBT_OK and res[1]["status"] == mbt.MBT_OK
+    # Z_p to 1e-9; the ARC is a derived quantity whose error is about ten times the Z_p error
+    assert worst[0][0] <= 1e-9 and worst[0][1] <= 1e-8
+    assert worst[1][0] <= 1e-6 and worst[1][1] <= 1e-6
+    # 16-bit variants within three refinement steps: measured characteristics
+    assert worst[3][0] <= 1e-4
+    assert worst[2][0] <= 1e-1

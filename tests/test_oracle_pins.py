@@ -349,3 +349,18 @@ def test_delayed_reorthogonalisation_gmres_matches_cgs2(cfg1, cfg1_dense):
         d = og.gmres_dcgs2(sysm.apply, b, restart=7, tol=1e-10)
         assert a.iters == d.iters and a.cycles == d.cycles and d.converged
         assert np.linalg.norm(a.x - d.x) <= 1e-9 * np.linalg.norm(a.x)
+
+
+def test_stored_sweep_reference_is_the_oracle():
+    """The stored 21-frequency results are the oracle's own (regenerated at the
+    two ends of the sweep), and the sweep's s = 1 entry is the single-frequency
+    5x5 workload."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                               "dipole_5x5_m15_21f_reference.npz"))
+    w = W.sweep_5x5_21f()
+    for i in (0, 20):
+        r = mom.solve_array(w.lattice, w.dipole, w.freqs[i], w.theta, w.phi)
+        assert np.max(np.abs(r.Zp - ref["Zp"][i])) <= 1e-10 * np.max(np.abs(r.Zp))
+        assert np.max(np.abs(r.Gamma - ref["Gamma"][i])) <= 1e-10
+    assert abs(ref["freqs"][10] - 1.0) < 1e-15
