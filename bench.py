@@ -8,9 +8,12 @@ active impedance / ARC at 64 scan angles -- with nothing reused across steps
 (the operator cache is bypassed).  The headline path runs the lattice FFTs
 and per-bin block products in FP32 on the matrix cores (FP64 Arnoldi
 accumulation, FP64 iterative refinement); the plain FP64 path is timed beside
-it at matched Z_p accuracy.  Prints one JSON line.
+it at the same accuracy target (Z_p entries and the center ARC within 1e-6
+relative of the FP64 oracle).  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1]
+  python bench.py [--steps K] [--warmup W] [--gpus 1]     headline 32x32 workload
+  python bench.py --serve 40 [--load 0.8] [--slots 4]     Poisson serving stream
+  python bench.py --sweep                                  21-frequency precision sweep
 """
 from __future__ import annotations
 
@@ -36,14 +39,20 @@ def log(*a):
 
 
 def zp_errors(out, ref):
+    """Errors against the stored oracle results: Z_p center row (norm-wise),
+    4096 sampled entries (each relative to itself and to max |Z_p|), the
+    diagonal, and the ARC at the 64 scan angles (absolute and relative)."""
     Zp = out["Zp"]
     c = int(ref["center"])
     row = np.linalg.norm(Zp[c, :] - ref["Zp_center_row"]) / np.linalg.norm(ref["Zp_center_row"])
-    samp = np.max(np.abs(Zp[ref["Zp_rows"], ref["Zp_cols"]] - ref["Zp_samples"])) / float(ref["Zp_max"])
+    d = np.abs(Zp[ref["Zp_rows"], ref["Zp_cols"]] - ref["Zp_samples"])
+    samp = np.max(d) / float(ref["Zp_max"])
+    elem = np.max(d / np.abs(ref["Zp_samples"]))
     diag = np.max(np.abs(np.diag(Zp) - ref["Zp_diag"]) / np.abs(ref["Zp_diag"]))
-    gam = np.max(np.abs(out["Gamma"] - ref["Gamma"]))
-    return {"zp_center_row_rel": float(row), "zp_sample_max_rel": float(samp), "zp_diag_max_rel": float(diag),
-            "gamma_max_abs": float(gam)}
+    dg = np.abs(out["Gamma"] - ref["Gamma"])
+    return {"zp_center_row_rel": float(row), "zp_sample_max_rel": float(samp), "zp_sample_elementwise_rel": float(elem),
+            "zp_diag_max_rel": float(diag), "gamma_max_abs": float(np.max(dg)),
+            "gamma_max_rel": float(np.max(dg / np.abs(ref["Gamma"])))}
 
 
 def run_steps(mbt, ctx, arr, w, opts, steps, warmup, kernel=None):
@@ -67,15 +76,15 @@ def run_steps(mbt, ctx, arr, w, opts, steps, warmup, kernel=None):
     return total, times, out, prof
 
 
-def cpu_baseline(w):
+def cpu_baseline(w, side=20):
     """The CPU oracle (dense fill from absolute positions, LAPACK LU, extraction)
     timed on a bounded sample: the same element, frequency and spacing on a
-    14x14 lattice (N = 6076), each phase scaled to the 32x32 size by its
+    20x20 lattice (N = 12,400), each phase scaled to the 32x32 size by its
     complexity (fill ~ N^2, LU ~ N^3, solve ~ N^2 * ports); the extraction
     (P x P inverse, S, scans) is timed at the real P = 1024."""
     from oracle import mom
     from paper_2608_17844_amd import workloads as W
-    lat_s = W.Lattice(14, 14, w.lattice.dx, w.lattice.dy)
+    lat_s = W.Lattice(side, side, w.lattice.dx, w.lattice.dy)
     r = mom.solve_array(lat_s, w.dipole, 1.0, w.theta, w.phi, z0=w.z0)
     n1 = lat_s.nx * lat_s.ny * w.dipole.nbases
     p1 = lat_s.nx * lat_s.ny
@@ -100,29 +109,30 @@ def cpu_baseline(w):
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     sample_s = sum(r.times.values()) + t_ext
     return {"value": p2 / total, "unit": "solves/s", "cores": min(cores, threads), "kind": "oracle",
-            "sample": "14x14 lattice of the same dipole (N=6076, 196 ports), dense fill + LAPACK LU + solve "
+            "sample": "%dx%d lattice of the same dipole (N=%d, %d ports), dense fill + LAPACK LU + solve "
                       "+ extraction, %.1f s of CPU work, phases scaled to 32x32 (fill N^2, LU N^3, solve N^2*P); "
-                      "extraction timed at P=1024" % sample_s,
+                      "extraction timed at P=1024" % (side, side, n1, p1, sample_s),
             "phases_s": {"fill": t_fill, "lu": t_lu, "solve": t_solve, "extract": t_ext}}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--pc", choices=["element_block", "normal_eq"], default="element_block")
-    ap.add_argument("--kernel", choices=sorted(KERNEL_CODES), default="arnoldi_update_dots")
-    ap.add_argument("--refine-tol", type=float, default=1e-7)
-    ap.add_argument("--fp64-tol", type=float, default=1e-7, help="FP64 GMRES tolerance at matched Z_p accuracy")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this solver's workload fits one MI355X and no multi-GPU path "
-              "is built (--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def kernel_rooflines(mbt, ctx, arr, w, opts, classes):
+    """One extra (untimed) step per kernel class with HIP-event timing of that
+    class: algorithmic bytes / measured time, against the HBM peak."""
+    out = {}
+    for name in classes:
+        mbt.mbt_prof_start(KERNEL_CODES[name])
+        mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
+        p = mbt.mbt_prof_read()
+        mbt.mbt_prof_start(0)
+        if p["launches"] and p["ms"] > 0:
+            gbs = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+            out[name] = {"achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS, "launches": p["launches"],
+                         "avg_launch_ms": p["ms"] / p["launches"], "alg_bytes_per_launch": p["bytes"] / p["launches"],
+                         "ms_total": p["ms"]}
+    return out
 
+
+def headline(args):
     from paper_2608_17844_amd import mbt
     from paper_2608_17844_amd import workloads as W
     import torch
@@ -136,7 +146,7 @@ def main():
     result = {}
     try:
         o32 = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=pc, restart=w.restart, refine_tol=args.refine_tol,
-                                   flags=mbt.MBT_FLAG_NO_CACHE)
+                                   inner_tol=args.inner_tol, flags=mbt.MBT_FLAG_NO_CACHE)
         log("fp32-mfma path: warmup %d, steps %d" % (args.warmup, args.steps))
         total, times, out, prof = run_steps(mbt, ctx, arr, w, o32, args.steps, args.warmup, args.kernel)
         err32 = zp_errors(out, ref)
@@ -154,6 +164,11 @@ def main():
                     "errors": err64, "iters_max": out64["stats"]["iters_max"],
                     "matvecs": out64["stats"]["matvecs"]}
             log("fp64: %.3f s/step  %.1f solves/s  err %s" % (t64 / args.steps, fp64["value"], err64))
+        kernels = {}
+        if not args.no_kernel_table:
+            log("per-kernel rooflines (one untimed step per kernel class)")
+            kernels = kernel_rooflines(mbt, ctx, arr, w, o32, ["arnoldi_dots", "fft_fwd_pad", "fft_inv_crop",
+                                                                 "bin_product", "precond_apply"])
         achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof and prof["ms"] > 0 else None
         roofline = {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
@@ -170,7 +185,8 @@ def main():
                        "preconditioner": args.pc, "restart": w.restart,
                        "precision": "FP32 lattice FFT + FP32 MFMA block products, FP32-stored Krylov basis with "
                                     "FP64 dot products/Givens, FP64 refinement residual and extraction",
-                       "refine_tol": args.refine_tol},
+                       "refine_tol": args.refine_tol, "inner_tol": args.inner_tol,
+                       "accuracy_target": "Z_p entries and center ARC within 1e-6 relative of the FP64 oracle"},
             "accuracy": err32, "iters_max": st32["iters_max"], "outer_steps": st32["outer_steps"],
             "matvecs_per_step": st32["matvecs"],
             "matvecs_per_s": st32["matvecs"] * args.steps / total,
@@ -179,6 +195,7 @@ def main():
             "fp64": fp64,
             "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
             "roofline": roofline,
+            "kernels": kernels,
         }
         torch.cuda.synchronize()
     finally:
@@ -189,6 +206,153 @@ def main():
         result["cpu_baseline"] = cpu_baseline(w)
     else:
         result["cpu_baseline"] = None
+    return result
+
+
+def serve(args):
+    """Serving form: a seeded Poisson stream of heterogeneous requests (Nx, Ny
+    in 8..48, 15 or 31 bases, 1-8 frequencies in 0.5-1.5 f0, 1-64 scans)
+    through the continuous-batching server.  First the saturation throughput
+    (all requests submitted at once), then the stream at a fraction of that
+    request rate; latency is submit -> result on the server clock."""
+    from paper_2608_17844_amd import mbt
+    from paper_2608_17844_amd import workloads as W
+
+    ctx = mbt.mbt_ctx_create(0)
+    srv = mbt.mbt_server_create(ctx, args.slots)
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, refine_tol=args.refine_tol,
+                                inner_tol=args.inner_tol, max_cycles=args.serve_max_cycles)
+
+    def submit(r):
+        return mbt.mbt_server_submit(srv, (r.dipole.length, r.dipole.radius, r.dipole.nbases),
+                                     (r.lattice.nx, r.lattice.ny, r.lattice.dx, r.lattice.dy),
+                                     r.freqs, r.theta, r.phi, opts, r.z0)
+
+    def solves(r):
+        return r.lattice.nx * r.lattice.ny * len(r.freqs)
+
+    def collect(tickets, reqs, t0):
+        out = []
+        for i, (t, r) in enumerate(zip(tickets, reqs)):
+            x = mbt.mbt_server_wait(srv, t)
+            out.append(x)
+            log("  request %d (%dx%d, M=%d, %d freq, %d scans) status %d, latency %.2f s, iters %s, at %.1f s" % (
+                i, r.lattice.nx, r.lattice.ny, r.dipole.nbases, len(r.freqs), len(r.theta), x["status"],
+                x["t_done"] - x["t_submit"], list(int(v) for v in x["iters_max"]), x["t_done"] - t0))
+        return out
+
+    try:
+        warm = W.serving_stream(args.serve_warmup, 0.0, seed=1)
+        log("serving: warm-up with %d requests" % len(warm))
+        collect([submit(r) for r in warm], warm, mbt.mbt_server_clock(srv))
+        reqs = W.serving_stream(args.serve, 1.0, seed=0)
+        log("serving: saturation run, %d requests submitted at once" % len(reqs))
+        t0 = mbt.mbt_server_clock(srv)
+        tickets = [submit(r) for r in reqs]
+        res = collect(tickets, reqs, t0)
+        t_sat = max(x["t_done"] for x in res) - t0
+        sat_rate = len(reqs) / t_sat
+        sat_solves = sum(solves(r) for r in reqs) / t_sat
+        bad = sum(1 for x in res if x["status"] != mbt.MBT_OK)
+        log("serving: saturation %.2f requests/s, %.1f solves/s (%d not converged)" % (sat_rate, sat_solves, bad))
+        rate = args.load * sat_rate
+        reqs = W.serving_stream(args.serve, rate, seed=0)
+        log("serving: Poisson stream at %.2f requests/s (%.0f%% of saturation)" % (rate, 100 * args.load))
+        t0 = mbt.mbt_server_clock(srv)
+        tickets = []
+        for r in reqs:
+            dt = t0 + r.arrival - mbt.mbt_server_clock(srv)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(submit(r))
+        res = collect(tickets, reqs, t0)
+        lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
+        wait = np.array([x["t_start"] - x["t_submit"] for x in res]) * 1e3
+        span = max(x["t_done"] for x in res) - t0
+        nsolves = sum(solves(r) for r in reqs)
+        bad = sum(1 for x in res if x["status"] != mbt.MBT_OK)
+    finally:
+        mbt.mbt_server_destroy(srv)
+        mbt.mbt_ctx_destroy(ctx)
+    return {"metric": "served port-excitation solves/s and p50/p99 request latency, Poisson stream",
+            "value": nsolves / span, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "dipole_serving_stream", "requests": len(reqs), "warmup_requests": len(warm),
+                       "slots": args.slots, "rate_rps": rate, "load_vs_saturation": args.load,
+                       "nx_ny": [8, 48], "nbases": [15, 31], "nfreq": [1, 8], "nscan": [1, 64],
+                       "refine_tol": args.refine_tol, "inner_tol": args.inner_tol,
+                       "max_cycles": args.serve_max_cycles},
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean()), "queue_wait_p50": float(np.percentile(wait, 50))},
+            "saturation": {"requests_per_s": sat_rate, "solves_per_s": sat_solves},
+            "not_converged": bad, "span_s": span}
+
+
+def sweep(args):
+    """Precision form: the 5x5 array at 21 frequencies (one request, served
+    concurrently) in FP64, FP32, FP16 and BF16 products with at most three FP64
+    refinement steps; per-frequency Z_p and ARC errors against the stored
+    oracle results."""
+    from paper_2608_17844_amd import mbt
+    from paper_2608_17844_amd import workloads as W
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "dipole_5x5_m15_21f_reference.npz"))
+    w = W.sweep_5x5_21f()
+    ctx = mbt.mbt_ctx_create(0)
+    srv = mbt.mbt_server_create(ctx, 4)
+    out = {}
+    try:
+        for name, prec in (("fp64", 0), ("fp32", 1), ("fp16", 3), ("bf16", 2)):
+            opts = mbt.mbt_default_opts(prec=prec, pc=mbt.MBT_PC_ELEMENT_BLOCK, refine_max=3, refine_tol=1e-9)
+            t = mbt.mbt_server_submit(srv, (w.dipole.length, w.dipole.radius, w.dipole.nbases),
+                                      (w.lattice.nx, w.lattice.ny, w.lattice.dx, w.lattice.dy),
+                                      w.freqs, w.theta, w.phi, opts)
+            r = mbt.mbt_server_wait(srv, t)
+            ez = [float(np.linalg.norm(r["Zp"][i] - ref["Zp"][i]) / np.linalg.norm(ref["Zp"][i])) for i in range(21)]
+            eg = [float(np.max(np.abs(r["Gamma"][i] - ref["Gamma"][i]) / np.abs(ref["Gamma"][i]))) for i in range(21)]
+            out[name] = {"status": int(r["status"]), "seconds": r["t_done"] - r["t_submit"],
+                         "zp_rel": ez, "gamma_rel": eg, "zp_rel_max": max(ez), "gamma_rel_max": max(eg)}
+            log("%s: %.3f s, max |dZp|/|Zp| %.2e, max |dGamma|/|Gamma| %.2e" % (
+                name, out[name]["seconds"], max(ez), max(eg)))
+    finally:
+        mbt.mbt_server_destroy(srv)
+        mbt.mbt_ctx_destroy(ctx)
+    return {"metric": "per-frequency Z_p and ARC error vs the FP64 oracle, 21-frequency sweep",
+            "config": {"workload": w.name, "freqs": list(w.freqs), "refine_max": 3}, "data": "synthetic",
+            "n_gpus": 1, "results": out}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--pc", choices=["element_block", "normal_eq"], default="element_block")
+    ap.add_argument("--kernel", choices=sorted(KERNEL_CODES), default="arnoldi_update_dots")
+    ap.add_argument("--refine-tol", type=float, default=1e-7, help="FP64 refinement stop of the mixed path")
+    ap.add_argument("--inner-tol", type=float, default=1e-3, help="inner FP32 GMRES tolerance of the mixed path")
+    ap.add_argument("--fp64-tol", type=float, default=1e-9,
+                    help="FP64 GMRES tolerance giving the same accuracy target (1e-6 on Z_p entries and ARC)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-kernel-table", action="store_true")
+    ap.add_argument("--serve", type=int, default=0, help="run the serving stream with this many requests instead")
+    ap.add_argument("--serve-warmup", type=int, default=4)
+    ap.add_argument("--serve-max-cycles", type=int, default=20,
+                    help="restart cycles per inner solve in the serving run (slow-converging requests report ENOCONV)")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--load", type=float, default=0.8, help="stream rate as a fraction of saturation")
+    ap.add_argument("--sweep", action="store_true", help="run the 21-frequency precision sweep instead")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this solver's workload fits one MI355X and no multi-GPU path "
+              "is built (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.serve > 0:
+        result = serve(args)
+    elif args.sweep:
+        result = sweep(args)
+    else:
+        result = headline(args)
     print(json.dumps(result), flush=True)
 
 
