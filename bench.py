@@ -232,13 +232,24 @@ def serve(args):
         return r.lattice.nx * r.lattice.ny * len(r.freqs)
 
     def collect(tickets, reqs, t0):
-        out = []
-        for i, (t, r) in enumerate(zip(tickets, reqs)):
-            x = mbt.mbt_server_wait(srv, t)
-            out.append(x)
-            log("  request %d (%dx%d, M=%d, %d freq, %d scans) status %d, latency %.2f s, iters %s, at %.1f s" % (
-                i, r.lattice.nx, r.lattice.ny, r.dipole.nbases, len(r.freqs), len(r.theta), x["status"],
-                x["t_done"] - x["t_submit"], list(int(v) for v in x["iters_max"]), x["t_done"] - t0))
+        """Results in submission order; each is logged as it completes."""
+        out = [None] * len(tickets)
+        pending = list(range(len(tickets)))
+        while pending:
+            still = []
+            for i in pending:
+                x = mbt.mbt_server_wait(srv, tickets[i], 0)
+                if x is None:
+                    still.append(i)
+                    continue
+                out[i] = x
+                r = reqs[i]
+                log("  request %d (%dx%d, M=%d, %d freq, %d scans) status %d, latency %.2f s, iters %s, at %.1f s" % (
+                    i, r.lattice.nx, r.lattice.ny, r.dipole.nbases, len(r.freqs), len(r.theta), x["status"],
+                    x["t_done"] - x["t_submit"], list(int(v) for v in x["iters_max"]), x["t_done"] - t0))
+            pending = still
+            if pending:
+                time.sleep(0.02)
         return out
 
     try:
@@ -337,16 +348,28 @@ def main():
     ap.add_argument("--no-kernel-table", action="store_true")
     ap.add_argument("--serve", type=int, default=0, help="run the serving stream with this many requests instead")
     ap.add_argument("--serve-warmup", type=int, default=4)
-    ap.add_argument("--serve-max-cycles", type=int, default=20,
+    ap.add_argument("--serve-max-cycles", type=int, default=8,
                     help="restart cycles per inner solve in the serving run (slow-converging requests report ENOCONV)")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--load", type=float, default=0.8, help="stream rate as a fraction of saturation")
     ap.add_argument("--sweep", action="store_true", help="run the 21-frequency precision sweep instead")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy kernel three times (a known-size reference "
+                         "for hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this solver's workload fits one MI355X and no multi-GPU path "
               "is built (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of %d bytes" % (src.numel() * 4))
+        del src, dst
     if args.serve > 0:
         result = serve(args)
     elif args.sweep:

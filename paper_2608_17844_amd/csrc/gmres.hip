@@ -510,6 +510,74 @@ void launch_dcgs2_dots_rpl(const TB* V, int64_t vs, int k, const TB* u, const TB
     MBT_LAUNCH_CHECK();
 }
 
+// Row-split update sweep: each wave owns RB consecutive rows of 64 RHS columns
+// and walks all k basis vectors itself, so there is no cross-wave reduction and
+// no workgroup barrier; the per-RHS coefficients are re-read (from L2) for each
+// block of rows.  The next vector's rows are loaded while the current ones are
+// accumulated.  Summation over i is sequential per (row, RHS).
+template <typename TB, int RB>
+__global__ __launch_bounds__(256) void dcgs2_update_rows_kernel(const TB* __restrict__ V, int64_t vstride, int k,
+                                                                TB* u, TB* w, const double2* __restrict__ cs,
+                                                                const double2* __restrict__ cc,
+                                                                const double* __restrict__ inv_nu, int64_t N, int R) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r = blockIdx.x * 64 + lane;
+    const int64_t n0 = ((int64_t)blockIdx.y * 4 + wave) * RB;
+    if (r >= R || n0 >= N) return;
+    const int nr = (int)min<int64_t>(RB, N - n0);
+    double2 a[RB], c[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) a[j] = c[j] = make_double2(0, 0);
+    const TB* base = V + n0 * R + r;
+    Raw<TB, 1> cur[RB], nxt[RB];
+    auto load = [&](int i, Raw<TB, 1>(&v)[RB]) {
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            if (j < nr) v[j].load(base + i * vstride + (int64_t)j * R);
+            else v[j].zero();
+        }
+    };
+    double2 fs = make_double2(0, 0), fc = make_double2(0, 0);
+    if (k > 0) {
+        load(0, cur);
+        fs = cs[r];
+        fc = cc[r];
+    }
+    for (int i = 0; i < k; ++i) {
+        double2 fs_n = make_double2(0, 0), fc_n = make_double2(0, 0);
+        if (i + 1 < k) {
+            load(i + 1, nxt);
+            fs_n = cs[(int64_t)(i + 1) * R + r];
+            fc_n = cc[(int64_t)(i + 1) * R + r];
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const double2 vv = cur[j].get(0);
+            a[j] = cadd(a[j], cmul(fs, vv));
+            c[j] = cadd(c[j], cmul(fc, vv));
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) cur[j] = nxt[j];
+        fs = fs_n;
+        fc = fc_n;
+    }
+    const double inu = inv_nu[r];
+    const double2 ckv = cc[(int64_t)k * R + r];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+        if (j < nr) {
+            const int64_t off = (n0 + j) * R + r;
+            const double2 d = csub(ld2(u + off), a[j]);
+            const double2 vk = make_double2(d.x * inu, d.y * inu);
+            const double2 wv = ld2(w + off);
+            const double2 un = csub(csub(make_double2(wv.x * inu, wv.y * inu), c[j]), cmul(ckv, vk));
+            st2(u + off, vk);
+            st2(w + off, un);
+        }
+    }
+}
+
 template <typename TB, int RPL>
 void launch_dcgs2_update_rpl(const TB* V, int64_t vs, int k, TB* u, TB* w, const double2* cs, const double2* cc,
                              const double* inv_nu, int64_t N, int R, int64_t rpc, int nchunk, hipStream_t s) {
@@ -544,6 +612,16 @@ void launch_dcgs2_dots(const TB* V, int64_t vs, int k, const TB* u, const TB* w,
 template <typename TB>
 void launch_dcgs2_update(const TB* V, int64_t vs, int k, TB* u, TB* w, const double2* cs, const double2* cc,
                          const double* inv_nu, int64_t N, int R, int64_t rpc, int nchunk, hipStream_t s) {
+    if (k >= 8) {
+        constexpr int RB = 8;
+        const int64_t rows_per_block = 4 * RB;
+        const int64_t gy = (N + rows_per_block - 1) / rows_per_block;
+        MBT_REQUIRE(gy < 65536, "dcgs2 update: too many row blocks");
+        hipLaunchKernelGGL((dcgs2_update_rows_kernel<TB, RB>), dim3((unsigned)((R + 63) / 64), (unsigned)gy),
+                           dim3(256), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R);
+        MBT_LAUNCH_CHECK();
+        return;
+    }
     if constexpr (sizeof(TB) == 8) {
         if (R % 2 == 0 && k <= 32) {
             launch_dcgs2_update_rpl<TB, 2>(V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc, nchunk, s);
