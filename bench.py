@@ -115,6 +115,28 @@ def cpu_baseline(w, side=20):
             "phases_s": {"fill": t_fill, "lu": t_lu, "solve": t_solve, "extract": t_ext}}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_dcgs2_update_dipole_32x32_m31_fp32.txt")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the dominant kernel class from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when
+    the summary does not cover this kernel or its source changed since."""
+    import hashlib
+    if kernel != "arnoldi_update_dots" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2608_17844_amd", "csrc", "gmres.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if not vals.get("kernel_source", "").endswith(sha):
+        return None
+    return float(vals["traffic_bytes_per_launch"].split()[0])
+
+
 def kernel_rooflines(mbt, ctx, arr, w, opts, classes):
     """One extra (untimed) step per kernel class with HIP-event timing of that
     class: algorithmic bytes / measured time, against the HBM peak."""
@@ -170,8 +192,10 @@ def headline(args):
             kernels = kernel_rooflines(mbt, ctx, arr, w, o32, ["arnoldi_dots", "fft_fwd_pad", "fft_inv_crop",
                                                                  "bin_product", "precond_apply"])
         achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof and prof["ms"] > 0 else None
+        traffic = measured_traffic(args.kernel)
         roofline = {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                    "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     "launches": prof["launches"] if prof else 0,
                     "avg_launch_ms": (prof["ms"] / prof["launches"]) if prof and prof["launches"] else None,
                     "alg_bytes_per_launch": (prof["bytes"] / prof["launches"]) if prof and prof["launches"] else None}
