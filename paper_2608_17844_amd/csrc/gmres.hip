@@ -219,12 +219,14 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 // ------------------------------------------------------------------ delayed reorthogonalisation (DCGS2)
 // Dot sweep: with u the candidate (slot k) and w = A u (slot k+1),
 //   s_i = V_i^H u, z_i = V_i^H w (i < k), alpha = u^H u, beta = u^H w.
-// Partials per chunk: [s_0..s_{k-1}, z_0..z_{k-1}, alpha, beta].
+// Partials per chunk: [s_0..s_{k-1}, z_0..z_{k-1}, alpha, beta].  One launch
+// covers the vectors i0 .. i0+nv-1 (the sweep may be split into launches of at
+// most NW*G vectors); alpha and beta come from the launch with i0 = 0.
 template <typename TB, int NW, int G, int RPL, bool HASW>
 __global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TB* __restrict__ V, int64_t vstride, int k,
-                                                             const TB* __restrict__ u, const TB* __restrict__ w,
-                                                             int64_t N, int R, int64_t rows_per_chunk,
-                                                             double2* __restrict__ partial) {
+                                                             int i0, int nv, const TB* __restrict__ u,
+                                                             const TB* __restrict__ w, int64_t N, int R,
+                                                             int64_t rows_per_chunk, double2* __restrict__ partial) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r0 = (blockIdx.x * 64 + lane) * RPL;
@@ -247,11 +249,12 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TB* __restric
         if (HASW) wr.load(w + off);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int i = wave + NW * g;
-            if (i < k) v[g].load(V + i * vstride + off);
+            const int j = wave + NW * g;
+            if (j < nv) v[g].load(V + (int64_t)(i0 + j) * vstride + off);
             else v[g].zero();
         }
     };
+    const bool ab_here = (i0 == 0) && (wave == 0);
     if (live && n0 < n1) load_row(n0, cur, cu, cw);
     for (int64_t n = n0; n < n1; ++n) {
         if (live && n + 1 < n1) load_row(n + 1, nxt, nu_, nw_);
@@ -266,7 +269,7 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TB* __restric
                     as[g][k2] = cadd(as[g][k2], cmulc(vv, uv));
                     if (HASW) az[g][k2] = cadd(az[g][k2], cmulc(vv, wv));
                 }
-                if (wave == 0) {
+                if (ab_here) {
                     aa[k2].x += uv.x * uv.x + uv.y * uv.y;
                     if (HASW) ab[k2] = cadd(ab[k2], cmulc(uv, wv));
                 }
@@ -280,15 +283,15 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TB* __restric
     if (!live) return;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int i = wave + NW * g;
-        if (i < k)
+        const int j = wave + NW * g;
+        if (j < nv)
 #pragma unroll
             for (int k2 = 0; k2 < RPL; ++k2) {
-                partial[(chunk * nred + i) * R + r0 + k2] = as[g][k2];
-                partial[(chunk * nred + k + i) * R + r0 + k2] = az[g][k2];
+                partial[(chunk * nred + i0 + j) * R + r0 + k2] = as[g][k2];
+                partial[(chunk * nred + k + i0 + j) * R + r0 + k2] = az[g][k2];
             }
     }
-    if (wave == 0)
+    if (ab_here)
 #pragma unroll
         for (int k2 = 0; k2 < RPL; ++k2) {
             partial[(chunk * nred + 2 * k) * R + r0 + k2] = aa[k2];
@@ -494,19 +497,24 @@ __global__ void dcgs2_coef_kernel(double2* __restrict__ Hraw, const double2* __r
 }
 
 template <typename TB, int RPL, bool HASW>
-void launch_dcgs2_dots_rpl(const TB* V, int64_t vs, int k, const TB* u, const TB* w, int64_t N, int R, int64_t rpc,
-                           int nchunk, double2* partial, hipStream_t s) {
+void launch_dcgs2_dots_rpl(const TB* V, int64_t vs, int k, int i0, int nv, const TB* u, const TB* w, int64_t N, int R,
+                           int64_t rpc, int nchunk, double2* partial, hipStream_t s) {
     const dim3 grid((unsigned)((R / RPL + 63) / 64), (unsigned)nchunk);
-    if (k <= 4)
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 1, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, u, w, N, R, rpc, partial);
-    else if (k <= 8)
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 2, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, u, w, N, R, rpc, partial);
-    else if (k <= 16)
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 4, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, u, w, N, R, rpc, partial);
-    else if (k <= 32)
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 8, 4, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, u, w, N, R, rpc, partial);
+    if (nv <= 4)
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 1, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, i0, nv, u, w, N, R,
+                           rpc, partial);
+    else if (nv <= 8)
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 2, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, i0, nv, u, w, N, R,
+                           rpc, partial);
+    else if (nv <= 16)
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 4, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, i0, nv, u, w, N, R,
+                           rpc, partial);
+    else if (nv <= 32)
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 8, 4, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, i0, nv, u, w, N, R,
+                           rpc, partial);
     else
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 8, 8, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, u, w, N, R, rpc, partial);
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 8, 8, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, i0, nv, u, w, N, R,
+                           rpc, partial);
     MBT_LAUNCH_CHECK();
 }
 
@@ -599,14 +607,19 @@ template <typename TB>
 void launch_dcgs2_dots(const TB* V, int64_t vs, int k, const TB* u, const TB* w, int64_t N, int R, int64_t rpc,
                        int nchunk, double2* partial, hipStream_t s) {
     if constexpr (sizeof(TB) == 8) {
-        if (R % 2 == 0 && k <= 32) {
-            if (w) launch_dcgs2_dots_rpl<TB, 2, true>(V, vs, k, u, w, N, R, rpc, nchunk, partial, s);
-            else launch_dcgs2_dots_rpl<TB, 2, false>(V, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+        if (R % 2 == 0) {
+            // FP32 pairs of RHS per lane (16-byte accesses) fit the register budget up to 32
+            // vectors per launch: longer sweeps are split, re-reading u and w once more
+            for (int i0 = 0; i0 == 0 || i0 < k; i0 += 32) {
+                const int nv = std::min(32, k - i0);
+                if (w) launch_dcgs2_dots_rpl<TB, 2, true>(V, vs, k, i0, nv, u, w, N, R, rpc, nchunk, partial, s);
+                else launch_dcgs2_dots_rpl<TB, 2, false>(V, vs, k, i0, nv, u, w, N, R, rpc, nchunk, partial, s);
+            }
             return;
         }
     }
-    if (w) launch_dcgs2_dots_rpl<TB, 1, true>(V, vs, k, u, w, N, R, rpc, nchunk, partial, s);
-    else launch_dcgs2_dots_rpl<TB, 1, false>(V, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+    if (w) launch_dcgs2_dots_rpl<TB, 1, true>(V, vs, k, 0, k, u, w, N, R, rpc, nchunk, partial, s);
+    else launch_dcgs2_dots_rpl<TB, 1, false>(V, vs, k, 0, k, u, w, N, R, rpc, nchunk, partial, s);
 }
 
 template <typename TB>
