@@ -3,10 +3,13 @@
 // normal-equation strategy, or GMRES with the element-block preconditioner).
 //
 // The paper uses MATLAB's GMRES and states no details; this solver fixes them:
-// x0 = 0; Arnoldi by classical Gram-Schmidt applied twice (CGS2); complex
-// Givens rotations (c real, s complex, c = 0 and s = 1 when the pivot is zero);
-// stop as soon as the least-squares residual |g_{j+1}| <= tol * ||b||; the
-// explicit residual b - A x is recomputed at every restart.
+// x0 = 0; Arnoldi by classical Gram-Schmidt with delayed reorthogonalisation
+// (DCGS2, Swirydowicz et al. 2021: the second projection of step k-1 is folded
+// into the dot sweep of step k, so each step sweeps the basis twice), or by
+// plain CGS2 in three sweeps on request; complex Givens rotations (c real,
+// s complex, c = 0 and s = 1 when the pivot is zero); stop as soon as the
+// least-squares residual |g_{j+1}| <= tol * ||b||; the explicit residual
+// b - A x is recomputed at every restart.
 //
 // Vectors are RHS-innermost, v[n][r]: a lane owns one RHS and walks rows, so
 // every per-RHS dot product is accumulated in a fixed order that does not
@@ -14,11 +17,14 @@
 // batched).  Rows are split into fixed chunks (a function of N only) whose
 // partial sums are reduced in chunk order by a second kernel.
 //
-// HBM traffic per Arnoldi step j is dominated by the basis reads.  CGS2 is
-// fused into three passes over V_{0..j}: (1) h = V^H w; (2) w <- w - V h
-// together with h2 = V^H w; (3) w <- w - V h2 together with ||w||^2.  The four
-// waves of a workgroup share the same rows and RHS and split the basis
-// vectors; the per-row combination is reduced across waves through LDS.
+// HBM traffic per Arnoldi step is dominated by the basis reads.  DCGS2 step k
+// reads V_{0..k-1}, the candidate u and w = A u once for all dot products
+// (s = V^H u, z = V^H w, u^H u, u^H w) and once more for the update that
+// writes the normalised v_k and the next candidate.  CGS2 is fused into three
+// passes: (1) h = V^H w; (2) w <- w - V h together with h2 = V^H w; (3)
+// w <- w - V h2 together with ||w||^2.  In the dot sweeps the waves of a
+// workgroup share rows and RHS and split the basis vectors; the DCGS2 update
+// gives each wave its own rows and all vectors.
 // The basis may be stored in FP32 (reduced-precision inner solves) while all
 // dot products, norms and the Hessenberg/Givens recurrences stay FP64.
 #include "common.h"
