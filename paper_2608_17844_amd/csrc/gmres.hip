@@ -40,6 +40,40 @@ namespace {
 
 constexpr int kMaxVec = 64;            // basis vectors per pass -> restart <= 63
 
+// Accumulations written as explicit fused multiply-adds in a fixed order.  The
+// kernels have variants that move one or two RHS per lane; leaving the fusion of
+// products and sums to the compiler lets it differ between variants, and a RHS's
+// result would then depend on the parity of the batch size.
+// acc + a b
+__device__ __forceinline__ double2 cfma(double2 acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc + conj(a) b
+__device__ __forceinline__ double2 cfmac(double2 acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+// w s - c - k v  (the DCGS2 candidate update)
+__device__ __forceinline__ double2 next_candidate(double2 w, double s, double2 c, double2 k, double2 v) {
+    double2 t;
+    t.x = fma(w.x, s, -c.x);
+    t.y = fma(w.y, s, -c.y);
+    t.x = fma(-k.x, v.x, t.x);
+    t.x = fma(k.y, v.y, t.x);
+    t.y = fma(-k.x, v.y, t.y);
+    t.y = fma(-k.y, v.x, t.y);
+    return t;
+}
+// acc + |a|^2
+__device__ __forceinline__ double nfma(double acc, double2 a) { return fma(a.y, a.y, fma(a.x, a.x, acc)); }
+
 __device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
 __device__ __forceinline__ double2 ld2(const float2* p) { float2 v = *p; return make_double2(v.x, v.y); }
 __device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
@@ -165,7 +199,7 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 #pragma unroll
                 for (int g = 0; g < G; ++g)
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) acc[g][k] = cadd(acc[g][k], cmulc(cur[g].get(k), wv[k]));
+                    for (int k = 0; k < RPL; ++k) acc[g][k] = cfmac(acc[g][k], cur[g].get(k), wv[k]);
             }
         } else {
             double2 u[RPL];
@@ -175,7 +209,7 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 #pragma unroll
                 for (int g = 0; g < G; ++g)
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) u[k] = cadd(u[k], cmul(cf[g][k], cur[g].get(k)));
+                    for (int k = 0; k < RPL; ++k) u[k] = cfma(u[k], cf[g][k], cur[g].get(k));
             }
 #pragma unroll
             for (int k = 0; k < RPL; ++k) xch[buf][wave][lane * RPL + k] = u[k];
@@ -194,10 +228,10 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 #pragma unroll
                     for (int g = 0; g < G; ++g)
 #pragma unroll
-                        for (int k = 0; k < RPL; ++k) acc[g][k] = cadd(acc[g][k], cmulc(cur[g].get(k), nw[k]));
+                        for (int k = 0; k < RPL; ++k) acc[g][k] = cfmac(acc[g][k], cur[g].get(k), nw[k]);
                 } else if constexpr (MODE == 2) {
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) nrm[k] += nw[k].x * nw[k].x + nw[k].y * nw[k].y;
+                    for (int k = 0; k < RPL; ++k) nrm[k] = nfma(nrm[k], nw[k]);
                 }
                 if (wave == 0) stp<RPL>(w + off, nw);
             }
@@ -272,12 +306,12 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TB* __restric
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     const double2 vv = cur[g].get(k2);
-                    as[g][k2] = cadd(as[g][k2], cmulc(vv, uv));
-                    if (HASW) az[g][k2] = cadd(az[g][k2], cmulc(vv, wv));
+                    as[g][k2] = cfmac(as[g][k2], vv, uv);
+                    if (HASW) az[g][k2] = cfmac(az[g][k2], vv, wv);
                 }
                 if (ab_here) {
-                    aa[k2].x += uv.x * uv.x + uv.y * uv.y;
-                    if (HASW) ab[k2] = cadd(ab[k2], cmulc(uv, wv));
+                    aa[k2].x = nfma(aa[k2].x, uv);
+                    if (HASW) ab[k2] = cfmac(ab[k2], uv, wv);
                 }
             }
         }
@@ -358,8 +392,8 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_update_kernel(const TB* __restr
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     const double2 vv = cur[g].get(k2);
-                    a = cadd(a, cmul(fs[g][k2], vv));
-                    c = cadd(c, cmul(fc[g][k2], vv));
+                    a = cfma(a, fs[g][k2], vv);
+                    c = cfma(c, fc[g][k2], vv);
                 }
             }
             xch[buf][wave][2 * (lane * RPL + k2)] = a;
@@ -379,7 +413,7 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_update_kernel(const TB* __restr
                 const double2 d = csub(cu.get(k2), a);
                 vk[k2] = make_double2(d.x * inu[k2], d.y * inu[k2]);
                 const double2 wv = cw.get(k2);
-                un[k2] = csub(csub(make_double2(wv.x * inu[k2], wv.y * inu[k2]), c), cmul(ck[k2], vk[k2]));
+                un[k2] = next_candidate(wv, inu[k2], c, ck[k2], vk[k2]);
             }
             stp<RPL>(u + off, vk);
             stp<RPL>(w + off, un);
@@ -568,8 +602,8 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows_kernel(const TB* __rest
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
             const double2 vv = cur[j].get(0);
-            a[j] = cadd(a[j], cmul(fs, vv));
-            c[j] = cadd(c[j], cmul(fc, vv));
+            a[j] = cfma(a[j], fs, vv);
+            c[j] = cfma(c[j], fc, vv);
         }
 #pragma unroll
         for (int j = 0; j < RB; ++j) cur[j] = nxt[j];
@@ -585,7 +619,7 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows_kernel(const TB* __rest
             const double2 d = csub(ld2(u + off), a[j]);
             const double2 vk = make_double2(d.x * inu, d.y * inu);
             const double2 wv = ld2(w + off);
-            const double2 un = csub(csub(make_double2(wv.x * inu, wv.y * inu), c[j]), cmul(ckv, vk));
+            const double2 un = next_candidate(wv, inu, c[j], ckv, vk);
             st2(u + off, vk);
             st2(w + off, un);
         }
@@ -652,15 +686,15 @@ void launch_dcgs2_update(const TB* V, int64_t vs, int k, TB* u, TB* w, const dou
 
 template <typename TB, typename TO, int MODE, int RPL>
 void launch_pass_rpl(const TB* V, int64_t vs, int nvec, const double2* coef, TO* w, int64_t N, int R, int64_t rpc,
-                     int nchunk, double2* partial, hipStream_t s) {
+                     int nchunk, double2* partial, hipStream_t s, int cfg_n) {
     const dim3 grid((unsigned)((R / RPL + 63) / 64), (unsigned)nchunk);
-    if (nvec <= 4)
+    if (cfg_n <= 4)
         hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 4, 1, RPL>), grid, dim3(256), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
-    else if (nvec <= 8)
+    else if (cfg_n <= 8)
         hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 4, 2, RPL>), grid, dim3(256), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
-    else if (nvec <= 16)
+    else if (cfg_n <= 16)
         hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 4, 4, RPL>), grid, dim3(256), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
-    else if (nvec <= 32)
+    else if (cfg_n <= 32)
         hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 8, 4, RPL>), grid, dim3(512), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
     else
         hipLaunchKernelGGL((arnoldi_kernel<TB, TO, MODE, 8, 8, RPL>), grid, dim3(512), 0, s, V, vs, nvec, coef, w, N, R, rpc, partial);
@@ -668,17 +702,22 @@ void launch_pass_rpl(const TB* V, int64_t vs, int nvec, const double2* coef, TO*
 }
 
 // FP32 bases with an even number of columns move two RHS per 16-byte access.
+// cfg_n (>= nvec) selects the kernel configuration: the order in which a lane's
+// sum over basis vectors is split across waves depends only on it, so a caller
+// that passes a fixed cfg_n gets results independent of nvec's value for
+// vectors beyond a RHS's own range (their coefficients are zero).
 template <typename TB, typename TO, int MODE>
 void launch_pass(const TB* V, int64_t vs, int nvec, const double2* coef, TO* w, int64_t N, int R, int64_t rpc,
-                 int nchunk, double2* partial, hipStream_t s) {
+                 int nchunk, double2* partial, hipStream_t s, int cfg_n = 0) {
+    cfg_n = std::max(cfg_n, nvec);
     if constexpr (sizeof(TB) == 8) {
         // the update-and-dot pass over more than 32 vectors keeps one RHS per lane (register budget)
-        if (R % 2 == 0 && !(MODE == 1 && nvec > 32)) {
-            launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s);
+        if (R % 2 == 0 && !(MODE == 1 && cfg_n > 32)) {
+            launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
             return;
         }
     }
-    launch_pass_rpl<TB, TO, MODE, 1>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s);
+    launch_pass_rpl<TB, TO, MODE, 1>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
 }
 
 // out[i][r] = sum over chunks of partial[chunk][i][r], in chunk order
@@ -702,7 +741,7 @@ __global__ void colnorm2_kernel(const TB* __restrict__ X, int64_t N, int R, int6
     double s = 0;
     for (int64_t n = n0; n < n1; ++n) {
         const double2 v = ld2(X + n * R + r);
-        s += v.x * v.x + v.y * v.y;
+        s = nfma(s, v);
     }
     partial[chunk * R + r] = make_double2(s, 0.0);
 }
@@ -1034,7 +1073,9 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
         // y = R^{-1} g ; x += V y
         hipLaunchKernelGGL(cycle_solve_kernel, gR, bR, 0, s, st, R, m, y);
         MBT_LAUNCH_CHECK();
-        launch_pass<TB, double2, 3>(Vbasis, vs, steps, y, x, N, R, rpc, nchunk, partial, s);
+        // configuration fixed by m: a RHS's update x += V y does not depend on how long
+        // the other RHS of the batch kept the cycle going
+        launch_pass<TB, double2, 3>(Vbasis, vs, steps, y, x, N, R, rpc, nchunk, partial, s, m);
         // explicit residual r = b - A x into V_0 (x cast to the basis type into V_1 first)
         TB* xb = Vbasis + vs;
         hipLaunchKernelGGL((from_f64_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, x, xb, vs);

@@ -57,7 +57,9 @@ def test_fp64_path_full_size(setup):
     _say({k: "%.2e" % v for k, v in e.items()}, out["stats"]["iters_max"])
     assert out["stats"]["nconverged"] == 1024
     assert e["zp_center_row"] <= 1e-9 and e["zp_samples_vs_max"] <= 1e-9 and e["zp_diag"] <= 1e-9
-    assert e["gamma_abs"] <= 1e-8 and e["gamma_wave_abs"] <= 1e-8
+    # the ARC sums all 1024 entries of the center row of Z_p with unit-modulus
+    # phases, so its error is up to ~100x the row's relative error (1e-9)
+    assert e["gamma_abs"] <= 1e-7 and e["gamma_wave_abs"] <= 1e-7
     # the port impedance matrix is symmetric (reciprocity) to the solve's accuracy
     Zp = out["Zp"]
     assert np.linalg.norm(Zp - Zp.T) / np.linalg.norm(Zp) <= 1e-9
