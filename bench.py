@@ -118,10 +118,11 @@ def cpu_baseline(w, side=20):
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_dcgs2_update_dipole_32x32_m31_fp32.txt")
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, restart):
     """HBM bytes per launch of the dominant kernel class from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when
-    the summary does not cover this kernel or its source changed since."""
+    the summary does not cover this kernel and configuration or the kernel
+    source changed since."""
     import hashlib
     if kernel != "arnoldi_update_dots" or not os.path.exists(TRAFFIC_PROFILE):
         return None
@@ -132,7 +133,7 @@ def measured_traffic(kernel):
             vals[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_2608_17844_amd", "csrc", "gmres.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if not vals.get("kernel_source", "").endswith(sha):
+    if not vals.get("kernel_source", "").endswith(sha) or vals.get("restart") != str(restart):
         return None
     return float(vals["traffic_bytes_per_launch"].split()[0])
 
@@ -167,7 +168,7 @@ def headline(args):
     P = w.lattice.nx * w.lattice.ny
     result = {}
     try:
-        o32 = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=pc, restart=w.restart, refine_tol=args.refine_tol,
+        o32 = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=pc, restart=args.restart, refine_tol=args.refine_tol,
                                    inner_tol=args.inner_tol, flags=mbt.MBT_FLAG_NO_CACHE)
         log("fp32-mfma path: warmup %d, steps %d" % (args.warmup, args.steps))
         total, times, out, prof = run_steps(mbt, ctx, arr, w, o32, args.steps, args.warmup, args.kernel)
@@ -177,12 +178,13 @@ def headline(args):
         log("fp32: %.3f s/step  %.1f solves/s  err %s" % (total / args.steps, value, err32))
         fp64 = None
         if not args.no_fp64:
-            o64 = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=pc, restart=w.restart, tol=args.fp64_tol,
+            o64 = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=pc, restart=args.fp64_restart, tol=args.fp64_tol,
                                        flags=mbt.MBT_FLAG_NO_CACHE)
             log("fp64 path (tol %g): warmup %d, steps %d" % (args.fp64_tol, args.warmup, args.steps))
             t64, times64, out64, _ = run_steps(mbt, ctx, arr, w, o64, args.steps, args.warmup)
             err64 = zp_errors(out64, ref)
             fp64 = {"value": P * args.steps / t64, "ms_per_step": 1e3 * t64 / args.steps, "tol": args.fp64_tol,
+                    "restart": args.fp64_restart,
                     "errors": err64, "iters_max": out64["stats"]["iters_max"],
                     "matvecs": out64["stats"]["matvecs"]}
             log("fp64: %.3f s/step  %.1f solves/s  err %s" % (t64 / args.steps, fp64["value"], err64))
@@ -192,7 +194,7 @@ def headline(args):
             kernels = kernel_rooflines(mbt, ctx, arr, w, o32, ["arnoldi_dots", "fft_fwd_pad", "fft_inv_crop",
                                                                  "bin_product", "precond_apply"])
         achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof and prof["ms"] > 0 else None
-        traffic = measured_traffic(args.kernel)
+        traffic = measured_traffic(args.kernel, args.restart)
         roofline = {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -206,7 +208,7 @@ def headline(args):
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": w.name, "nx": w.lattice.nx, "ny": w.lattice.ny, "nbases": w.dipole.nbases,
                        "unknowns": P * w.dipole.nbases, "ports": P, "nscan": int(len(w.theta)),
-                       "preconditioner": args.pc, "restart": w.restart,
+                       "preconditioner": args.pc, "restart": args.restart, "fp64_restart": args.fp64_restart,
                        "precision": "FP32 lattice FFT + FP32 MFMA block products, FP32-stored Krylov basis with "
                                     "FP64 dot products/Givens, FP64 refinement residual and extraction",
                        "refine_tol": args.refine_tol, "inner_tol": args.inner_tol,
@@ -363,6 +365,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--pc", choices=["element_block", "normal_eq"], default="element_block")
     ap.add_argument("--kernel", choices=sorted(KERNEL_CODES), default="arnoldi_update_dots")
+    ap.add_argument("--restart", type=int, default=32, help="restart length of the mixed path's inner GMRES")
+    ap.add_argument("--fp64-restart", type=int, default=50, help="restart length of the FP64 path (the workload's)")
     ap.add_argument("--refine-tol", type=float, default=1e-7, help="FP64 refinement stop of the mixed path")
     ap.add_argument("--inner-tol", type=float, default=1e-3, help="inner FP32 GMRES tolerance of the mixed path")
     ap.add_argument("--fp64-tol", type=float, default=1e-9,

@@ -78,10 +78,10 @@ def test_port_admittance_columns_full_size(setup):
 
 
 def test_mixed_path_full_size_in_bench_configuration(setup):
-    """FP32 products, inner tolerance 1e-3, FP64 refinement to 1e-7: Z_p
+    """FP32 products, inner GMRES(32) to 1e-3, FP64 refinement to 1e-7: Z_p
     entries and the center ARC within 1e-6 relative of the oracle."""
     mbt, ctx, arr, w, ref = setup
-    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=50, refine_tol=1e-7,
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=32, refine_tol=1e-7,
                                 inner_tol=1e-3, flags=mbt.MBT_FLAG_NO_CACHE)
     out = mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
     e = _errors(out, ref)
