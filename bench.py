@@ -246,8 +246,8 @@ def serve(args):
 
     ctx = mbt.mbt_ctx_create(0)
     srv = mbt.mbt_server_create(ctx, args.slots)
-    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, refine_tol=args.refine_tol,
-                                inner_tol=args.inner_tol, max_cycles=args.serve_max_cycles)
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=args.restart,
+                                refine_tol=args.refine_tol, inner_tol=args.inner_tol, max_cycles=args.serve_max_cycles)
 
     def submit(r):
         return mbt.mbt_server_submit(srv, (r.dipole.length, r.dipole.radius, r.dipole.nbases),
@@ -293,16 +293,18 @@ def serve(args):
         bad = sum(1 for x in res if x["status"] != mbt.MBT_OK)
         log("serving: saturation %.2f requests/s, %.1f solves/s (%d not converged)" % (sat_rate, sat_solves, bad))
         rate = args.load * sat_rate
-        reqs = W.serving_stream(args.serve, rate, seed=0)
-        log("serving: Poisson stream at %.2f requests/s (%.0f%% of saturation)" % (rate, 100 * args.load))
-        t0 = mbt.mbt_server_clock(srv)
-        tickets = []
-        for r in reqs:
-            dt = t0 + r.arrival - mbt.mbt_server_clock(srv)
-            if dt > 0:
-                time.sleep(dt)
-            tickets.append(submit(r))
-        res = collect(tickets, reqs, t0)
+        if args.load > 0:
+            reqs = W.serving_stream(args.serve, rate, seed=0)
+            log("serving: Poisson stream at %.2f requests/s (%.0f%% of saturation)" % (rate, 100 * args.load))
+            t0 = mbt.mbt_server_clock(srv)
+            tickets = []
+            for r in reqs:
+                dt = t0 + r.arrival - mbt.mbt_server_clock(srv)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append(submit(r))
+            res = collect(tickets, reqs, t0)
+        # with --load 0 the latencies reported are those of the saturation run
         lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
         wait = np.array([x["t_start"] - x["t_submit"] for x in res]) * 1e3
         span = max(x["t_done"] for x in res) - t0
@@ -317,7 +319,7 @@ def serve(args):
             "config": {"workload": "dipole_serving_stream", "requests": len(reqs), "warmup_requests": len(warm),
                        "slots": args.slots, "rate_rps": rate, "load_vs_saturation": args.load,
                        "nx_ny": [8, 48], "nbases": [15, 31], "nfreq": [1, 8], "nscan": [1, 64],
-                       "refine_tol": args.refine_tol, "inner_tol": args.inner_tol,
+                       "restart": args.restart, "refine_tol": args.refine_tol, "inner_tol": args.inner_tol,
                        "max_cycles": args.serve_max_cycles},
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "mean": float(lat.mean()), "queue_wait_p50": float(np.percentile(wait, 50))},
@@ -379,7 +381,8 @@ def main():
     ap.add_argument("--serve-max-cycles", type=int, default=8,
                     help="restart cycles per inner solve in the serving run (slow-converging requests report ENOCONV)")
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--load", type=float, default=0.8, help="stream rate as a fraction of saturation")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="stream rate as a fraction of saturation (0: report the saturation run only)")
     ap.add_argument("--sweep", action="store_true", help="run the 21-frequency precision sweep instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy kernel three times (a known-size reference "

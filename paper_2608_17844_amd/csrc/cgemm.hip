@@ -137,6 +137,9 @@ void launch_mp(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, 
     const int ntiles = (R + 15) / 16;
     const int64_t total = nbatch * ntiles;
     int tpw = (int)std::max<int64_t>(1, std::min<int64_t>(8, total / 32768));
+    // one block shared by every batch entry (the element-block preconditioner):
+    // longer runs of tiles per wave amortise loading its fragments
+    if (strideA == 0) tpw = 8;
     tpw = std::min(tpw, ntiles);
     const int groups = (ntiles + 4 * tpw - 1) / (4 * tpw);
     const int64_t blocks = nbatch * groups;
