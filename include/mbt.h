@@ -133,6 +133,17 @@ const char* mbt_version(void);
  * nx/ny < 1 or > 1024, dx/dy <= 0. */
 mbt_status mbt_array_create_dipole(mbt_ctx* ctx, const mbt_dipole* elem, const mbt_lattice* lat,
                                    mbt_array** out);
+/* Array whose operator is given by its unique lattice blocks instead of an
+ * element fill (Sec. II-A: one M x M block per offset between a test and a
+ * source element).  T holds (2ny-1)(2nx-1) blocks of nbases x nbases complex
+ * values, T[((dy+ny-1)*(2nx-1) + (dx+nx-1))*M*M + p*M + q] the coupling of
+ * basis p of an element to basis q of the element -d = (-dx, -dy) away, i.e.
+ * Z[t][s] = T[t - s]; copied at the call.  The operator does not depend on
+ * freq_ratio.  Port j is basis (M-1)/2 of element j.  Limits: nbases 1..128,
+ * nx, ny 1..64; more than 32 bases: element-block preconditioner, FP64 or FP32
+ * products, no scans.  Errors: MBT_EINVAL (sizes, non-finite values). */
+mbt_status mbt_array_create_blocks(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t nbases, const double* T,
+                                   mbt_array** out);
 void mbt_array_destroy(mbt_array* arr);
 
 /* Sizes: unknowns N = nx*ny*M, ports P = nx*ny, FFT grid (gx, gy) >= (2nx-1, 2ny-1). */

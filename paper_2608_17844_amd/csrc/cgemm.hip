@@ -153,6 +153,121 @@ void launch_mp(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, 
     MBT_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------- large blocks (M up to 128)
+// Blocks too large for register-resident fragments: one workgroup per batch
+// entry and group of up to four 16-column tiles; A is staged through LDS in
+// chunks of KC complex columns, the four waves split the 16-row tiles of the
+// real 2M x 2M product, and the X fragments are read straight from memory.  At
+// M = 96 and 32 columns a bin moves 123 KB (FP32) for 2.4 MFLOP, at the FP32
+// MFMA ridge.
+template <typename T, int MP, bool HERM>
+__global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restrict__ A, int64_t strideA,
+                                                        const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Y, int M,
+                                                        int R) {
+    using C = cplx<T>;
+    using V = typename Acc<T>::type;
+    constexpr int KC = 32;         // complex K per LDS stage
+    constexpr int NRT = MP / 8;    // 16-row tiles of the 2MP-row real matrix
+    constexpr int RTW = NRT / 4;   // row tiles per wave
+    constexpr int CT = 4;          // column tiles per workgroup
+    constexpr int LDA = KC + 1;
+    __shared__ C As[MP * LDA];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int li = lane & 15;
+    const int64_t b = blockIdx.x;
+    const int ct0 = blockIdx.y * CT;
+    const int ntiles = (R + 15) >> 4;
+    const int nct = min(CT, ntiles - ct0);
+    const C* Ab = A + b * strideA;
+    const C* Xb = X + b * (int64_t)M * R;
+    C* Yb = Y + b * (int64_t)M * R;
+
+    // real row of tile t held by lane li -> (p, re/im), as in cgemm_kernel
+    int pr[RTW];
+    bool oddr[RTW];
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+        const int t = wave + 4 * i;
+        if constexpr (sizeof(T) == 8) {
+            const int v = li >> 2, gg = li & 3;
+            pr[i] = 8 * t + 2 * gg + (v >> 1);
+            oddr[i] = v & 1;
+        } else {
+            const int rho = 16 * t + li;
+            pr[i] = rho >> 1;
+            oddr[i] = rho & 1;
+        }
+    }
+    V acc[RTW][CT];
+#pragma unroll
+    for (int i = 0; i < RTW; ++i)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[i][c] = V{0, 0, 0, 0};
+
+    for (int kc = 0; kc < M; kc += KC) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < MP * KC; e += 256) {
+            const int p = e / KC, j = e - p * KC, q = kc + j;
+            C c = mk<T>(0, 0);
+            if (p < M && q < M) {
+                c = HERM ? Ab[(int64_t)q * M + p] : Ab[(int64_t)p * M + q];
+                if (HERM) c.y = -c.y;
+            }
+            As[p * LDA + j] = c;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int s4 = 0; s4 < KC / 4; ++s4) {
+            const int q = kc + 4 * s4 + g;
+            C bv[CT];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int col = (ct0 + c) * 16 + li;
+                bv[c] = (c < nct && q < M && col < R) ? Xb[(int64_t)q * R + col] : mk<T>(0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < RTW; ++i) {
+                const C a = As[pr[i] * LDA + 4 * s4 + g];
+                const T are = oddr[i] ? a.y : a.x;
+                const T aim = oddr[i] ? a.x : -a.y;
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    acc[i][c] = mfma(are, bv[c].x, acc[i][c]);
+                    acc[i][c] = mfma(aim, bv[c].y, acc[i][c]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+        const int p0 = 8 * (wave + 4 * i) + 2 * g;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int col = (ct0 + c) * 16 + li;
+            if (c < nct && col < R) {
+                if (p0 < M) Yb[(int64_t)p0 * R + col] = mk<T>(acc[i][c][0], acc[i][c][1]);
+                if (p0 + 1 < M) Yb[(int64_t)(p0 + 1) * R + col] = mk<T>(acc[i][c][2], acc[i][c][3]);
+            }
+        }
+    }
+}
+
+template <typename T, int MP>
+void launch_big(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R, int64_t nbatch, int op,
+                hipStream_t s) {
+    const int ntiles = (R + 15) / 16;
+    const int groups = (ntiles + 3) / 4;
+    MBT_REQUIRE(nbatch < (1LL << 31) && groups < 65536, "cgemm: grid too large");
+    const dim3 grid((unsigned)nbatch, (unsigned)groups);
+    if (op == 0)
+        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, false>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
+    else
+        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, true>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
+    MBT_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------- 16-bit inputs
 // The same real formulation on the 16x16x16 MFMA with 16-bit inputs and FP32
 // accumulation.  A lane supplies four consecutive K values; with K interleaving
@@ -293,7 +408,10 @@ void cgemm_batched(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>*
     if (nbatch <= 0 || R <= 0) return;
     if (M <= 16) launch_mp<T, 16>(A, strideA, X, Y, M, R, nbatch, op, s);
     else if (M <= 32) launch_mp<T, 32>(A, strideA, X, Y, M, R, nbatch, op, s);
-    else throw Error(-1, "cgemm: block size above 32 is not supported");
+    else if (M <= 64) launch_big<T, 64>(A, strideA, X, Y, M, R, nbatch, op, s);
+    else if (M <= 96) launch_big<T, 96>(A, strideA, X, Y, M, R, nbatch, op, s);
+    else if (M <= kMaxBlockM) launch_big<T, 128>(A, strideA, X, Y, M, R, nbatch, op, s);
+    else throw Error(-1, "cgemm: block size above 128 is not supported");
 }
 
 template void cgemm_batched<double>(const double2*, int64_t, const double2*, double2*, int, int, int64_t, int, hipStream_t);

@@ -130,6 +130,9 @@ class ProfScope {
     double bytes_, flops_;
 };
 
+// largest basis count per element of the block products (block-defined arrays)
+constexpr int kMaxBlockM = 128;
+
 // ------------------------------------------------------------------ geometry
 struct Geom {
     int nx = 0, ny = 0, M = 0;     // lattice size, bases per element

@@ -89,6 +89,10 @@ struct mbt_array {
     mbt::Geom g;
     mbt_dipole elem;
     mbt_lattice lat;
+    // arrays defined by caller-supplied unique blocks (no element fill): host copy
+    // of T[dy][dx][p][q] and an identity for the operator cache
+    std::shared_ptr<const std::vector<double2>> blocks;
+    uint64_t uid = 0;
 };
 
 struct mbt_ctx {
@@ -105,10 +109,12 @@ struct mbt_ctx {
 namespace mbt {
 
 Geom make_geom(const mbt_dipole& d, const mbt_lattice& l);
+// Geometry of a block-defined lattice operator (nx x ny elements, M bases each).
+Geom make_geom_blocks(int nx, int ny, int M);
 void validate_opts(const mbt_solve_opts& o);
 // Cached operator data; need_pa adds the normal-equation preconditioner, prec
 // adds the copies that a reduced-precision inner solve reads.
-std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_pa, int prec, Worker& wk);
+std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const mbt_array* arr, double s, bool need_pa, int prec, Worker& wk);
 // 16-bit storage format of a precision (kFmtNone for FP64 and FP32).
 int fmt16_of(int prec);
 size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o);

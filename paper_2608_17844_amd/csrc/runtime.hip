@@ -4,6 +4,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <sstream>
@@ -104,6 +105,26 @@ Geom make_geom(const mbt_dipole& d, const mbt_lattice& l) {
     return g;
 }
 
+Geom make_geom_blocks(int nx, int ny, int M) {
+    MBT_REQUIRE(M >= 1 && M <= kMaxBlockM, "nbases must be within 1..128 for a block-defined array");
+    MBT_REQUIRE(nx >= 1 && ny >= 1 && nx <= 64 && ny <= 64, "lattice size must be within 1..64 per axis");
+    Geom g;
+    g.nx = nx;
+    g.ny = ny;
+    g.M = M;
+    g.dx = g.dy = 0.5;   // nominal: the blocks carry the geometry
+    g.P = nx * ny;
+    g.N = (int64_t)g.P * g.M;
+    g.Lx = pow2_at_least(nx, 8);
+    g.Ly = pow2_at_least(ny, 8);
+    g.Px = 2 * g.Lx;
+    g.Py = 2 * g.Ly;
+    g.nox = 2 * nx - 1;
+    g.noy = 2 * ny - 1;
+    g.pc = (M - 1) / 2;
+    return g;
+}
+
 void validate_opts(const mbt_solve_opts& o) {
     MBT_REQUIRE(o.prec == MBT_FP64 || o.prec == MBT_FP32 || o.prec == MBT_BF16 || o.prec == MBT_FP16,
                 "unknown precision");
@@ -124,15 +145,18 @@ static double inner_tol(const mbt_solve_opts& o) {
 int fmt16_of(int prec) { return prec == MBT_BF16 ? kFmtBf16 : prec == MBT_FP16 ? kFmtF16 : kFmtNone; }
 
 // ------------------------------------------------------------------ operator cache
-static std::string op_key(const Geom& g, double s) {
+static std::string op_key(const mbt_array* arr, double s) {
+    const Geom& g = arr->g;
     std::ostringstream os;
     os.precision(17);
+    if (arr->blocks) os << "blocks#" << arr->uid << ',';
     os << g.nx << ',' << g.ny << ',' << g.M << ',' << g.dx << ',' << g.dy << ',' << g.L << ',' << g.a << ',' << s;
     return os.str();
 }
 
 static void build_pa(OpData& op, Worker& wk) {
     const Geom& g = op.g;
+    MBT_REQUIRE(g.M <= 32, "the normal-equation preconditioner supports at most 32 bases per element");
     const int64_t MM = (int64_t)g.M * g.M;
     DBuf G, Pb, info;
     G.alloc(sizeof(double2) * g.noff() * MM);
@@ -190,14 +214,20 @@ static void build_16(OpData& op, int fmt, Worker& wk) {
     op.scale16[fmt] = scale;
 }
 
-static std::shared_ptr<OpData> build_op(const Geom& g, double s, Worker& wk) {
+static std::shared_ptr<OpData> build_op(const mbt_array* arr, double s, Worker& wk) {
+    const Geom& g = arr->g;
     auto op = std::make_shared<OpData>();
     op->g = g;
     op->s = s;
     op->k = 2.0 * M_PI * s;
     const int64_t MM = (int64_t)g.M * g.M;
     op->T.alloc(sizeof(double2) * g.noff() * MM);
-    fill_blocks(g, op->k, op->T.as<double2>(), wk.stream);
+    if (arr->blocks) {
+        MBT_REQUIRE((int64_t)arr->blocks->size() == g.noff() * MM, "block array size mismatch");
+        MBT_HIP(hipMemcpyAsync(op->T.p, arr->blocks->data(), op->T.bytes, hipMemcpyHostToDevice, wk.stream));
+    } else {
+        fill_blocks(g, op->k, op->T.as<double2>(), wk.stream);
+    }
     op->Chat.alloc(sizeof(double2) * g.bins() * MM);
     {
         DBuf scratch;
@@ -210,23 +240,37 @@ static std::shared_ptr<OpData> build_op(const Geom& g, double s, Worker& wk) {
     make_twiddles(g.Px, op->tw.as<double2>(), wk.stream);
     make_twiddles(g.Py, op->tw.as<double2>() + g.Px, wk.stream);
     // P_K: inverse of the self block (offset 0)
-    DBuf info;
-    info.alloc(sizeof(int));
     op->PkInv.alloc(sizeof(double2) * MM);
     const int64_t center = (int64_t)(g.ny - 1) * g.nox + (g.nx - 1);
-    batched_inverse(op->T.as<double2>() + center * MM, op->PkInv.as<double2>(), g.M, 1, false, info.as<int>(), wk.stream);
-    int hinfo = 0;
-    MBT_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, wk.stream));
-    MBT_HIP(hipStreamSynchronize(wk.stream));
-    MBT_REQUIRE(hinfo == 0, "element self block is singular");
+    if (g.M <= 32) {
+        DBuf info;
+        info.alloc(sizeof(int));
+        batched_inverse(op->T.as<double2>() + center * MM, op->PkInv.as<double2>(), g.M, 1, false, info.as<int>(),
+                        wk.stream);
+        int hinfo = 0;
+        MBT_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, wk.stream));
+        MBT_HIP(hipStreamSynchronize(wk.stream));
+        MBT_REQUIRE(hinfo == 0, "element self block is singular");
+    } else {
+        // larger blocks: the general Gauss-Jordan inverse on a copy of the self block
+        DBuf work;
+        work.alloc(sizeof(double2) * (MM + g.M) + sizeof(int) * (g.M + 8));
+        double2* A = work.as<double2>();
+        MBT_HIP(hipMemcpyAsync(A, op->T.as<double2>() + center * MM, sizeof(double2) * MM, hipMemcpyDeviceToDevice,
+                               wk.stream));
+        int* piv = reinterpret_cast<int*>(A + MM + g.M);
+        gj_inverse(A, op->PkInv.as<double2>(), g.M, A + MM, piv, piv + g.M, wk.stream);
+        MBT_HIP(hipStreamSynchronize(wk.stream));
+    }
     return op;
 }
 
-std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_pa, int prec, Worker& wk) {
+std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const mbt_array* arr, double s, bool need_pa, int prec, Worker& wk) {
     const bool need32 = prec != MBT_FP64;
     const int fmt = fmt16_of(prec);
     MBT_REQUIRE(s > 0 && std::isfinite(s), "freq_ratio must be positive");
-    const std::string key = op_key(g, s);
+    MBT_REQUIRE(fmt == kFmtNone || arr->g.M <= 32, "16-bit products support at most 32 bases per element");
+    const std::string key = op_key(arr, s);
     std::shared_ptr<OpData> op;
     {
         std::lock_guard<std::mutex> lk(ctx->cache_mu);
@@ -238,7 +282,7 @@ std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const Geom& g, double s, bool need_
         }
     }
     if (!op) {
-        op = build_op(g, s, wk);
+        op = build_op(arr, s, wk);
         std::lock_guard<std::mutex> lk(ctx->cache_mu);
         auto it = ctx->cache.find(key);
         if (it != ctx->cache.end()) {
@@ -587,12 +631,13 @@ SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t*
     const double t0 = now_s();
     std::shared_ptr<OpData> op;
     if (o.flags & MBT_FLAG_NO_CACHE) {
-        op = build_op(g, s, wk);
+        MBT_REQUIRE(fmt16_of(o.prec) == kFmtNone || g.M <= 32, "16-bit products support at most 32 bases per element");
+        op = build_op(arr, s, wk);
         if (o.pc == MBT_PC_NORMAL_EQ) build_pa(*op, wk);
         if (o.prec != MBT_FP64) build_32(*op, wk);
         if (fmt16_of(o.prec) != kFmtNone) build_16(*op, fmt16_of(o.prec), wk);
     } else {
-        op = get_op(ctx, g, s, o.pc == MBT_PC_NORMAL_EQ, o.prec, wk);
+        op = get_op(ctx, arr, s, o.pc == MBT_PC_NORMAL_EQ, o.prec, wk);
     }
     MBT_HIP(hipStreamSynchronize(wk.stream));
     const double t1 = now_s();
@@ -647,6 +692,7 @@ SolveOut solve_frequency(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt
                          const double* theta, const double* phi, int nscan, double z0, double* Zp, double* Za,
                          double* Gamma, double* Gamma_wave, Worker& wk, mbt_stats* st) {
     const Geom& g = arr->g;
+    MBT_REQUIRE(!(arr->blocks && nscan > 0), "scan quantities need element positions: dipole arrays only");
     const int P = g.P;
     const int64_t PP = (int64_t)P * P;
     std::vector<int32_t> pl(P);
@@ -778,6 +824,25 @@ mbt_status mbt_array_create_dipole(mbt_ctx* ctx, const mbt_dipole* e, const mbt_
     API_END
 }
 
+mbt_status mbt_array_create_blocks(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t nbases, const double* T,
+                                   mbt_array** out) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && T && out, "NULL argument");
+    std::unique_ptr<mbt_array> a(new mbt_array());
+    a->g = make_geom_blocks(nx, ny, nbases);
+    a->elem = mbt_dipole{0.0, 0.0, nbases};
+    a->lat = mbt_lattice{nx, ny, a->g.dx, a->g.dy};
+    const int64_t n = a->g.noff() * (int64_t)nbases * nbases;
+    auto blk = std::make_shared<std::vector<double2>>((size_t)n);
+    std::memcpy(blk->data(), T, sizeof(double2) * (size_t)n);
+    for (const double2& v : *blk) MBT_REQUIRE(std::isfinite(v.x) && std::isfinite(v.y), "blocks must be finite");
+    a->blocks = blk;
+    static std::atomic<uint64_t> next_uid{1};
+    a->uid = next_uid++;
+    *out = a.release();
+    API_END
+}
+
 void mbt_array_destroy(mbt_array* a) { delete a; }
 
 mbt_status mbt_array_info(const mbt_array* a, int64_t* N, int32_t* P, int32_t* gx, int32_t* gy) {
@@ -885,6 +950,7 @@ mbt_status mbt_active(mbt_ctx* ctx, const mbt_array* arr, double s, const double
     MBT_REQUIRE(ctx && arr && Zp && theta && phi && Za && Gamma, "NULL argument");
     MBT_REQUIRE(nscan >= 1, "nscan must be >= 1");
     MBT_REQUIRE(s > 0 && z0 > 0, "freq_ratio and z0 must be positive");
+    MBT_REQUIRE(!arr->blocks, "scan quantities need element positions: dipole arrays only");
     std::lock_guard<std::mutex> lk(ctx->api_mu);
     DevScope ds(ctx->device);
     const Geom& g = arr->g;
@@ -925,7 +991,7 @@ mbt_status mbt_dbg_fill_blocks(mbt_ctx* ctx, const mbt_array* arr, double s, dou
     MBT_REQUIRE(ctx && arr && T, "NULL argument");
     std::lock_guard<std::mutex> lk(ctx->api_mu);
     DevScope ds(ctx->device);
-    auto op = get_op(ctx, arr->g, s, false, MBT_FP64, *ctx->main);
+    auto op = get_op(ctx, arr, s, false, MBT_FP64, *ctx->main);
     MBT_HIP(hipMemcpy(T, op->T.p, op->T.bytes, hipMemcpyDeviceToHost));
     API_END
 }
@@ -940,7 +1006,7 @@ mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t 
     DevScope ds(ctx->device);
     const Geom& g = arr->g;
     Worker& wk = *ctx->main;
-    auto op = get_op(ctx, g, s, false, prec, wk);
+    auto op = get_op(ctx, arr, s, false, prec, wk);
     const int64_t NR = g.N * R;
     DBuf hx, dx, dy, Xh, Yh, tmp, f1, f2;
     hx.alloc(sizeof(double2) * NR);
@@ -987,7 +1053,7 @@ mbt_status mbt_dbg_precond_apply(mbt_ctx* ctx, const mbt_array* arr, double s, i
     DevScope ds(ctx->device);
     const Geom& g = arr->g;
     Worker& wk = *ctx->main;
-    auto op = get_op(ctx, g, s, pc == MBT_PC_NORMAL_EQ, MBT_FP64, wk);
+    auto op = get_op(ctx, arr, s, pc == MBT_PC_NORMAL_EQ, MBT_FP64, wk);
     const int64_t NR = g.N * R;
     DBuf hx, dx, dy;
     hx.alloc(sizeof(double2) * NR);
@@ -1010,7 +1076,7 @@ mbt_status mbt_dbg_precond_blocks(mbt_ctx* ctx, const mbt_array* arr, double s, 
     DevScope ds(ctx->device);
     const Geom& g = arr->g;
     Worker& wk = *ctx->main;
-    auto op = get_op(ctx, g, s, false, MBT_FP64, wk);
+    auto op = get_op(ctx, arr, s, false, MBT_FP64, wk);
     const int64_t MM = (int64_t)g.M * g.M;
     if (pc == MBT_PC_ELEMENT_BLOCK) {
         const int64_t center = (int64_t)(g.ny - 1) * g.nox + (g.nx - 1);
@@ -1037,7 +1103,7 @@ mbt_status mbt_dbg_solve(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt
     const Geom& g = arr->g;
     Worker& wk = *ctx->main;
     const double t0 = now_s();
-    auto op = get_op(ctx, g, s, opts->pc == MBT_PC_NORMAL_EQ, opts->prec, wk);
+    auto op = get_op(ctx, arr, s, opts->pc == MBT_PC_NORMAL_EQ, opts->prec, wk);
     const int64_t NR = g.N * R;
     wk.ensure(solve_bytes(g, R, *opts) + 3 * sizeof(double2) * NR);
     DevArena arena;

@@ -98,6 +98,8 @@ def lib():
             "mbt_version": (ctypes.c_char_p, []),
             "mbt_array_create_dipole": (S, [_vp, ctypes.POINTER(mbt_dipole), ctypes.POINTER(mbt_lattice),
                                             ctypes.POINTER(_vp)]),
+            "mbt_array_create_blocks": (S, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp,
+                                            ctypes.POINTER(_vp)]),
             "mbt_array_destroy": (None, [_vp]),
             "mbt_array_info": (S, [_vp, ctypes.POINTER(ctypes.c_int64), _ip, _ip, _ip]),
             "mbt_footprint": (ctypes.c_size_t, [_vp, ctypes.c_int32, ctypes.POINTER(mbt_solve_opts)]),
@@ -141,7 +143,7 @@ def exported_symbols() -> list:
     """Names of every C entry point this binding declares (all must exist in the library)."""
     return [
         "mbt_default_opts", "mbt_ctx_create", "mbt_ctx_destroy", "mbt_last_error", "mbt_version",
-        "mbt_array_create_dipole", "mbt_array_destroy", "mbt_array_info", "mbt_footprint",
+        "mbt_array_create_dipole", "mbt_array_create_blocks", "mbt_array_destroy", "mbt_array_info", "mbt_footprint",
         "mbt_port_admittance", "mbt_port_admittance_dev", "mbt_port_impedance", "mbt_solve", "mbt_active",
         "mbt_server_create", "mbt_server_submit", "mbt_server_wait", "mbt_result_free", "mbt_server_clock",
         "mbt_server_destroy", "mbt_dbg_fill_blocks", "mbt_dbg_matvec", "mbt_dbg_precond_apply",
@@ -192,6 +194,15 @@ def mbt_array_create_dipole(ctx: int, dipole, lattice) -> int:
     l = mbt_lattice(lattice.nx, lattice.ny, lattice.dx, lattice.dy)
     h = _vp()
     _check(lib().mbt_array_create_dipole(ctx, ctypes.byref(d), ctypes.byref(l), ctypes.byref(h)))
+    return h.value
+
+
+def mbt_array_create_blocks(ctx: int, T: np.ndarray) -> int:
+    """T of shape (2ny-1, 2nx-1, M, M), complex: the unique lattice blocks."""
+    T = np.ascontiguousarray(T, dtype=np.complex128)
+    ny, nx = (T.shape[0] + 1) // 2, (T.shape[1] + 1) // 2
+    h = _vp()
+    _check(lib().mbt_array_create_blocks(ctx, nx, ny, T.shape[2], T.ctypes.data_as(_dp), ctypes.byref(h)))
     return h.value
 
 

@@ -82,11 +82,46 @@ def gpu_size_32x32() -> Workload:
     return Workload("dipole_32x32_m31", Dipole(0.5, 0.005, 31), Lattice(32, 32, 0.5, 0.5), [1.0], th, ph)
 
 
+def blocks_64x64_m96_shape():
+    """The largest single-GPU shape: 64 x 64 elements of 96 bases (N = 393,216),
+    FFT grid 128 x 128, 32 port excitations per operator and 5 operators (one
+    per frequency; seeds 0..4 of synthetic_blocks), since the 96-basis planar
+    element fill is not part of this build.  Returns (nx, ny, M, seeds, ports)."""
+    rng = np.random.default_rng(0)
+    ports = np.sort(rng.choice(64 * 64, size=32, replace=False)).astype(np.int32)
+    return 64, 64, 96, [0, 1, 2, 3, 4], ports
+
+
 def sweep_5x5_21f() -> Workload:
     """The 5x5 array at 21 frequencies s_i = 0.5 + 0.05 i."""
     th, ph = scan_angles(10, seed=0, broadside_first=True)
     freqs = [0.5 + 0.05 * i for i in range(21)]
     return Workload("dipole_5x5_m15_21f", Dipole(0.5, 0.005, 15), Lattice(5, 5, 0.5, 0.5), freqs, th, ph)
+
+
+def synthetic_blocks(nx: int, ny: int, nbases: int, seed: int = 0, coupling: float = 0.05) -> np.ndarray:
+    """Seeded unique blocks of a block-Toeplitz lattice operator for workloads
+    whose element fill is not built (the 96-basis planar elements): T[dy][dx]
+    (M x M complex, offsets dy + ny - 1, dx + nx - 1) with the reciprocity of a
+    Galerkin operator, T(-d) = T(d)^T, a symmetric self block I (1 + 0.5j) plus
+    a small random part, and random coupling blocks whose size decays as 1/|d|.
+    Shape (2ny-1, 2nx-1, M, M), complex128."""
+    rng = np.random.default_rng(seed)
+    M = nbases
+    T = np.zeros((2 * ny - 1, 2 * nx - 1, M, M), dtype=np.complex128)
+    for dy in range(0, ny):
+        for dx in range(-(nx - 1), nx):
+            if dy == 0 and dx < 0:
+                continue
+            G = (rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))) / (2.0 * np.sqrt(M))
+            if dy == 0 and dx == 0:
+                S = 0.1 * (G + G.T) / 2 + (1.0 + 0.5j) * np.eye(M)
+                T[ny - 1, nx - 1] = S
+            else:
+                B = coupling / np.hypot(dx, dy) * G
+                T[dy + ny - 1, dx + nx - 1] = B
+                T[-dy + ny - 1, -dx + nx - 1] = B.T
+    return T
 
 
 @dataclass

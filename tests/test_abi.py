@@ -49,6 +49,7 @@ def test_null_and_invalid_arguments_rejected_on_host(lib):
     st = lib.mbt_port_admittance(None, None, 1.0, None, -1, None, None, None, None)
     assert st == mbt.MBT_EINVAL
     assert lib.mbt_footprint(None, 1, None) == 0
+    assert lib.mbt_array_create_blocks(None, 2, 2, 3, None, ctypes.byref(h)) == mbt.MBT_EINVAL
 
 
 def test_struct_layouts_match_header_sizes():

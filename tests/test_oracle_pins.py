@@ -364,3 +364,39 @@ def test_stored_sweep_reference_is_the_oracle():
         assert np.max(np.abs(r.Zp - ref["Zp"][i])) <= 1e-10 * np.max(np.abs(r.Zp))
         assert np.max(np.abs(r.Gamma - ref["Gamma"][i])) <= 1e-10
     assert abs(ref["freqs"][10] - 1.0) < 1e-15
+
+
+def test_block_assembly_reproduces_the_dipole_matrix(cfg1, cfg1_dense):
+    """Blocks cut from the dense dipole fill at every offset (one anchor pair
+    each) reassemble into the same dense matrix: the assembly rule Z[t, s] =
+    T[t - s] is the lattice's translation invariance."""
+    from oracle import blocks as ob
+    lat, dip = cfg1.lattice, cfg1.dipole
+    M = dip.nbases
+    T = np.zeros((2 * lat.ny - 1, 2 * lat.nx - 1, M, M), dtype=np.complex128)
+    for oy in range(-(lat.ny - 1), lat.ny):
+        for ox in range(-(lat.nx - 1), lat.nx):
+            ex, ey = max(0, -ox), max(0, -oy)
+            s = ey * lat.nx + ex
+            t = (ey + oy) * lat.nx + (ex + ox)
+            T[oy + lat.ny - 1, ox + lat.nx - 1] = cfg1_dense[t * M:(t + 1) * M, s * M:(s + 1) * M]
+    Z = ob.dense_from_blocks(T, lat.nx, lat.ny)
+    assert np.max(np.abs(Z - cfg1_dense)) <= 1e-12 * np.max(np.abs(cfg1_dense))
+
+
+def test_block_matvec_entries_match_dense_product():
+    from oracle import blocks as ob
+    T = W.synthetic_blocks(4, 3, 6, seed=2)
+    Z = ob.dense_from_blocks(T, 4, 3)
+    x = W.random_vectors(Z.shape[0], 3, seed=4)
+    rows = [0, 5, 17, 40, 71]
+    assert np.max(np.abs(ob.matvec_entries(T, 4, 3, x, rows) - (Z @ x)[rows])) <= 1e-13 * np.max(np.abs(Z @ x))
+
+
+def test_synthetic_blocks_are_reciprocal():
+    """T(-d) = T(d)^T makes the assembled operator symmetric, as a Galerkin
+    operator is."""
+    from oracle import blocks as ob
+    T = W.synthetic_blocks(3, 4, 5, seed=1)
+    Z = ob.dense_from_blocks(T, 3, 4)
+    assert np.array_equal(Z, Z.T)
