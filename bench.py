@@ -293,10 +293,27 @@ def serve(args):
         sat_solves = sum(solves(r) for r in reqs) / t_sat
         bad = sum(1 for x in res if x["status"] != mbt.MBT_OK)
         log("serving: saturation %.2f requests/s, %.1f solves/s (%d not converged)" % (sat_rate, sat_solves, bad))
-        rate = args.load * sat_rate
-        if args.load > 0:
+        loads = [float(v) for v in str(args.load).split(",")]
+
+        def summary(res, reqs, t0):
+            lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
+            wait = np.array([x["t_start"] - x["t_submit"] for x in res]) * 1e3
+            span = max(x["t_done"] for x in res) - t0
+            return {"solves_per_s": sum(solves(r) for r in reqs) / span, "span_s": span,
+                    "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                                   "mean": float(lat.mean()), "queue_wait_p50": float(np.percentile(wait, 50))},
+                    "not_converged": sum(1 for x in res if x["status"] != mbt.MBT_OK)}
+
+        runs = []
+        if not any(load > 0 for load in loads):
+            # the latencies reported are those of the saturation run
+            runs.append(dict(summary(res, reqs, t0), load_vs_saturation=0.0, rate_rps=None))
+        for load in loads:
+            if load <= 0:
+                continue
+            rate = load * sat_rate
             reqs = W.serving_stream(args.serve, rate, seed=0)
-            log("serving: Poisson stream at %.2f requests/s (%.0f%% of saturation)" % (rate, 100 * args.load))
+            log("serving: Poisson stream at %.3f requests/s (%.0f%% of saturation)" % (rate, 100 * load))
             t0 = mbt.mbt_server_clock(srv)
             tickets = []
             for r in reqs:
@@ -305,27 +322,26 @@ def serve(args):
                     time.sleep(dt)
                 tickets.append(submit(r))
             res = collect(tickets, reqs, t0)
-        # with --load 0 the latencies reported are those of the saturation run
-        lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
-        wait = np.array([x["t_start"] - x["t_submit"] for x in res]) * 1e3
-        span = max(x["t_done"] for x in res) - t0
-        nsolves = sum(solves(r) for r in reqs)
-        bad = sum(1 for x in res if x["status"] != mbt.MBT_OK)
+            runs.append(dict(summary(res, reqs, t0), load_vs_saturation=load, rate_rps=rate))
+            log("serving: load %.2f: %.1f solves/s, p50 %.1f s, p99 %.1f s" % (
+                load, runs[-1]["solves_per_s"], runs[-1]["latency_ms"]["p50"] / 1e3,
+                runs[-1]["latency_ms"]["p99"] / 1e3))
     finally:
         mbt.mbt_server_destroy(srv)
         mbt.mbt_ctx_destroy(ctx)
+    head = runs[0]
     return {"metric": "served port-excitation solves/s and p50/p99 request latency, Poisson stream",
-            "value": nsolves / span, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": "dipole_serving_stream", "requests": len(reqs), "warmup_requests": len(warm),
-                       "slots": args.slots, "rate_rps": rate, "load_vs_saturation": args.load,
+                       "slots": args.slots, "rate_rps": head["rate_rps"],
+                       "load_vs_saturation": head["load_vs_saturation"],
                        "nx_ny": [8, 48], "nbases": [15, 31], "nfreq": [1, 8], "nscan": [1, 64],
                        "restart": args.restart, "refine_tol": args.refine_tol, "inner_tol": args.inner_tol,
                        "max_cycles": args.serve_max_cycles},
-            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                           "mean": float(lat.mean()), "queue_wait_p50": float(np.percentile(wait, 50))},
-            "saturation": {"requests_per_s": sat_rate, "solves_per_s": sat_solves},
-            "not_converged": bad, "span_s": span}
+            "latency_ms": head["latency_ms"],
+            "saturation": {"requests_per_s": sat_rate, "solves_per_s": sat_solves, "not_converged": bad},
+            "not_converged": head["not_converged"], "span_s": head["span_s"], "loads": runs}
 
 
 def blocks_shape(args):
@@ -445,8 +461,9 @@ def main():
     ap.add_argument("--serve-max-cycles", type=int, default=8,
                     help="restart cycles per inner solve in the serving run (slow-converging requests report ENOCONV)")
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--load", type=float, default=0.8,
-                    help="stream rate as a fraction of saturation (0: report the saturation run only)")
+    ap.add_argument("--load", default="0.8",
+                    help="stream rates as fractions of saturation, comma-separated (the first is the headline "
+                         "of the JSON line; 0: report the saturation run only)")
     ap.add_argument("--sweep", action="store_true", help="run the 21-frequency precision sweep instead")
     ap.add_argument("--blocks", type=int, default=0,
                     help="run the 64x64x96 synthetic-block shape with this many operators (1..5) instead")

@@ -160,7 +160,7 @@ void launch_mp(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, 
 // real 2M x 2M product, and the X fragments are read straight from memory.  At
 // M = 96 and 32 columns a bin moves 123 KB (FP32) for 2.4 MFLOP, at the FP32
 // MFMA ridge.
-template <typename T, int MP, bool HERM>
+template <typename T, int MP, bool HERM, int CT>
 __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restrict__ A, int64_t strideA,
                                                         const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Y, int M,
                                                         int R) {
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restric
     constexpr int KC = 32;         // complex K per LDS stage
     constexpr int NRT = MP / 8;    // 16-row tiles of the 2MP-row real matrix
     constexpr int RTW = NRT / 4;   // row tiles per wave
-    constexpr int CT = 4;          // column tiles per workgroup
+    // CT: column tiles per workgroup (1, 2 or 4)
     constexpr int LDA = KC + 1;
     __shared__ C As[MP * LDA];
     const int lane = threadIdx.x & 63;
@@ -254,18 +254,27 @@ __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restric
     }
 }
 
-template <typename T, int MP>
-void launch_big(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R, int64_t nbatch, int op,
-                hipStream_t s) {
+template <typename T, int MP, int CT>
+void launch_big_ct(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R, int64_t nbatch,
+                   int op, hipStream_t s) {
     const int ntiles = (R + 15) / 16;
-    const int groups = (ntiles + 3) / 4;
+    const int groups = (ntiles + CT - 1) / CT;
     MBT_REQUIRE(nbatch < (1LL << 31) && groups < 65536, "cgemm: grid too large");
     const dim3 grid((unsigned)nbatch, (unsigned)groups);
     if (op == 0)
-        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, false>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
+        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, false, CT>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
     else
-        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, true>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
+        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, true, CT>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
     MBT_LAUNCH_CHECK();
+}
+
+// as few column tiles per workgroup as cover R (no MFMA work on padding columns)
+template <typename T, int MP>
+void launch_big(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R, int64_t nbatch, int op,
+                hipStream_t s) {
+    if (R <= 16) launch_big_ct<T, MP, 1>(A, strideA, X, Y, M, R, nbatch, op, s);
+    else if (R <= 32) launch_big_ct<T, MP, 2>(A, strideA, X, Y, M, R, nbatch, op, s);
+    else launch_big_ct<T, MP, 4>(A, strideA, X, Y, M, R, nbatch, op, s);
 }
 
 // ---------------------------------------------------------------- 16-bit inputs

@@ -158,16 +158,20 @@ void embed_blocks_fft(const Geom& g, const double2* T, double2* Chat, double sca
                       hipStream_t s);
 // twiddle table tw[j] = exp(-2 pi i j / P), j < P
 void make_twiddles(int P, double2* tw, hipStream_t s);
+// Zero-padded forward transform of B columns and the cropped inverse.  scratch
+// (at least ny * Px * B complex values, not overlapping the operands) lets FP32
+// transforms on 128-point axes run as two passes of 1-D transforms; with NULL
+// they run as one LDS-tiled kernel.
 template <typename T>
 void fft_fwd_pad(const Geom& g, const cplx<T>* X, cplx<T>* Xh, int64_t B, const cplx<T>* twx,
-                 const cplx<T>* twy, hipStream_t s);
+                 const cplx<T>* twy, cplx<T>* scratch, hipStream_t s);
 template <typename T>
 void fft_inv_crop(const Geom& g, const cplx<T>* Yh, cplx<T>* Y, int64_t B, const cplx<T>* twx,
-                  const cplx<T>* twy, hipStream_t s);
+                  const cplx<T>* twy, cplx<T>* scratch, hipStream_t s);
 
 // Forward lattice FFT with the spectrum stored in 16-bit complex (FMT); the
-// transform itself runs in FP32.  scratch (bins*B float2) is used on grids whose
-// sub-transforms do not fit the register kernels.
+// transform itself runs in FP32.  scratch (ny * Px * B float2) is used on grids
+// whose sub-transforms do not fit the register kernels.
 template <int FMT>
 void fft_fwd_pad16(const Geom& g, const float2* X, uint32_t* Xh, int64_t B, const float2* twx, const float2* twy,
                    float2* scratch, hipStream_t s);

@@ -22,6 +22,16 @@ namespace mbt {
 
 namespace {
 
+// Workgroups are handed to the 8 XCDs round robin, and each XCD has its own L2.
+// Logical block b of a launch of n is taken from a workgroup id such that
+// consecutive logical blocks (adjacent columns, which share cache lines when a
+// block's column run is shorter than a line) run on the same XCD.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
+    const int64_t full = n - n % 8;
+    if (b >= full) return b;
+    return (b % 8) * (full / 8) + b / 8;
+}
+
 // ------------------------------------------------------------------ small DFTs in registers
 template <typename C, bool INV> __device__ __forceinline__ void dft2(C* v) {
     C t = v[0];
@@ -165,7 +175,7 @@ __global__ __launch_bounds__(kNT) void fft_fwd_pad_kernel(const cplx<T>* __restr
     constexpr int PX = 2 * LX, NTILE = LX * LY * W;
     constexpr int NOWN = (NTILE + kNT - 1) / kNT;
     __shared__ C tile[NTILE];
-    const int64_t c0 = (int64_t)blockIdx.x * W;
+    const int64_t c0 = xcd_block(blockIdx.x, gridDim.x) * W;
     C xin[NOWN];
 #pragma unroll
     for (int i = 0; i < NOWN; ++i) {
@@ -209,7 +219,7 @@ __global__ __launch_bounds__(kNT) void fft_inv_crop_kernel(const cplx<T>* __rest
     constexpr int PX = 2 * LX, NTILE = LX * LY * W;
     constexpr int NOWN = (NTILE + kNT - 1) / kNT;
     __shared__ C tile[NTILE];
-    const int64_t c0 = (int64_t)blockIdx.x * W;
+    const int64_t c0 = xcd_block(blockIdx.x, gridDim.x) * W;
     C acc[NOWN];
 #pragma unroll
     for (int i = 0; i < NOWN; ++i) acc[i] = mk<T>(0, 0);
@@ -416,6 +426,175 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_inv_reg_kernel(co
     }
 }
 
+// ------------------------------------------------------------------ two-pass FP32 transforms (128-point axes)
+// On a 128-point axis one column's L x L sub-transforms take 32 KB of LDS, so a
+// fused kernel holds only a few columns per CU and reads 32-byte runs.  These
+// grids run as two passes of 1-D transforms instead, each line of a column
+// held and transformed in one thread's registers.  A wave covers 32 adjacent
+// columns twice: lanes 0-31 take parity 0 of a line and lanes 32-63 parity 1
+// (256 contiguous bytes per half-wave access; both halves of the forward
+// passes read the same addresses).  The inverse passes add the two parity
+// contributions across the halves with a lane exchange, each half writing
+// half of the line.  The intermediate Z (ny x 2Lx lines per column) sits in
+// the spare spectral buffer.
+constexpr int kLineNT = 256;
+constexpr int kLineCols = kLineNT / 2;   // columns per workgroup
+
+struct LineIdx {
+    int line, half;
+    int64_t c;
+    bool cv;
+};
+__device__ __forceinline__ LineIdx line_idx(int64_t ctiles, int64_t B) {
+    LineIdx L;
+    const int lane = threadIdx.x & 63;
+    L.line = (int)(blockIdx.x / ctiles);
+    L.half = lane >> 5;
+    L.c = (int64_t)(blockIdx.x % ctiles) * kLineCols + (threadIdx.x >> 6) * 32 + (lane & 31);
+    L.cv = L.c < B;
+    return L;
+}
+
+// v times the parity twiddle tw[i] (or its conjugate) on odd halves, v on even
+// halves (the product takes the uniform twiddle; only the result is selected)
+template <bool CONJ>
+__device__ __forceinline__ float2 par_tw(float2 v, const float2* __restrict__ tw, int i, int half) {
+    float2 t = tw[i];
+    if (CONJ) t.y = -t.y;
+    const float2 p = cmul(v, t);
+    return half ? p : v;
+}
+
+// Forward, pass 1: rows.  Z[iy][2b+be][c] = sum_ix x[iy][ix][c] W_{2Lx}^{ix(2b+be)}.
+template <int LX>
+__global__ __launch_bounds__(kLineNT) void fft_rows_fwd_kernel(const float2* __restrict__ X, float2* __restrict__ Z,
+                                                               int nx, int64_t B, int64_t ctiles,
+                                                               const float2* __restrict__ twx) {
+    constexpr int PX = 2 * LX;
+    const LineIdx t = line_idx(ctiles, B);
+    const int iy = t.line;
+    float2 f[LX];
+#pragma unroll
+    for (int ix = 0; ix < LX; ++ix) {
+        const float2 v = (t.cv && ix < nx) ? X[(int64_t)(iy * nx + ix) * B + t.c] : mk<float>(0, 0);
+        f[ix] = ix ? par_tw<false>(v, twx, ix, t.half) : v;
+    }
+    fft_reg<float, LX, false>(f, twx);
+    if (t.cv) {
+#pragma unroll
+        for (int b = 0; b < LX; ++b) Z[((int64_t)iy * PX + 2 * b + t.half) * B + t.c] = f[b];
+    }
+}
+
+// Forward, pass 2: columns.  Xh[2a+al][kx][c] = sum_iy Z[iy][kx][c] W_{2Ly}^{iy(2a+al)},
+// stored as FP32 complex or packed 16-bit complex (FMT).
+template <int LX, int LY, int FMT>
+__global__ __launch_bounds__(kLineNT) void fft_cols_fwd_kernel(const float2* __restrict__ Z, void* __restrict__ Xh_,
+                                                               int ny, int64_t B, int64_t ctiles,
+                                                               const float2* __restrict__ twy) {
+    constexpr int PX = 2 * LX;
+    const LineIdx t = line_idx(ctiles, B);
+    const int kx = t.line;
+    float2 g[LY];
+#pragma unroll
+    for (int iy = 0; iy < LY; ++iy) {
+        const float2 v = (t.cv && iy < ny) ? Z[((int64_t)iy * PX + kx) * B + t.c] : mk<float>(0, 0);
+        g[iy] = iy ? par_tw<false>(v, twy, iy, t.half) : v;
+    }
+    fft_reg<float, LY, false>(g, twy);
+    if (t.cv) {
+#pragma unroll
+        for (int a = 0; a < LY; ++a) {
+            const int64_t o = ((int64_t)(2 * a + t.half) * PX + kx) * B + t.c;
+            if constexpr (FMT == kFmtNone)
+                static_cast<float2*>(Xh_)[o] = g[a];
+            else
+                static_cast<uint32_t*>(Xh_)[o] = pack16<FMT>(g[a]);
+        }
+    }
+}
+
+// the value of element j (j < L/2) of the two halves' sum that this half
+// writes: its own element j + half*L/2 plus the other half's
+template <int L>
+__device__ __forceinline__ float2 half_sum(const float2 (&v)[L], int j, int half) {
+    const float2 send = half ? v[j] : v[j + L / 2];
+    const float2 mine = half ? v[j + L / 2] : v[j];
+    float2 recv;
+    recv.x = __shfl_xor(send.x, 32);
+    recv.y = __shfl_xor(send.y, 32);
+    return cadd(mine, recv);
+}
+
+// Inverse, pass 1: columns.  Z[iy][kx][c] = sum_al tw_al(iy)* IDFT_Ly(Yh[2a+al][kx][c])[iy], iy < ny.
+template <int LX, int LY>
+__global__ __launch_bounds__(kLineNT) void fft_cols_inv_kernel(const float2* __restrict__ Yh, float2* __restrict__ Z,
+                                                               int ny, int64_t B, int64_t ctiles,
+                                                               const float2* __restrict__ twy) {
+    constexpr int PX = 2 * LX;
+    const LineIdx t = line_idx(ctiles, B);
+    const int kx = t.line;
+    float2 g[LY];
+#pragma unroll
+    for (int a = 0; a < LY; ++a) g[a] = t.cv ? Yh[((int64_t)(2 * a + t.half) * PX + kx) * B + t.c] : mk<float>(0, 0);
+    fft_reg<float, LY, true>(g, twy);
+#pragma unroll
+    for (int iy = 1; iy < LY; ++iy) g[iy] = par_tw<true>(g[iy], twy, iy, t.half);
+#pragma unroll
+    for (int j = 0; j < LY / 2; ++j) {
+        const float2 v = half_sum<LY>(g, j, t.half);
+        const int iy = j + t.half * (LY / 2);
+        if (t.cv && iy < ny) Z[((int64_t)iy * PX + kx) * B + t.c] = v;
+    }
+}
+
+// Inverse, pass 2: rows.  Y[iy][ix][c] = sum_be tw_be(ix)* IDFT_Lx(Z[iy][2b+be][c])[ix], ix < nx.
+template <int LX>
+__global__ __launch_bounds__(kLineNT) void fft_rows_inv_kernel(const float2* __restrict__ Z, float2* __restrict__ Y,
+                                                               int nx, int64_t B, int64_t ctiles,
+                                                               const float2* __restrict__ twx) {
+    constexpr int PX = 2 * LX;
+    const LineIdx t = line_idx(ctiles, B);
+    const int iy = t.line;
+    float2 h[LX];
+#pragma unroll
+    for (int b = 0; b < LX; ++b) h[b] = t.cv ? Z[((int64_t)iy * PX + 2 * b + t.half) * B + t.c] : mk<float>(0, 0);
+    fft_reg<float, LX, true>(h, twx);
+#pragma unroll
+    for (int ix = 1; ix < LX; ++ix) h[ix] = par_tw<true>(h[ix], twx, ix, t.half);
+#pragma unroll
+    for (int j = 0; j < LX / 2; ++j) {
+        const float2 v = half_sum<LX>(h, j, t.half);
+        const int ix = j + t.half * (LX / 2);
+        if (t.cv && ix < nx) Y[(int64_t)(iy * nx + ix) * B + t.c] = v;
+    }
+}
+
+// Z needs ny * 2Lx * B complex values of scratch.
+template <bool FWD, int LX, int LY, int FMT>
+void launch_two_pass(const Geom& g, const float2* in, void* out, int64_t B, const float2* twx, const float2* twy,
+                     float2* Z, hipStream_t s) {
+    const int64_t ctiles = (B + kLineCols - 1) / kLineCols;
+    const int64_t rows = (int64_t)g.ny * ctiles, cols = (int64_t)(2 * LX) * ctiles;
+    MBT_REQUIRE(g.nx <= LX && g.ny <= LY, "fft: lattice larger than its grid");
+    MBT_REQUIRE(cols * kLineNT < (1LL << 32), "fft: batch too large");
+    if (FWD) {
+        hipLaunchKernelGGL((fft_rows_fwd_kernel<LX>), dim3((unsigned)rows), dim3(kLineNT), 0, s, in, Z, g.nx, B, ctiles,
+                           twx);
+        MBT_LAUNCH_CHECK();
+        hipLaunchKernelGGL((fft_cols_fwd_kernel<LX, LY, FMT>), dim3((unsigned)cols), dim3(kLineNT), 0, s, Z, out, g.ny,
+                           B, ctiles, twy);
+        MBT_LAUNCH_CHECK();
+    } else {
+        hipLaunchKernelGGL((fft_cols_inv_kernel<LX, LY>), dim3((unsigned)cols), dim3(kLineNT), 0, s, in, Z, g.ny, B,
+                           ctiles, twy);
+        MBT_LAUNCH_CHECK();
+        hipLaunchKernelGGL((fft_rows_inv_kernel<LX>), dim3((unsigned)rows), dim3(kLineNT), 0, s, Z,
+                           static_cast<float2*>(out), g.nx, B, ctiles, twx);
+        MBT_LAUNCH_CHECK();
+    }
+}
+
 // ------------------------------------------------------------------ twiddles and block spectra
 __global__ void twiddle_kernel(int P, double2* tw) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -480,10 +659,16 @@ template <typename T> constexpr int tile_w(int lx, int ly) {
 
 template <typename T, bool FWD, int LX, int LY>
 void launch_fft_t(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
-                  hipStream_t s) {
+                  cplx<T>* scratch, hipStream_t s) {
     constexpr int W = tile_w<T>(LX, LY);
     const int64_t blocks = (B + W - 1) / W;
     MBT_REQUIRE(blocks < (1LL << 31), "fft: batch too large");
+    if constexpr (sizeof(T) == 4 && (LX > 32 || LY > 32)) {
+        if (scratch) {
+            launch_two_pass<FWD, LX, LY, kFmtNone>(g, in, out, B, twx, twy, scratch, s);
+            return;
+        }
+    }
     if constexpr (sizeof(T) == 4 && LX <= 32 && LY <= 32) {
         constexpr int NT = (LX > LY ? LX : LY) * W;
         if (FWD)
@@ -506,32 +691,26 @@ void launch_fft_t(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, con
 
 template <typename T, bool FWD, int LX>
 void dispatch_ly(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
-                 hipStream_t s) {
+                 cplx<T>* scratch, hipStream_t s) {
     switch (g.Ly) {
-        case 8: launch_fft_t<T, FWD, LX, 8>(g, in, out, B, twx, twy, s); break;
-        case 16: launch_fft_t<T, FWD, LX, 16>(g, in, out, B, twx, twy, s); break;
-        case 32: launch_fft_t<T, FWD, LX, 32>(g, in, out, B, twx, twy, s); break;
-        case 64: launch_fft_t<T, FWD, LX, 64>(g, in, out, B, twx, twy, s); break;
+        case 8: launch_fft_t<T, FWD, LX, 8>(g, in, out, B, twx, twy, scratch, s); break;
+        case 16: launch_fft_t<T, FWD, LX, 16>(g, in, out, B, twx, twy, scratch, s); break;
+        case 32: launch_fft_t<T, FWD, LX, 32>(g, in, out, B, twx, twy, scratch, s); break;
+        case 64: launch_fft_t<T, FWD, LX, 64>(g, in, out, B, twx, twy, scratch, s); break;
         default: throw Error(-1, "fft: unsupported grid (ny > 64)");
     }
 }
 
 template <typename T, bool FWD>
 void dispatch(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
-              hipStream_t s) {
+              cplx<T>* scratch, hipStream_t s) {
     switch (g.Lx) {
-        case 8: dispatch_ly<T, FWD, 8>(g, in, out, B, twx, twy, s); break;
-        case 16: dispatch_ly<T, FWD, 16>(g, in, out, B, twx, twy, s); break;
-        case 32: dispatch_ly<T, FWD, 32>(g, in, out, B, twx, twy, s); break;
-        case 64: dispatch_ly<T, FWD, 64>(g, in, out, B, twx, twy, s); break;
+        case 8: dispatch_ly<T, FWD, 8>(g, in, out, B, twx, twy, scratch, s); break;
+        case 16: dispatch_ly<T, FWD, 16>(g, in, out, B, twx, twy, scratch, s); break;
+        case 32: dispatch_ly<T, FWD, 32>(g, in, out, B, twx, twy, scratch, s); break;
+        case 64: dispatch_ly<T, FWD, 64>(g, in, out, B, twx, twy, scratch, s); break;
         default: throw Error(-1, "fft: unsupported grid (nx > 64)");
     }
-}
-
-template <int FMT>
-__global__ void pack16_f_kernel(const float2* __restrict__ src, uint32_t* __restrict__ dst, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = pack16<FMT>(src[i]);
 }
 
 template <int FMT, int LX, int LY>
@@ -547,12 +726,8 @@ void launch_fwd16(const Geom& g, const float2* X, uint32_t* Xh, int64_t B, const
                            g.nx, g.ny, B, twx, twy);
         MBT_LAUNCH_CHECK();
     } else {
-        // FP32 transform into scratch, then one packing pass
-        launch_fft_t<float, true, LX, LY>(g, X, scratch, B, twx, twy, s);
-        const int64_t n = g.bins() * B;
-        const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
-        hipLaunchKernelGGL((pack16_f_kernel<FMT>), dim3(grid), dim3(256), 0, s, scratch, Xh, n);
-        MBT_LAUNCH_CHECK();
+        // two passes, the second storing the packed spectrum; scratch holds the row spectra
+        launch_two_pass<true, LX, LY, FMT>(g, X, Xh, B, twx, twy, scratch, s);
     }
 }
 
@@ -607,19 +782,23 @@ void embed_blocks_fft(const Geom& g, const double2* T, double2* Chat, double sca
 
 template <typename T>
 void fft_fwd_pad(const Geom& g, const cplx<T>* X, cplx<T>* Xh, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
-                 hipStream_t s) {
-    dispatch<T, true>(g, X, Xh, B, twx, twy, s);
+                 cplx<T>* scratch, hipStream_t s) {
+    dispatch<T, true>(g, X, Xh, B, twx, twy, scratch, s);
 }
 
 template <typename T>
 void fft_inv_crop(const Geom& g, const cplx<T>* Yh, cplx<T>* Y, int64_t B, const cplx<T>* twx, const cplx<T>* twy,
-                  hipStream_t s) {
-    dispatch<T, false>(g, Yh, Y, B, twx, twy, s);
+                  cplx<T>* scratch, hipStream_t s) {
+    dispatch<T, false>(g, Yh, Y, B, twx, twy, scratch, s);
 }
 
-template void fft_fwd_pad<double>(const Geom&, const double2*, double2*, int64_t, const double2*, const double2*, hipStream_t);
-template void fft_fwd_pad<float>(const Geom&, const float2*, float2*, int64_t, const float2*, const float2*, hipStream_t);
-template void fft_inv_crop<double>(const Geom&, const double2*, double2*, int64_t, const double2*, const double2*, hipStream_t);
-template void fft_inv_crop<float>(const Geom&, const float2*, float2*, int64_t, const float2*, const float2*, hipStream_t);
+template void fft_fwd_pad<double>(const Geom&, const double2*, double2*, int64_t, const double2*, const double2*,
+                                  double2*, hipStream_t);
+template void fft_fwd_pad<float>(const Geom&, const float2*, float2*, int64_t, const float2*, const float2*, float2*,
+                                 hipStream_t);
+template void fft_inv_crop<double>(const Geom&, const double2*, double2*, int64_t, const double2*, const double2*,
+                                   double2*, hipStream_t);
+template void fft_inv_crop<float>(const Geom&, const float2*, float2*, int64_t, const float2*, const float2*, float2*,
+                                  hipStream_t);
 
 }  // namespace mbt

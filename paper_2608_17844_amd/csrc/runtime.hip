@@ -414,14 +414,14 @@ template <typename T> static void zmul(const OpV<T>& o, int opz, const cplx<T>* 
             }
             {
                 ProfScope ps(kKFftInv, spat + spec, 0.0, o.s);
-                fft_inv_crop<T>(g, o.Yh, y, B, o.twx, o.twy, o.s);
+                fft_inv_crop<T>(g, o.Yh, y, B, o.twx, o.twy, reinterpret_cast<cplx<T>*>(o.Xh), o.s);
             }
             return;
         }
     }
     {
         ProfScope ps(kKFftFwd, spat + spec, 0.0, o.s);
-        fft_fwd_pad<T>(g, x, o.Xh, B, o.twx, o.twy, o.s);
+        fft_fwd_pad<T>(g, x, o.Xh, B, o.twx, o.twy, o.Yh, o.s);   // Y^ is free until the product
     }
     {
         ProfScope ps(kKBinProduct, 2 * spec + (double)g.bins() * g.M * g.M * sc, 8.0 * g.bins() * g.M * g.M * o.R, o.s);
@@ -429,7 +429,7 @@ template <typename T> static void zmul(const OpV<T>& o, int opz, const cplx<T>* 
     }
     {
         ProfScope ps(kKFftInv, spat + spec, 0.0, o.s);
-        fft_inv_crop<T>(g, o.Yh, y, B, o.twx, o.twy, o.s);
+        fft_inv_crop<T>(g, o.Yh, y, B, o.twx, o.twy, o.Xh, o.s);   // X^ is free after the product
     }
 }
 

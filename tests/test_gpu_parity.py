@@ -48,6 +48,10 @@ SHAPES = [
     (W.Lattice(5, 5, 0.5, 0.5), W.Dipole(0.5, 0.005, 15)),
     (W.Lattice(9, 6, 0.5, 0.55), W.Dipole(0.5, 0.005, 31)),
     (W.Lattice(17, 3, 0.5, 0.5), W.Dipole(0.48, 0.004, 21)),
+    # 128-point grid axes (two-pass FP32 transforms): x only, y only, both
+    (W.Lattice(40, 2, 0.5, 0.5), W.Dipole(0.5, 0.005, 7)),
+    (W.Lattice(3, 36, 0.5, 0.5), W.Dipole(0.5, 0.005, 5)),
+    (W.Lattice(33, 34, 0.5, 0.5), W.Dipole(0.5, 0.005, 3)),
 ]
 
 
