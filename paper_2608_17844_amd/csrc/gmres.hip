@@ -339,93 +339,6 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TB* __restric
         }
 }
 
-// Update sweep: v_k = (u - sum_{i<k} s_i V_i) / nu  (into slot k, over u),
-//               u_{k+1} = w / nu - sum_{i<k} c_i V_i - c_k v_k  (into slot k+1, over w).
-template <typename TB, int NW, int G, int RPL>
-__global__ __launch_bounds__(NW * 64) void dcgs2_update_kernel(const TB* __restrict__ V, int64_t vstride, int k,
-                                                               TB* u, TB* w, const double2* __restrict__ cs,
-                                                               const double2* __restrict__ cc,
-                                                               const double* __restrict__ inv_nu, int64_t N, int R,
-                                                               int64_t rows_per_chunk) {
-    __shared__ double2 xch[2][NW][2 * 64 * RPL];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int r0 = (blockIdx.x * 64 + lane) * RPL;
-    const bool live = r0 < R;
-    const int64_t chunk = blockIdx.y;
-    const int64_t n0 = chunk * rows_per_chunk;
-    const int64_t n1 = min(N, n0 + rows_per_chunk);
-    double2 fs[G][RPL], fc[G][RPL], ck[RPL];
-    double inu[RPL];
-#pragma unroll
-    for (int k2 = 0; k2 < RPL; ++k2) {
-        inu[k2] = live ? inv_nu[r0 + k2] : 0.0;
-        ck[k2] = live ? cc[(int64_t)k * R + r0 + k2] : make_double2(0, 0);
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int i = wave + NW * g;
-            fs[g][k2] = (live && i < k) ? cs[(int64_t)i * R + r0 + k2] : make_double2(0, 0);
-            fc[g][k2] = (live && i < k) ? cc[(int64_t)i * R + r0 + k2] : make_double2(0, 0);
-        }
-    }
-    Raw<TB, RPL> cur[G], nxt[G], cu, nu_, cw, nw_;
-    auto load_row = [&](int64_t n, Raw<TB, RPL>(&v)[G], Raw<TB, RPL>& ur, Raw<TB, RPL>& wr) {
-        const int64_t off = n * R + r0;
-        ur.load(u + off);
-        wr.load(w + off);
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int i = wave + NW * g;
-            if (i < k) v[g].load(V + i * vstride + off);
-            else v[g].zero();
-        }
-    };
-    if (live && n0 < n1) load_row(n0, cur, cu, cw);
-    int buf = 0;
-    for (int64_t n = n0; n < n1; ++n) {
-        const int64_t off = n * R + r0;
-        if (live && n + 1 < n1) load_row(n + 1, nxt, nu_, nw_);
-#pragma unroll
-        for (int k2 = 0; k2 < RPL; ++k2) {
-            double2 a = make_double2(0, 0), c = make_double2(0, 0);
-            if (live) {
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const double2 vv = cur[g].get(k2);
-                    a = cfma(a, fs[g][k2], vv);
-                    c = cfma(c, fc[g][k2], vv);
-                }
-            }
-            xch[buf][wave][2 * (lane * RPL + k2)] = a;
-            xch[buf][wave][2 * (lane * RPL + k2) + 1] = c;
-        }
-        __syncthreads();
-        if (live && wave == 0) {
-            double2 vk[RPL], un[RPL];
-#pragma unroll
-            for (int k2 = 0; k2 < RPL; ++k2) {
-                double2 a = xch[buf][0][2 * (lane * RPL + k2)], c = xch[buf][0][2 * (lane * RPL + k2) + 1];
-#pragma unroll
-                for (int q = 1; q < NW; ++q) {
-                    a = cadd(a, xch[buf][q][2 * (lane * RPL + k2)]);
-                    c = cadd(c, xch[buf][q][2 * (lane * RPL + k2) + 1]);
-                }
-                const double2 d = csub(cu.get(k2), a);
-                vk[k2] = make_double2(d.x * inu[k2], d.y * inu[k2]);
-                const double2 wv = cw.get(k2);
-                un[k2] = next_candidate(wv, inu[k2], c, ck[k2], vk[k2]);
-            }
-            stp<RPL>(u + off, vk);
-            stp<RPL>(w + off, un);
-        }
-        buf ^= 1;
-#pragma unroll
-        for (int g = 0; g < G; ++g) cur[g] = nxt[g];
-        cu = nu_;
-        cw = nw_;
-    }
-}
-
 // Per-RHS bookkeeping of DCGS2 step k (red: reduced [s, z, alpha, beta]):
 // completes Hessenberg column k-1 (raw and rotated), Givens, convergence.
 // inv_nu[r] = 1/nu for a RHS that takes another step, 0 for one that stops.
@@ -626,23 +539,6 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows_kernel(const TB* __rest
     }
 }
 
-template <typename TB, int RPL>
-void launch_dcgs2_update_rpl(const TB* V, int64_t vs, int k, TB* u, TB* w, const double2* cs, const double2* cc,
-                             const double* inv_nu, int64_t N, int R, int64_t rpc, int nchunk, hipStream_t s) {
-    const dim3 grid((unsigned)((R / RPL + 63) / 64), (unsigned)nchunk);
-    if (k <= 4)
-        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 4, 1, RPL>), grid, dim3(256), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
-    else if (k <= 8)
-        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 4, 2, RPL>), grid, dim3(256), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
-    else if (k <= 16)
-        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 4, 4, RPL>), grid, dim3(256), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
-    else if (k <= 32)
-        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 8, 4, RPL>), grid, dim3(512), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
-    else
-        hipLaunchKernelGGL((dcgs2_update_kernel<TB, 8, 8, RPL>), grid, dim3(512), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc);
-    MBT_LAUNCH_CHECK();
-}
-
 template <typename TB>
 void launch_dcgs2_dots(const TB* V, int64_t vs, int k, const TB* u, const TB* w, int64_t N, int R, int64_t rpc,
                        int nchunk, double2* partial, hipStream_t s) {
@@ -665,23 +561,15 @@ void launch_dcgs2_dots(const TB* V, int64_t vs, int k, const TB* u, const TB* w,
 template <typename TB>
 void launch_dcgs2_update(const TB* V, int64_t vs, int k, TB* u, TB* w, const double2* cs, const double2* cc,
                          const double* inv_nu, int64_t N, int R, int64_t rpc, int nchunk, hipStream_t s) {
-    if (k >= 8) {
-        constexpr int RB = 8;
-        const int64_t rows_per_block = 4 * RB;
-        const int64_t gy = (N + rows_per_block - 1) / rows_per_block;
-        MBT_REQUIRE(gy < 65536, "dcgs2 update: too many row blocks");
-        hipLaunchKernelGGL((dcgs2_update_rows_kernel<TB, RB>), dim3((unsigned)((R + 63) / 64), (unsigned)gy),
-                           dim3(256), 0, s, V, vs, k, u, w, cs, cc, inv_nu, N, R);
-        MBT_LAUNCH_CHECK();
-        return;
-    }
-    if constexpr (sizeof(TB) == 8) {
-        if (R % 2 == 0 && k <= 32) {
-            launch_dcgs2_update_rpl<TB, 2>(V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc, nchunk, s);
-            return;
-        }
-    }
-    launch_dcgs2_update_rpl<TB, 1>(V, vs, k, u, w, cs, cc, inv_nu, N, R, rpc, nchunk, s);
+    (void)rpc;
+    (void)nchunk;
+    constexpr int RB = 8;
+    const int64_t rows_per_block = 4 * RB;
+    const int64_t gy = (N + rows_per_block - 1) / rows_per_block;
+    MBT_REQUIRE(gy < 65536, "dcgs2 update: too many row blocks");
+    hipLaunchKernelGGL((dcgs2_update_rows_kernel<TB, RB>), dim3((unsigned)((R + 63) / 64), (unsigned)gy), dim3(256), 0,
+                       s, V, vs, k, u, w, cs, cc, inv_nu, N, R);
+    MBT_LAUNCH_CHECK();
 }
 
 template <typename TB, typename TO, int MODE, int RPL>
@@ -916,7 +804,11 @@ inline unsigned ew_grid(int64_t n) {
 }  // namespace
 
 // Row chunks depend on N only, so a RHS's reduction order never depends on the batch.
-int64_t gmres_rows_per_chunk(int64_t N) { return std::max<int64_t>(32, (N + 255) / 256); }
+// Chunks of the row range for the reduction sweeps: a function of N alone, so a
+// right-hand side's sums do not depend on how many others share the batch.  Up
+// to 2048 chunks (at least 128 rows each) keep a few-RHS batch spread over the
+// whole chip while the partial sums stay small next to one basis vector.
+int64_t gmres_rows_per_chunk(int64_t N) { return std::max<int64_t>(128, (N + 2047) / 2048); }
 int gmres_nchunk(int64_t N) { return (int)((N + gmres_rows_per_chunk(N) - 1) / gmres_rows_per_chunk(N)); }
 
 size_t gmres_state_bytes(int64_t N, int R, int m) {
