@@ -384,7 +384,7 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_inv_reg_kernel(co
     constexpr int RS = LX * W + W;
     __shared__ C tile[LY * RS];
     const int w = threadIdx.x % W, r = threadIdx.x / W;
-    const int64_t c = (int64_t)blockIdx.x * W + w;
+    const int64_t c = xcd_block(blockIdx.x, gridDim.x) * W + w;
     const bool cv = c < B;
     C out[LX];
 #pragma unroll
@@ -674,9 +674,14 @@ void launch_fft_t(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, con
         if (FWD)
             hipLaunchKernelGGL((fft_fwd_reg_kernel<LX, LY, W, kFmtNone>), dim3((unsigned)blocks), dim3(NT), 0, s, in,
                                (void*)out, g.nx, g.ny, B, twx, twy);
-        else
-            hipLaunchKernelGGL((fft_inv_reg_kernel<LX, LY, W>), dim3((unsigned)blocks), dim3(NT), 0, s, in, out, g.nx,
-                               g.ny, B, twx, twy);
+        else {
+            // the inverse reads four times what it writes: half-size tiles put two
+            // workgroups on a CU, so one loads while the other transforms (pairs of
+            // workgroups that share 128-byte lines run on one XCD)
+            constexpr int WI = W > 8 ? 8 : W;
+            hipLaunchKernelGGL((fft_inv_reg_kernel<LX, LY, WI>), dim3((unsigned)((B + WI - 1) / WI)),
+                               dim3((LX > LY ? LX : LY) * WI), 0, s, in, out, g.nx, g.ny, B, twx, twy);
+        }
         MBT_LAUNCH_CHECK();
         return;
     }
