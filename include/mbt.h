@@ -99,6 +99,11 @@ typedef struct {
  * the default delayed reorthogonalisation (DCGS2, two sweeps; same iterates in
  * exact arithmetic). */
 #define MBT_FLAG_CGS2 2
+/* mbt_solve_opts.flags, reduced precision: keep the inner solve's Krylov basis
+ * in FP32.  By default it is stored packed, each FP32 component rounded to its
+ * top 24 bits (unit roundoff 2^-16, three quarters of the bytes); an odd
+ * number of ports is then solved with one port repeated. */
+#define MBT_FLAG_FP32_BASIS 4
 
 typedef struct {
     int32_t nrhs;             /* RHS solved */

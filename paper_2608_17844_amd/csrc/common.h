@@ -205,7 +205,8 @@ template <typename TS>
 void add_to_f64(double2* x, const TS* d, int64_t n, hipStream_t s);                         // x += d
 void sub_d(const double2* a, const double2* b, double2* out, int64_t n, hipStream_t s);    // out = a - b
 void column_norms(const double2* X, int64_t N, int R, double* partial, double* out, hipStream_t s);
-void gather_ports(const Geom& g, const double2* I, int R, double2* Y, hipStream_t s);      // Y (P x R col-major)
+// Y (P x R col-major) from the port-basis rows of the first R of the Rs columns of I
+void gather_ports(const Geom& g, const double2* I, int Rs, int R, double2* Y, hipStream_t s);
 void transpose_nr(const double2* src, double2* dst, int64_t N, int R, bool to_device_layout, hipStream_t s);
 void scale_columns_d(double2* X, const double* scale, int64_t N, int R, hipStream_t s);      // X[n][r] *= scale[r]
 void zero_d(double2* p, int64_t n, hipStream_t s);                                             // fill kernel, no memset

@@ -45,6 +45,7 @@ struct GmresParams {
     int max_cycles = 400;
     int matvecs_per_apply = 1;
     bool dcgs2 = true;           // delayed reorthogonalisation (two sweeps); false: classical CGS2 (three)
+    bool packed_basis = false;   // FP32 solves with DCGS2, even R, restart >= 4: basis in the packed 24-bit format
     int* host_count = nullptr;   // pinned host int for the active-count readback
 };
 
@@ -59,7 +60,9 @@ int gmres_nchunk(int64_t N);
 size_t gmres_state_bytes(int64_t N, int R, int m);
 
 // Solves A x = b for R independent columns (b, basis of type TB = double2 or
-// float2; x accumulated in FP64).  Vbasis holds (restart+1) vectors of N x R.
+// float2; x accumulated in FP64).  Vbasis holds (restart+1) vectors of N x R of
+// type TB (with a packed basis it holds two TB work vectors and the packed
+// vectors instead, in no more space).
 template <typename TB>
 GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, const TB* b, double2* x, TB* Vbasis,
                           int64_t N, int R, const GmresParams& prm, DevArena& arena, hipStream_t s);

@@ -31,6 +31,7 @@
 #include "gmres.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <vector>
 
@@ -136,6 +137,51 @@ template <> struct Raw<float2, 2> {
     __device__ __forceinline__ double2 get(int k) const { return k ? make_double2(v.z, v.w) : make_double2(v.x, v.y); }
 };
 
+// ------------------------------------------------------------------ packed 24-bit basis storage
+// The mixed path may keep its Krylov basis with the low byte of each FP32
+// component rounded away (sign, 8-bit exponent, 15-bit mantissa; unit roundoff
+// 2^-16), three quarters of the FP32 bytes.  Two complex values of adjacent RHS
+// columns (four components) form one 12-byte word, so a basis vector of N x R
+// values (R even) is N x R/2 words.  The work vectors (the candidate and A times
+// it) stay FP32.
+struct p24x2 {
+    uint32_t w[3];
+};
+template <typename T> struct PerWord { static constexpr int v = 1; };
+template <> struct PerWord<p24x2> { static constexpr int v = 2; };
+// element offset n*R + r (r even for packed words) -> offset in storage words
+template <typename T> __device__ __forceinline__ int64_t vofs(int64_t off) { return off / PerWord<T>::v; }
+
+__device__ __forceinline__ uint32_t to24(double x) {
+    const uint32_t u = __float_as_uint((float)x);
+    return (u + 0x7Fu + ((u >> 8) & 1u)) >> 8;   // nearest, ties to even, on the dropped byte
+}
+__device__ __forceinline__ double from24(uint32_t t) { return (double)__uint_as_float(t << 8); }
+__device__ __forceinline__ double2 round24(double2 v) { return make_double2(from24(to24(v.x)), from24(to24(v.y))); }
+
+template <> struct Raw<p24x2, 2> {
+    uint32_t a, b, c;
+    __device__ __forceinline__ void load(const p24x2* p) {
+        const uint3 t = *reinterpret_cast<const uint3*>(p);
+        a = t.x;
+        b = t.y;
+        c = t.z;
+    }
+    __device__ __forceinline__ void zero() { a = b = c = 0; }
+    __device__ __forceinline__ double2 get(int k) const {
+        if (k == 0) return make_double2(from24(a & 0xFFFFFFu), from24((a >> 24) | ((b & 0xFFFFu) << 8)));
+        return make_double2(from24((b >> 16) | ((c & 0xFFu) << 16)), from24(c >> 8));
+    }
+};
+__device__ __forceinline__ void st24(p24x2* p, double2 v0, double2 v1) {
+    const uint32_t t0 = to24(v0.x), t1 = to24(v0.y), t2 = to24(v1.x), t3 = to24(v1.y);
+    uint3 o;
+    o.x = t0 | (t1 << 24);
+    o.y = (t1 >> 8) | (t2 << 16);
+    o.z = (t2 >> 16) | (t3 << 8);
+    *reinterpret_cast<uint3*>(p) = o;
+}
+
 // One pass over the basis V_0..V_{nvec-1} (rows of one chunk, 64*RPL RHS columns
 // per workgroup).  The NW waves of a workgroup read the same rows and columns
 // and split the basis vectors (wave w takes i = w, w+NW, ..., G per wave); a
@@ -182,7 +228,7 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int i = wave + NW * g;
-            if (i < nvec) v[g].load(V + i * vstride + off);
+            if (i < nvec) v[g].load(V + i * vstride + vofs<TB>(off));
             else v[g].zero();
         }
     };
@@ -262,8 +308,8 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 // Partials per chunk: [s_0..s_{k-1}, z_0..z_{k-1}, alpha, beta].  One launch
 // covers the vectors i0 .. i0+nv-1 (the sweep may be split into launches of at
 // most NW*G vectors); alpha and beta come from the launch with i0 = 0.
-template <typename TB, int NW, int G, int RPL, bool HASW>
-__global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TB* __restrict__ V, int64_t vstride, int k,
+template <typename TB, typename TV, int NW, int G, int RPL, bool HASW>
+__global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TV* __restrict__ V, int64_t vstride, int k,
                                                              int i0, int nv, const TB* __restrict__ u,
                                                              const TB* __restrict__ w, int64_t N, int R,
                                                              int64_t rows_per_chunk, double2* __restrict__ partial) {
@@ -282,15 +328,16 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TB* __restric
 #pragma unroll
         for (int g = 0; g < G; ++g) as[g][k2] = az[g][k2] = make_double2(0, 0);
     }
-    Raw<TB, RPL> cur[G], nxt[G], cu, nu_, cw, nw_;
-    auto load_row = [&](int64_t n, Raw<TB, RPL>(&v)[G], Raw<TB, RPL>& ur, Raw<TB, RPL>& wr) {
+    Raw<TV, RPL> cur[G], nxt[G];
+    Raw<TB, RPL> cu, nu_, cw, nw_;
+    auto load_row = [&](int64_t n, Raw<TV, RPL>(&v)[G], Raw<TB, RPL>& ur, Raw<TB, RPL>& wr) {
         const int64_t off = n * R + r0;
         ur.load(u + off);
         if (HASW) wr.load(w + off);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int j = wave + NW * g;
-            if (j < nv) v[g].load(V + (int64_t)(i0 + j) * vstride + off);
+            if (j < nv) v[g].load(V + (int64_t)(i0 + j) * vstride + vofs<TV>(off));
             else v[g].zero();
         }
     };
@@ -449,24 +496,24 @@ __global__ void dcgs2_coef_kernel(double2* __restrict__ Hraw, const double2* __r
     cc_out[(int64_t)i * R + r] = make_double2(t.x * in + h.x, t.y * in + h.y);
 }
 
-template <typename TB, int RPL, bool HASW>
-void launch_dcgs2_dots_rpl(const TB* V, int64_t vs, int k, int i0, int nv, const TB* u, const TB* w, int64_t N, int R,
+template <typename TB, typename TV, int RPL, bool HASW>
+void launch_dcgs2_dots_rpl(const TV* V, int64_t vs, int k, int i0, int nv, const TB* u, const TB* w, int64_t N, int R,
                            int64_t rpc, int nchunk, double2* partial, hipStream_t s) {
     const dim3 grid((unsigned)((R / RPL + 63) / 64), (unsigned)nchunk);
     if (nv <= 4)
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 1, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, i0, nv, u, w, N, R,
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, TV, 4, 1, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, i0, nv, u, w, N, R,
                            rpc, partial);
     else if (nv <= 8)
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 2, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, i0, nv, u, w, N, R,
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, TV, 4, 2, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, i0, nv, u, w, N, R,
                            rpc, partial);
     else if (nv <= 16)
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 4, 4, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, i0, nv, u, w, N, R,
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, TV, 4, 4, RPL, HASW>), grid, dim3(256), 0, s, V, vs, k, i0, nv, u, w, N, R,
                            rpc, partial);
     else if (nv <= 32)
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 8, 4, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, i0, nv, u, w, N, R,
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, TV, 8, 4, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, i0, nv, u, w, N, R,
                            rpc, partial);
     else
-        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, 8, 8, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, i0, nv, u, w, N, R,
+        hipLaunchKernelGGL((dcgs2_dots_kernel<TB, TV, 8, 8, RPL, HASW>), grid, dim3(512), 0, s, V, vs, k, i0, nv, u, w, N, R,
                            rpc, partial);
     MBT_LAUNCH_CHECK();
 }
@@ -539,8 +586,112 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows_kernel(const TB* __rest
     }
 }
 
-template <typename TB>
-void launch_dcgs2_dots(const TB* V, int64_t vs, int k, const TB* u, const TB* w, int64_t N, int R, int64_t rpc,
+// Row-split update sweep into the packed basis: as dcgs2_update_rows_kernel,
+// with a lane owning two adjacent RHS columns (one packed word per row).  v_k
+// goes to its own slot vk (rounded to the packed format, and the rounded value
+// is the one removed from u_{k+1}); u_{k+1} overwrites u.
+template <int RB>
+__global__ __launch_bounds__(256) void dcgs2_update_rows24_kernel(const p24x2* __restrict__ V, int64_t vstride, int k,
+                                                                  float2* u, const float2* __restrict__ w,
+                                                                  p24x2* __restrict__ vk, const double2* __restrict__ cs,
+                                                                  const double2* __restrict__ cc,
+                                                                  const double* __restrict__ inv_nu, int64_t N, int R) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r0 = 2 * (blockIdx.x * 64 + lane);
+    const int64_t n0 = ((int64_t)blockIdx.y * 4 + wave) * RB;
+    if (r0 >= R || n0 >= N) return;
+    const int nr = (int)min<int64_t>(RB, N - n0);
+    const int64_t rw = R / 2;   // packed words per row
+    double2 a[RB][2], c[RB][2];
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) a[j][q] = c[j][q] = make_double2(0, 0);
+    const p24x2* base = V + (n0 * R + r0) / 2;
+    Raw<p24x2, 2> cur[RB], nxt[RB];
+    auto load = [&](int i, Raw<p24x2, 2>(&v)[RB]) {
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            if (j < nr) v[j].load(base + i * vstride + (int64_t)j * rw);
+            else v[j].zero();
+        }
+    };
+    double2 fs[2] = {make_double2(0, 0), make_double2(0, 0)}, fc[2] = {make_double2(0, 0), make_double2(0, 0)};
+    if (k > 0) {
+        load(0, cur);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            fs[q] = cs[r0 + q];
+            fc[q] = cc[r0 + q];
+        }
+    }
+    for (int i = 0; i < k; ++i) {
+        double2 fs_n[2] = {make_double2(0, 0), make_double2(0, 0)}, fc_n[2] = {make_double2(0, 0), make_double2(0, 0)};
+        if (i + 1 < k) {
+            load(i + 1, nxt);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                fs_n[q] = cs[(int64_t)(i + 1) * R + r0 + q];
+                fc_n[q] = cc[(int64_t)(i + 1) * R + r0 + q];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double2 vv = cur[j].get(q);
+                a[j][q] = cfma(a[j][q], fs[q], vv);
+                c[j][q] = cfma(c[j][q], fc[q], vv);
+            }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) cur[j] = nxt[j];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            fs[q] = fs_n[q];
+            fc[q] = fc_n[q];
+        }
+    }
+    double inu[2];
+    double2 ckv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        inu[q] = inv_nu[r0 + q];
+        ckv[q] = cc[(int64_t)k * R + r0 + q];
+    }
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+        if (j < nr) {
+            const int64_t off = (n0 + j) * R + r0;
+            double2 uv[2], wv[2], v[2], un[2];
+            ldp<2>(u + off, uv);
+            ldp<2>(w + off, wv);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double2 d = csub(uv[q], a[j][q]);
+                v[q] = round24(make_double2(d.x * inu[q], d.y * inu[q]));
+                un[q] = next_candidate(wv[q], inu[q], c[j][q], ckv[q], v[q]);
+            }
+            st24(vk + off / 2, v[0], v[1]);
+            stp<2>(u + off, un);
+        }
+    }
+}
+
+void launch_dcgs2_update24(const p24x2* V, int64_t vs, int k, float2* u, const float2* w, p24x2* vk,
+                           const double2* cs, const double2* cc, const double* inv_nu, int64_t N, int R, hipStream_t s) {
+    constexpr int RB = 4;
+    MBT_REQUIRE(R % 2 == 0, "packed basis needs an even number of RHS");
+    const int64_t rows_per_block = 4 * RB;
+    const int64_t gy = (N + rows_per_block - 1) / rows_per_block;
+    MBT_REQUIRE(gy < 65536, "dcgs2 update: too many row blocks");
+    hipLaunchKernelGGL((dcgs2_update_rows24_kernel<RB>), dim3((unsigned)((R / 2 + 63) / 64), (unsigned)gy), dim3(256), 0,
+                       s, V, vs, k, u, w, vk, cs, cc, inv_nu, N, R);
+    MBT_LAUNCH_CHECK();
+}
+
+template <typename TB, typename TV>
+void launch_dcgs2_dots(const TV* V, int64_t vs, int k, const TB* u, const TB* w, int64_t N, int R, int64_t rpc,
                        int nchunk, double2* partial, hipStream_t s) {
     if constexpr (sizeof(TB) == 8) {
         if (R % 2 == 0) {
@@ -548,14 +699,18 @@ void launch_dcgs2_dots(const TB* V, int64_t vs, int k, const TB* u, const TB* w,
             // vectors per launch: longer sweeps are split, re-reading u and w once more
             for (int i0 = 0; i0 == 0 || i0 < k; i0 += 32) {
                 const int nv = std::min(32, k - i0);
-                if (w) launch_dcgs2_dots_rpl<TB, 2, true>(V, vs, k, i0, nv, u, w, N, R, rpc, nchunk, partial, s);
-                else launch_dcgs2_dots_rpl<TB, 2, false>(V, vs, k, i0, nv, u, w, N, R, rpc, nchunk, partial, s);
+                if (w) launch_dcgs2_dots_rpl<TB, TV, 2, true>(V, vs, k, i0, nv, u, w, N, R, rpc, nchunk, partial, s);
+                else launch_dcgs2_dots_rpl<TB, TV, 2, false>(V, vs, k, i0, nv, u, w, N, R, rpc, nchunk, partial, s);
             }
             return;
         }
     }
-    if (w) launch_dcgs2_dots_rpl<TB, 1, true>(V, vs, k, 0, k, u, w, N, R, rpc, nchunk, partial, s);
-    else launch_dcgs2_dots_rpl<TB, 1, false>(V, vs, k, 0, k, u, w, N, R, rpc, nchunk, partial, s);
+    if constexpr (std::is_same<TV, TB>::value) {
+        if (w) launch_dcgs2_dots_rpl<TB, TV, 1, true>(V, vs, k, 0, k, u, w, N, R, rpc, nchunk, partial, s);
+        else launch_dcgs2_dots_rpl<TB, TV, 1, false>(V, vs, k, 0, k, u, w, N, R, rpc, nchunk, partial, s);
+    } else {
+        throw Error(-1, "packed basis needs an even number of RHS");
+    }
 }
 
 template <typename TB>
@@ -598,14 +753,19 @@ template <typename TB, typename TO, int MODE>
 void launch_pass(const TB* V, int64_t vs, int nvec, const double2* coef, TO* w, int64_t N, int R, int64_t rpc,
                  int nchunk, double2* partial, hipStream_t s, int cfg_n = 0) {
     cfg_n = std::max(cfg_n, nvec);
-    if constexpr (sizeof(TB) == 8) {
-        // the update-and-dot pass over more than 32 vectors keeps one RHS per lane (register budget)
-        if (R % 2 == 0 && !(MODE == 1 && cfg_n > 32)) {
-            launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
-            return;
+    if constexpr (std::is_same<TB, p24x2>::value) {
+        MBT_REQUIRE(R % 2 == 0, "packed basis needs an even number of RHS");
+        launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
+    } else {
+        if constexpr (sizeof(TB) == 8) {
+            // the update-and-dot pass over more than 32 vectors keeps one RHS per lane (register budget)
+            if (R % 2 == 0 && !(MODE == 1 && cfg_n > 32)) {
+                launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
+                return;
+            }
         }
+        launch_pass_rpl<TB, TO, MODE, 1>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
     }
-    launch_pass_rpl<TB, TO, MODE, 1>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
 }
 
 // out[i][r] = sum over chunks of partial[chunk][i][r], in chunk order
@@ -886,36 +1046,55 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
         return *h_count;
     };
 
+    // Packed basis (FP32 work vectors, even R, m >= 4): the candidate u and w = A u
+    // live in two work vectors and the basis vectors in m packed slots, which
+    // together take no more than the m+1 FP32 slots of the plain layout.  Plain
+    // layout: slot k holds the candidate u_k, slot k+1 receives w = A u_k.
+    bool packed = false;
+    if constexpr (std::is_same<TB, float2>::value) packed = prm.packed_basis && prm.dcgs2 && R % 2 == 0 && m >= 4;
+    TB* U = Vbasis;                                   // packed: candidate, residual
+    TB* Wv = Vbasis + vs;                             // packed: A u, iterate copy
+    p24x2* V24 = reinterpret_cast<p24x2*>(Vbasis + 2 * vs);
+    const int64_t vs24 = vs / 2;
+    TB* r0v = Vbasis;                                 // residual / first candidate (both layouts)
+    TB* xb = Vbasis + vs;                             // iterate in the basis type (both layouts)
+
     // x = 0, r0 = b
     hipLaunchKernelGGL(zero_kernel, dim3(ew_grid(vs)), dim3(256), 0, s, x, vs);
-    hipLaunchKernelGGL((copy_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, b, Vbasis, vs);
+    hipLaunchKernelGGL((copy_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, b, r0v, vs);
     MBT_LAUNCH_CHECK();
     bool first = true;
     for (int cycle = 0; cycle < prm.max_cycles; ++cycle) {
-        // beta = ||r|| (r sits in V_0)
-        hipLaunchKernelGGL((colnorm2_kernel<TB>), dim3((R + 63) / 64, nchunk), dim3(64), 0, s, Vbasis, N, R, rpc, partial);
+        // beta = ||r|| (r sits in V_0, or in the candidate vector when packed)
+        hipLaunchKernelGGL((colnorm2_kernel<TB>), dim3((R + 63) / 64, nchunk), dim3(64), 0, s, r0v, N, R, rpc, partial);
         hipLaunchKernelGGL(cycle_init_kernel, gR, bR, 0, s, st, partial, nchunk, R, first ? 1 : 0);
         MBT_LAUNCH_CHECK();
         first = false;
         if (count_active() == 0) break;
         res.cycles++;
-        hipLaunchKernelGGL((scale_cols_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, Vbasis, st.scale, N, R);
+        hipLaunchKernelGGL((scale_cols_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, r0v, st.scale, N, R);
         MBT_LAUNCH_CHECK();
         int steps = 0;
-        // delayed reorthogonalisation: slot k holds the candidate u_k, slot k+1 receives w = A u_k;
-        // one dot sweep and one update sweep per step (the last step needs only the dots of u_m)
+        // delayed reorthogonalisation: one dot sweep and one update sweep per step
+        // (the last step needs only the dots of u_m)
         for (int k = 0; prm.dcgs2 && k <= m; ++k) {
             const bool hasw = k < m;
-            TB* u = Vbasis + (int64_t)k * vs;
-            TB* w = hasw ? Vbasis + (int64_t)(k + 1) * vs : nullptr;
+            TB* u = packed ? U : Vbasis + (int64_t)k * vs;
+            TB* w = hasw ? (packed ? Wv : Vbasis + (int64_t)(k + 1) * vs) : nullptr;
             if (hasw) {
                 apply(u, w);
                 res.matvecs += prm.matvecs_per_apply;
             }
             const double vbytes = (double)vs * sizeof(TB);
+            const double bbytes = packed ? (double)vs * 6.0 : vbytes;   // one basis vector
             {
-                ProfScope ps(kKArnoldiDots, (k + (hasw ? 2 : 1)) * vbytes, 8.0 * (2 * k + 2) * vs, s);
-                launch_dcgs2_dots<TB>(Vbasis, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+                ProfScope ps(kKArnoldiDots, k * bbytes + (hasw ? 2 : 1) * vbytes, 8.0 * (2 * k + 2) * vs, s);
+                if (packed) {
+                    if constexpr (std::is_same<TB, float2>::value)
+                        launch_dcgs2_dots<TB, p24x2>(V24, vs24, k, u, w, N, R, rpc, nchunk, partial, s);
+                } else {
+                    launch_dcgs2_dots<TB, TB>(Vbasis, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+                }
             }
             const int nred = 2 * k + 2;
             hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nred * R + 255) / 256)), bR, 0, s,
@@ -928,8 +1107,15 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
                                coef_s, coef_c);
             MBT_LAUNCH_CHECK();
             {
-                ProfScope ps(kKArnoldiUpdateDots, (k + 2) * vbytes + 2 * vbytes, 16.0 * k * vs, s);
-                launch_dcgs2_update<TB>(Vbasis, vs, k, u, w, coef_s, coef_c, inv_nu, N, R, rpc, nchunk, s);
+                // k basis vectors, u and w read; v_k and u_{k+1} written
+                ProfScope ps(kKArnoldiUpdateDots, (k + 1) * bbytes + 3 * vbytes, 16.0 * k * vs, s);
+                if (packed) {
+                    if constexpr (std::is_same<TB, float2>::value)
+                        launch_dcgs2_update24(V24, vs24, k, U, Wv, V24 + (int64_t)k * vs24, coef_s, coef_c, inv_nu, N,
+                                              R, s);
+                } else {
+                    launch_dcgs2_update<TB>(Vbasis, vs, k, u, w, coef_s, coef_c, inv_nu, N, R, rpc, nchunk, s);
+                }
             }
         }
         for (int j = 0; !prm.dcgs2 && j < m; ++j) {
@@ -967,9 +1153,11 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
         MBT_LAUNCH_CHECK();
         // configuration fixed by m: a RHS's update x += V y does not depend on how long
         // the other RHS of the batch kept the cycle going
-        launch_pass<TB, double2, 3>(Vbasis, vs, steps, y, x, N, R, rpc, nchunk, partial, s, m);
+        if (packed)
+            launch_pass<p24x2, double2, 3>(V24, vs24, steps, y, x, N, R, rpc, nchunk, partial, s, m);
+        else
+            launch_pass<TB, double2, 3>(Vbasis, vs, steps, y, x, N, R, rpc, nchunk, partial, s, m);
         // explicit residual r = b - A x into V_0 (x cast to the basis type into V_1 first)
-        TB* xb = Vbasis + vs;
         hipLaunchKernelGGL((from_f64_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, x, xb, vs);
         MBT_LAUNCH_CHECK();
         // all converged? then skip the residual
@@ -981,9 +1169,9 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
         bool all = true;
         for (int r = 0; r < R; ++r) all = all && (conv[r] || flag[r]);
         if (all) break;
-        apply(xb, Vbasis);
+        apply(xb, r0v);
         res.matvecs += prm.matvecs_per_apply;
-        hipLaunchKernelGGL((residual_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, b, Vbasis, vs);
+        hipLaunchKernelGGL((residual_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, b, r0v, vs);
         MBT_LAUNCH_CHECK();
     }
     MBT_HIP(hipMemcpyAsync(res.iters.data(), st.iters, sizeof(int) * R, hipMemcpyDeviceToHost, s));

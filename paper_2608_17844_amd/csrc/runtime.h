@@ -78,6 +78,7 @@ struct Worker {
 
 struct SolveOut {
     std::vector<int> iters;
+    std::vector<char> conv, flag;   // per RHS
     int cycles = 0, outer = 0, nconv = 0, nflag = 0;
     int64_t matvecs = 0;
     double relres_max = 0;
@@ -120,6 +121,9 @@ int fmt16_of(int prec);
 size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o);
 // Largest RHS batch (<= R) whose solve workspace fits `budget` bytes.
 int choose_chunk(size_t budget, const Geom& g, int R, const mbt_solve_opts& o);
+// columns actually solved for a batch of R ports (reduced precision with the
+// packed basis repeats the last port of an odd batch)
+int padded(int R, const mbt_solve_opts& o);
 // Device bytes of the extraction buffers of one frequency (Y_p, Z_p, S, work, scans).
 size_t extract_bytes(int P, int nscan);
 // Solves Z X = V for R device columns (layout [n][r]); X receives FP64 currents.

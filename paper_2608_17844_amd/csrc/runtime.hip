@@ -134,7 +134,7 @@ void validate_opts(const mbt_solve_opts& o) {
     MBT_REQUIRE(o.max_cycles >= 1, "max_cycles must be >= 1");
     MBT_REQUIRE(o.prec == MBT_FP64 || (o.refine_max >= 1 && o.refine_tol > 0), "refinement options invalid");
     MBT_REQUIRE(o.rhs_chunk >= 0, "rhs_chunk must be >= 0");
-    MBT_REQUIRE((o.flags & ~(MBT_FLAG_NO_CACHE | MBT_FLAG_CGS2)) == 0, "unknown flags");
+    MBT_REQUIRE((o.flags & ~(MBT_FLAG_NO_CACHE | MBT_FLAG_CGS2 | MBT_FLAG_FP32_BASIS)) == 0, "unknown flags");
 }
 
 static double inner_tol(const mbt_solve_opts& o) {
@@ -475,11 +475,20 @@ size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o) {
     return b;
 }
 
+// The packed basis of the reduced-precision paths takes RHS in pairs: an odd
+// batch is solved with its last port repeated (the extra column is identical
+// and dropped).
+static bool pads_odd(const mbt_solve_opts& o) {
+    return o.prec != MBT_FP64 && !(o.flags & MBT_FLAG_FP32_BASIS) && !(o.flags & MBT_FLAG_CGS2);
+}
+int padded(int R, const mbt_solve_opts& o) { return R + ((pads_odd(o) && (R & 1)) ? 1 : 0); }
+
 int choose_chunk(size_t budget, const Geom& g, int R, const mbt_solve_opts& o) {
     if (o.rhs_chunk > 0) return std::min(R, o.rhs_chunk);
     int c = R;
-    while (c > 1 && solve_bytes(g, c, o) > budget) c = (c + 1) / 2;
-    if (solve_bytes(g, c, o) > budget) throw Error(-2, "one right-hand side does not fit the device-memory budget");
+    while (c > 1 && solve_bytes(g, padded(c, o), o) > budget) c = (c + 1) / 2;
+    if (solve_bytes(g, padded(c, o), o) > budget)
+        throw Error(-2, "one right-hand side does not fit the device-memory budget");
     return c;
 }
 
@@ -515,6 +524,8 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
     hipStream_t s = wk.stream;
     SolveOut out;
     out.iters.assign(R, 0);
+    out.conv.assign(R, 0);
+    out.flag.assign(R, 0);
     void* Xh = arena.get<double2>((size_t)g.bins() * g.M * R);
     void* Yh = arena.get<double2>((size_t)g.bins() * g.M * R);
     double2* tmp = arena.get<double2>(NR);
@@ -524,6 +535,7 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
     prm.matvecs_per_apply = o.pc == MBT_PC_NORMAL_EQ ? 2 : 1;
     prm.host_count = wk.host_count;
     prm.dcgs2 = !(o.flags & MBT_FLAG_CGS2);
+    prm.packed_basis = o.prec != MBT_FP64 && !(o.flags & MBT_FLAG_FP32_BASIS);
     std::vector<double> vn;
     norms_host(V, g.N, R, arena, vn, s);
 
@@ -541,8 +553,10 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
         out.matvecs += gr.matvecs;
         out.outer = 1;
         for (int r = 0; r < R; ++r) {
-            out.nconv += gr.conv[r] ? 1 : 0;
-            out.nflag += gr.flag[r] ? 1 : 0;
+            out.conv[r] = gr.conv[r] ? 1 : 0;
+            out.flag[r] = gr.flag[r] ? 1 : 0;
+            out.nconv += out.conv[r];
+            out.nflag += out.flag[r];
         }
     } else {
         float2* basis = arena.get<float2>((size_t)(m + 1) * NR);
@@ -605,8 +619,10 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
         norms_host(r64, g.N, R, arena, rn, s);
         for (int r = 0; r < R; ++r) {
             const double rel = vn[r] > 0 ? rn[r] / vn[r] : 0.0;
-            out.nconv += (rel <= o.refine_tol && !flagged[r]) ? 1 : 0;
-            out.nflag += flagged[r];
+            out.conv[r] = (rel <= o.refine_tol && !flagged[r]) ? 1 : 0;
+            out.flag[r] = flagged[r] ? 1 : 0;
+            out.nconv += out.conv[r];
+            out.nflag += out.flag[r];
             out.relres_max = std::max(out.relres_max, rel);
         }
         return out;
@@ -642,29 +658,42 @@ SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t*
     MBT_HIP(hipStreamSynchronize(wk.stream));
     const double t1 = now_s();
     const int chunk = choose_chunk(budget, g, nports, o);
-    const size_t need = solve_bytes(g, chunk, o) + sizeof(int32_t) * nports + 4096;
+    // port list laid out chunk by chunk, odd chunks padded with their last port
+    std::vector<int32_t> plist;
+    plist.reserve((size_t)nports + (size_t)nports / std::max(chunk, 1) + 1);
+    for (int c0 = 0; c0 < nports; c0 += chunk) {
+        const int R = std::min(chunk, nports - c0);
+        plist.insert(plist.end(), ports + c0, ports + c0 + R);
+        if (padded(R, o) > R) plist.push_back(ports[c0 + R - 1]);
+    }
+    const size_t need = solve_bytes(g, padded(chunk, o), o) + sizeof(int32_t) * plist.size() + 4096;
     wk.ensure(need);
     DevArena arena;
     arena.base = wk.ws.as<char>();
     arena.cap = wk.ws.bytes;
-    int32_t* dports = arena.get<int32_t>(nports);
-    MBT_HIP(hipMemcpyAsync(dports, ports, sizeof(int32_t) * nports, hipMemcpyHostToDevice, wk.stream));
+    int32_t* dports = arena.get<int32_t>(plist.size());
+    MBT_HIP(hipMemcpyAsync(dports, plist.data(), sizeof(int32_t) * plist.size(), hipMemcpyHostToDevice, wk.stream));
     SolveOut total;
     total.iters.assign(nports, 0);
     const size_t base_mark = arena.off;
+    int64_t pl0 = 0;
     for (int c0 = 0; c0 < nports; c0 += chunk) {
         const int R = std::min(chunk, nports - c0);
+        const int Rs = padded(R, o);   // columns solved
         arena.off = base_mark;
-        double2* V = arena.get<double2>((size_t)g.N * R);
-        double2* X = arena.get<double2>((size_t)g.N * R);
-        scatter_ports(g, dports + c0, R, V, wk.stream);
-        SolveOut so = solve_rhs(*op, o, V, R, X, wk, arena);
-        gather_ports(g, X, R, Ydev + (int64_t)c0 * g.P, wk.stream);
+        double2* V = arena.get<double2>((size_t)g.N * Rs);
+        double2* X = arena.get<double2>((size_t)g.N * Rs);
+        scatter_ports(g, dports + pl0, Rs, V, wk.stream);
+        pl0 += Rs;
+        SolveOut so = solve_rhs(*op, o, V, Rs, X, wk, arena);
+        gather_ports(g, X, Rs, R, Ydev + (int64_t)c0 * g.P, wk.stream);
         for (int r = 0; r < R; ++r) total.iters[c0 + r] = so.iters[r];
         total.cycles = std::max(total.cycles, so.cycles);
         total.outer = std::max(total.outer, so.outer);
-        total.nconv += so.nconv;
-        total.nflag += so.nflag;
+        for (int r = 0; r < R; ++r) {   // the padding column (a repeat) is not counted
+            total.nconv += so.conv[r];
+            total.nflag += so.flag[r];
+        }
         total.matvecs += so.matvecs;
         total.relres_max = std::max(total.relres_max, so.relres_max);
     }
@@ -863,7 +892,7 @@ size_t mbt_footprint(const mbt_array* a, int32_t nrhs, const mbt_solve_opts* o) 
         size_t opb = (size_t)g.noff() * MM * 16 + (size_t)g.bins() * MM * 16 + (size_t)g.P * MM * 16 * 2;
         if (o->prec != MBT_FP64) opb += (size_t)g.bins() * MM * 8 + (size_t)g.P * MM * 8;
         if (fmt16_of(o->prec) != kFmtNone) opb += (size_t)g.bins() * MM * 4;
-        return solve_bytes(g, nrhs, *o) + opb;
+        return solve_bytes(g, padded(nrhs, *o), *o) + opb;
     } catch (...) {
         return 0;
     }

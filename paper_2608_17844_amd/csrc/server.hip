@@ -205,7 +205,9 @@ mbt_status mbt_server_submit(mbt_server* srv, const mbt_request* req, uint64_t* 
         rq->need_xs = extract_bytes(g.P, req->nscan);
         const size_t xs_held = Worker::grown(0, rq->need_xs);
         if (xs_held >= srv->budget) throw Error(MBT_ENOMEM, "request does not fit the device-memory budget");
-        auto ws_for = [&](int c) { return solve_bytes(g, c, rq->opts) + sizeof(int32_t) * g.P + 4096; };
+        auto ws_for = [&](int c) {
+            return solve_bytes(g, padded(c, rq->opts), rq->opts) + sizeof(int32_t) * (g.P + g.P / c + 1) + 4096;
+        };
         int chunk = req->opts.rhs_chunk > 0 ? std::min(req->opts.rhs_chunk, g.P) : g.P;
         if (req->opts.rhs_chunk <= 0) {
             const size_t half = srv->budget / 2;

@@ -96,12 +96,14 @@ __global__ void colnorm_final_kernel(const double* __restrict__ partial, int nch
 }
 
 // Y[i + P*r] = I[(i*M + pc)][r]   (column-major P x R output)
-__global__ void gather_ports_kernel(const double2* __restrict__ I, int P, int M, int pc, int R, double2* __restrict__ Y) {
+// Y[r][i] = I[i*M + pc][r] for the first R of the Rs columns of I
+__global__ void gather_ports_kernel(const double2* __restrict__ I, int P, int M, int pc, int Rs, int R,
+                                    double2* __restrict__ Y) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= (int64_t)P * R) return;
     const int i = (int)(t % P);
     const int r = (int)(t / P);
-    Y[t] = I[((int64_t)i * M + pc) * R + r];
+    Y[t] = I[((int64_t)i * M + pc) * Rs + r];
 }
 
 // to_device_layout: dst[n][r] = src[n + N*r]; else dst[n + N*r] = src[n][r]
@@ -199,9 +201,11 @@ void column_norms(const double2* X, int64_t N, int R, double* partial, double* o
     MBT_LAUNCH_CHECK();
 }
 
-void gather_ports(const Geom& g, const double2* I, int R, double2* Y, hipStream_t s) {
+void gather_ports(const Geom& g, const double2* I, int Rs, int R, double2* Y, hipStream_t s) {
+    MBT_REQUIRE(R <= Rs, "gather_ports: more columns than solved");
     const int64_t n = (int64_t)g.P * R;
-    hipLaunchKernelGGL(gather_ports_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, I, g.P, g.M, g.pc, R, Y);
+    hipLaunchKernelGGL(gather_ports_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, I, g.P, g.M, g.pc, Rs, R,
+                       Y);
     MBT_LAUNCH_CHECK();
 }
 

@@ -72,3 +72,31 @@ def test_repeated_and_empty_port_lists(setup):
     with pytest.raises(mbt.MbtError) as ei:
         mbt.mbt_port_admittance(ctx, arr, 1.0, [], opts)
     assert ei.value.status == mbt.MBT_EINVAL
+
+
+def test_packed_basis_against_fp32_basis(setup):
+    """The reduced-precision inner solves keep their Krylov basis packed (FP32
+    components rounded to 24 bits) unless told otherwise; both forms reach the
+    same refined accuracy with about the same work, and an odd port count
+    (solved with one port repeated) reports every port exactly once."""
+    mbt, ctx, arr, ref = setup
+    res = {}
+    for name, flags in (("packed", 0), ("fp32", mbt.MBT_FLAG_FP32_BASIS)):
+        opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=32, tol=1e-11,
+                                    refine_tol=1e-10, refine_max=4, flags=flags)
+        Y, iters, st = mbt.mbt_port_admittance(ctx, arr, 1.0, None, opts)
+        err = np.linalg.norm(Y - ref.Yp) / np.linalg.norm(ref.Yp)
+        _say("%s basis: iters %d..%d (total %d), outer %d, err %.2e" % (name, iters.min(), iters.max(), iters.sum(),
+                                                                         st["outer_steps"], err))
+        assert err <= 1e-8
+        assert st["nconverged"] == 256
+        res[name] = (iters, st)
+    ip, ifp = res["packed"][0], res["fp32"][0]
+    assert abs(int(ip.sum()) - int(ifp.sum())) <= 0.1 * ifp.sum()
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, tol=1e-11, refine_tol=1e-10,
+                                refine_max=4)
+    odd = [0, 17, 255]
+    Y3, it3, st3 = mbt.mbt_port_admittance(ctx, arr, 1.0, odd, opts)
+    assert Y3.shape == (256, 3) and it3.shape == (3,)
+    assert st3["nrhs"] == 3 and st3["nconverged"] == 3
+    assert np.linalg.norm(Y3 - ref.Yp[:, odd]) <= 1e-8 * np.linalg.norm(ref.Yp[:, odd])
