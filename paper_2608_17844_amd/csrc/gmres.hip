@@ -680,7 +680,7 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows24_kernel(const p24x2* _
 
 void launch_dcgs2_update24(const p24x2* V, int64_t vs, int k, float2* u, const float2* w, p24x2* vk,
                            const double2* cs, const double2* cc, const double* inv_nu, int64_t N, int R, hipStream_t s) {
-    constexpr int RB = 4;
+    constexpr int RB = 8;
     MBT_REQUIRE(R % 2 == 0, "packed basis needs an even number of RHS");
     const int64_t rows_per_block = 4 * RB;
     const int64_t gy = (N + rows_per_block - 1) / rows_per_block;
