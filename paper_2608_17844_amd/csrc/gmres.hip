@@ -189,7 +189,6 @@ __device__ __forceinline__ void st24(p24x2* p, double2 v0, double2 v1) {
 // MODE 0: h[i] = sum_n conj(V_i[n]) w[n]                         (partials per chunk)
 // MODE 1: w <- w - sum_i coef_i V_i ; h2[i] = sum_n conj(V_i) w   (partials per chunk)
 // MODE 2: w <- w - sum_i coef_i V_i ; ||w||^2                      (partials per chunk)
-// MODE 3: out <- out + sum_i coef_i V_i  (out is FP64; solution update)
 template <typename TB, typename TO, int MODE, int NW, int G, int RPL>
 __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__ V, int64_t vstride, int nvec,
                                                           const double2* __restrict__ coef, TO* w, int64_t N, int R,
@@ -266,7 +265,7 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
                 double2 tot = xch[buf][0][lane * RPL + k];
 #pragma unroll
                 for (int q = 1; q < NW; ++q) tot = cadd(tot, xch[buf][q][lane * RPL + k]);
-                nw[k] = (MODE == 3) ? cadd(wv[k], tot) : csub(wv[k], tot);
+                nw[k] = csub(wv[k], tot);
             }
             buf ^= 1;
             if (live) {
@@ -690,6 +689,84 @@ void launch_dcgs2_update24(const p24x2* V, int64_t vs, int k, float2* u, const f
     MBT_LAUNCH_CHECK();
 }
 
+// End of a cycle: x += sum_{i < steps} y_i V_i.  Each wave owns RB rows of 64
+// lanes (RPL adjacent RHS per lane) and walks the vectors in order, so a
+// RHS's sum has the same order whatever the batch and however long the cycle
+// of the other RHS ran.
+template <typename TV, int RPL, int RB>
+__global__ __launch_bounds__(256) void solution_update_kernel(const TV* __restrict__ V, int64_t vstride, int steps,
+                                                              const double2* __restrict__ y, double2* __restrict__ x,
+                                                              int64_t N, int R) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r0 = (blockIdx.x * 64 + lane) * RPL;
+    const int64_t n0 = ((int64_t)blockIdx.y * 4 + wave) * RB;
+    if (r0 >= R || n0 >= N) return;
+    const int nr = (int)min<int64_t>(RB, N - n0);
+    double2 acc[RB][RPL];
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) acc[j][q] = make_double2(0, 0);
+    Raw<TV, RPL> cur[RB], nxt[RB];
+    auto load = [&](int i, Raw<TV, RPL>(&v)[RB]) {
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            if (j < nr) v[j].load(V + i * vstride + vofs<TV>((n0 + j) * R + r0));
+            else v[j].zero();
+        }
+    };
+    double2 yc[RPL];
+    if (steps > 0) {
+        load(0, cur);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) yc[q] = y[r0 + q];
+    }
+    for (int i = 0; i < steps; ++i) {
+        double2 yn[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) yn[q] = make_double2(0, 0);
+        if (i + 1 < steps) {
+            load(i + 1, nxt);
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) yn[q] = y[(int64_t)(i + 1) * R + r0 + q];
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) acc[j][q] = cfma(acc[j][q], yc[q], cur[j].get(q));
+#pragma unroll
+        for (int j = 0; j < RB; ++j) cur[j] = nxt[j];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) yc[q] = yn[q];
+    }
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+        if (j < nr) {
+            const int64_t off = (n0 + j) * R + r0;
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) x[off + q] = cadd(x[off + q], acc[j][q]);
+        }
+    }
+}
+
+template <typename TV>
+void launch_solution_update(const TV* V, int64_t vs, int steps, const double2* y, double2* x, int64_t N, int R,
+                            hipStream_t s) {
+    constexpr int RB = 8;
+    const int64_t gy = (N + 4 * RB - 1) / (4 * RB);
+    MBT_REQUIRE(gy < 65536, "solution update: too many row blocks");
+    if constexpr (std::is_same<TV, p24x2>::value) {
+        MBT_REQUIRE(R % 2 == 0, "packed basis needs an even number of RHS");
+        hipLaunchKernelGGL((solution_update_kernel<TV, 2, RB>), dim3((unsigned)((R / 2 + 63) / 64), (unsigned)gy),
+                           dim3(256), 0, s, V, vs, steps, y, x, N, R);
+    } else {
+        hipLaunchKernelGGL((solution_update_kernel<TV, 1, RB>), dim3((unsigned)((R + 63) / 64), (unsigned)gy),
+                           dim3(256), 0, s, V, vs, steps, y, x, N, R);
+    }
+    MBT_LAUNCH_CHECK();
+}
+
 template <typename TB, typename TV>
 void launch_dcgs2_dots(const TV* V, int64_t vs, int k, const TB* u, const TB* w, int64_t N, int R, int64_t rpc,
                        int nchunk, double2* partial, hipStream_t s) {
@@ -745,38 +822,61 @@ void launch_pass_rpl(const TB* V, int64_t vs, int nvec, const double2* coef, TO*
 }
 
 // FP32 bases with an even number of columns move two RHS per 16-byte access.
-// cfg_n (>= nvec) selects the kernel configuration: the order in which a lane's
-// sum over basis vectors is split across waves depends only on it, so a caller
-// that passes a fixed cfg_n gets results independent of nvec's value for
-// vectors beyond a RHS's own range (their coefficients are zero).
+// The kernel configuration follows nvec (the classical CGS2 sweeps).
 template <typename TB, typename TO, int MODE>
 void launch_pass(const TB* V, int64_t vs, int nvec, const double2* coef, TO* w, int64_t N, int R, int64_t rpc,
-                 int nchunk, double2* partial, hipStream_t s, int cfg_n = 0) {
-    cfg_n = std::max(cfg_n, nvec);
-    if constexpr (std::is_same<TB, p24x2>::value) {
-        MBT_REQUIRE(R % 2 == 0, "packed basis needs an even number of RHS");
-        launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
-    } else {
-        if constexpr (sizeof(TB) == 8) {
-            // the update-and-dot pass over more than 32 vectors keeps one RHS per lane (register budget)
-            if (R % 2 == 0 && !(MODE == 1 && cfg_n > 32)) {
-                launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
-                return;
-            }
+                 int nchunk, double2* partial, hipStream_t s) {
+    const int cfg_n = nvec;
+    if constexpr (sizeof(TB) == 8) {
+        // the update-and-dot pass over more than 32 vectors keeps one RHS per lane (register budget)
+        if (R % 2 == 0 && !(MODE == 1 && cfg_n > 32)) {
+            launch_pass_rpl<TB, TO, MODE, 2>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
+            return;
         }
-        launch_pass_rpl<TB, TO, MODE, 1>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
     }
+    launch_pass_rpl<TB, TO, MODE, 1>(V, vs, nvec, coef, w, N, R, rpc, nchunk, partial, s, cfg_n);
 }
 
 // out[i][r] = sum over chunks of partial[chunk][i][r], in chunk order
-__global__ void reduce_partials_kernel(const double2* __restrict__ partial, int nchunk, int nvec, int R,
-                                       double2* __restrict__ out) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (int64_t)nvec * R) return;
-    const int i = (int)(t / R), r = (int)(t % R);
-    double2 s = make_double2(0, 0);
-    for (int c = 0; c < nchunk; ++c) s = cadd(s, partial[((int64_t)c * nvec + i) * R + r]);
-    out[t] = s;
+// out[t] = sum over chunks c of partial[c][t], t < nvec*R, in an order fixed by
+// nchunk alone: groups of kRedGroup consecutive chunks are summed in chunk
+// order, then the group sums in group order.  A workgroup owns 64 outputs and
+// its waves share the groups, so a short batch still spreads its (up to 2048)
+// chunks over many loads in flight.
+constexpr int kRedGroup = 64;
+constexpr int kRedWaves = 8;
+constexpr int kMaxChunks = 2048;
+__global__ __launch_bounds__(64 * kRedWaves) void reduce_partials_kernel(const double2* __restrict__ partial,
+                                                                         int nchunk, int nvec, int R,
+                                                                         double2* __restrict__ out) {
+    __shared__ double2 gs[kMaxChunks / kRedGroup][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t nout = (int64_t)nvec * R;
+    const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+    const int ng = (nchunk + kRedGroup - 1) / kRedGroup;
+    for (int g = wave; g < ng; g += kRedWaves) {
+        double2 sg = make_double2(0, 0);
+        if (t < nout) {
+            const int c1 = min(nchunk, (g + 1) * kRedGroup);
+            for (int c = g * kRedGroup; c < c1; ++c) sg = cadd(sg, partial[(int64_t)c * nout + t]);
+        }
+        gs[g][lane] = sg;
+    }
+    __syncthreads();
+    if (wave == 0 && t < nout) {
+        double2 sum = gs[0][lane];
+        for (int g = 1; g < ng; ++g) sum = cadd(sum, gs[g][lane]);
+        out[t] = sum;
+    }
+}
+
+void launch_reduce_partials(const double2* partial, int nchunk, int nvec, int R, double2* out, hipStream_t s) {
+    MBT_REQUIRE(nchunk >= 1 && nchunk <= kMaxChunks, "reduction: too many chunks");
+    const int64_t nout = (int64_t)nvec * R;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nout + 63) / 64)), dim3(64 * kRedWaves), 0, s, partial,
+                       nchunk, nvec, R, out);
+    MBT_LAUNCH_CHECK();
 }
 
 template <typename TB>
@@ -800,11 +900,12 @@ __device__ __forceinline__ double sum_norm_partials(const double2* partial, int 
     return sqrt(s);
 }
 
-// Start of a restart cycle: beta = ||r||; decide convergence at restart.
-__global__ void cycle_init_kernel(GmresState st, const double2* __restrict__ partial, int nchunk, int R, int first) {
+// Start of a restart cycle: beta = ||r|| (nrm2: the reduced squared norms);
+// decide convergence at restart.
+__global__ void cycle_init_kernel(GmresState st, const double2* __restrict__ nrm2, int R, int first) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
-    const double beta = sum_norm_partials(partial, nchunk, R, r);
+    const double beta = sqrt(nrm2[r].x);
     if (first) {
         st.bnorm[r] = beta;
         st.conv[r] = (beta == 0.0) ? 1 : 0;
@@ -981,6 +1082,7 @@ size_t gmres_state_bytes(int64_t N, int R, int m) {
     s += sizeof(double2) * (size_t)(m + 1) * R * 2;            // h1, h2
     s += sizeof(double2) * (size_t)m * R;                      // y
     s += sizeof(double2) * (size_t)nchunk * (2 * m + 2) * R;   // partials
+    s += sizeof(double2) * (size_t)R + 256;                    // reduced squared norms
     s += sizeof(double) * (size_t)R * 4 + sizeof(int) * (size_t)R * 6 + 64;
     // delayed reorthogonalisation: unrotated Hessenberg, reduced sweep, coefficients, 1/nu
     s += sizeof(double2) * (size_t)(m + 1) * (m + 1) * R + sizeof(double2) * (size_t)(2 * m + 2) * R +
@@ -1017,6 +1119,7 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     double2* h2 = arena.get<double2>((size_t)(m + 1) * R);
     double2* y = arena.get<double2>((size_t)m * R);
     double2* partial = arena.get<double2>((size_t)nchunk * (2 * m + 2) * R);
+    double2* nrm2 = arena.get<double2>(R);
     double2* Hraw = nullptr;
     double2* red = nullptr;
     double2* coef_s = nullptr;
@@ -1067,7 +1170,8 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     for (int cycle = 0; cycle < prm.max_cycles; ++cycle) {
         // beta = ||r|| (r sits in V_0, or in the candidate vector when packed)
         hipLaunchKernelGGL((colnorm2_kernel<TB>), dim3((R + 63) / 64, nchunk), dim3(64), 0, s, r0v, N, R, rpc, partial);
-        hipLaunchKernelGGL(cycle_init_kernel, gR, bR, 0, s, st, partial, nchunk, R, first ? 1 : 0);
+        launch_reduce_partials(partial, nchunk, 1, R, nrm2, s);
+        hipLaunchKernelGGL(cycle_init_kernel, gR, bR, 0, s, st, nrm2, R, first ? 1 : 0);
         MBT_LAUNCH_CHECK();
         first = false;
         if (count_active() == 0) break;
@@ -1097,8 +1201,7 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
                 }
             }
             const int nred = 2 * k + 2;
-            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nred * R + 255) / 256)), bR, 0, s,
-                               partial, nchunk, nred, R, red);
+            launch_reduce_partials(partial, nchunk, nred, R, red, s);
             hipLaunchKernelGGL(dcgs2_finalize_kernel, gR, bR, 0, s, st, Hraw, red, R, k, m, inv_nu);
             MBT_LAUNCH_CHECK();
             steps = k;
@@ -1131,14 +1234,12 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
                 ProfScope ps(kKArnoldiDots, (nvec + 1) * vbytes, 8.0 * nvec * vs, s);
                 launch_pass<TB, TB, 0>(Vbasis, vs, nvec, nullptr, w, N, R, rpc, nchunk, partial, s);
             }
-            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nvec * R + 255) / 256)), bR, 0, s,
-                               partial, nchunk, nvec, R, h1);
+            launch_reduce_partials(partial, nchunk, nvec, R, h1, s);
             {
                 ProfScope ps(kKArnoldiUpdateDots, (nvec + 2) * vbytes, 16.0 * nvec * vs, s);
                 launch_pass<TB, TB, 1>(Vbasis, vs, nvec, h1, w, N, R, rpc, nchunk, partial, s);
             }
-            hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(((int64_t)nvec * R + 255) / 256)), bR, 0, s,
-                               partial, nchunk, nvec, R, h2);
+            launch_reduce_partials(partial, nchunk, nvec, R, h2, s);
             {
                 ProfScope ps(kKArnoldiUpdateNorm, (nvec + 2) * vbytes, 8.0 * nvec * vs, s);
                 launch_pass<TB, TB, 2>(Vbasis, vs, nvec, h2, w, N, R, rpc, nchunk, partial, s);
@@ -1154,9 +1255,9 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
         // configuration fixed by m: a RHS's update x += V y does not depend on how long
         // the other RHS of the batch kept the cycle going
         if (packed)
-            launch_pass<p24x2, double2, 3>(V24, vs24, steps, y, x, N, R, rpc, nchunk, partial, s, m);
+            launch_solution_update<p24x2>(V24, vs24, steps, y, x, N, R, s);
         else
-            launch_pass<TB, double2, 3>(Vbasis, vs, steps, y, x, N, R, rpc, nchunk, partial, s, m);
+            launch_solution_update<TB>(Vbasis, vs, steps, y, x, N, R, s);
         // explicit residual r = b - A x into V_0 (x cast to the basis type into V_1 first)
         hipLaunchKernelGGL((from_f64_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, x, xb, vs);
         MBT_LAUNCH_CHECK();

@@ -3,6 +3,8 @@
 // host-layout transposes.
 #include "common.h"
 
+#include <algorithm>
+
 namespace mbt {
 
 namespace {
@@ -87,12 +89,32 @@ __global__ void colnorm_partial_kernel(const double2* __restrict__ X, int64_t N,
     partial[chunk * R + r] = s;
 }
 
-__global__ void colnorm_final_kernel(const double* __restrict__ partial, int nchunk, int R, double* __restrict__ out) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    double s = 0;
-    for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * R + r];
-    out[r] = sqrt(s);
+// out[r] = sqrt(sum over chunks of partial[c][r]): groups of 64 consecutive
+// chunks in chunk order, then the group sums in group order (an order fixed by
+// nchunk alone); the eight waves of a workgroup share the groups of 64 columns.
+constexpr int kNormGroup = 64;
+constexpr int kNormMaxChunks = 2048;
+__global__ __launch_bounds__(512) void colnorm_final_kernel(const double* __restrict__ partial, int nchunk, int R,
+                                                            double* __restrict__ out) {
+    __shared__ double gs[kNormMaxChunks / kNormGroup][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r = blockIdx.x * 64 + lane;
+    const int ng = (nchunk + kNormGroup - 1) / kNormGroup;
+    for (int g = wave; g < ng; g += 8) {
+        double sg = 0;
+        if (r < R) {
+            const int c1 = min(nchunk, (g + 1) * kNormGroup);
+            for (int c = g * kNormGroup; c < c1; ++c) sg += partial[(int64_t)c * R + r];
+        }
+        gs[g][lane] = sg;
+    }
+    __syncthreads();
+    if (wave == 0 && r < R) {
+        double sum = gs[0][lane];
+        for (int g = 1; g < ng; ++g) sum += gs[g][lane];
+        out[r] = sqrt(sum);
+    }
 }
 
 // Y[i + P*r] = I[(i*M + pc)][r]   (column-major P x R output)
@@ -193,11 +215,12 @@ void sub_d(const double2* a, const double2* b, double2* out, int64_t n, hipStrea
 
 // partial must hold nchunk*R doubles with nchunk = ceil(N / rows_per_chunk), rows_per_chunk = 256
 void column_norms(const double2* X, int64_t N, int R, double* partial, double* out, hipStream_t s) {
-    const int64_t rpc = 256;
+    // at least 256 rows per chunk, at most kNormMaxChunks chunks (partial holds ceil(N/256) x R)
+    const int64_t rpc = std::max<int64_t>(256, (N + kNormMaxChunks - 1) / kNormMaxChunks);
     const int nchunk = (int)((N + rpc - 1) / rpc);
     hipLaunchKernelGGL(colnorm_partial_kernel, dim3((R + 63) / 64, nchunk), dim3(64), 0, s, X, N, R, rpc, partial);
     MBT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(colnorm_final_kernel, dim3((R + 63) / 64), dim3(64), 0, s, partial, nchunk, R, out);
+    hipLaunchKernelGGL(colnorm_final_kernel, dim3((R + 63) / 64), dim3(512), 0, s, partial, nchunk, R, out);
     MBT_LAUNCH_CHECK();
 }
 
