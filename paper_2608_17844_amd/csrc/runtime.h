@@ -48,13 +48,15 @@ struct OpData {
     Geom g;
     double s = 0, k = 0;
     DBuf T, Chat, tw, PkInv, PaInv;            // FP64
+    DBuf ChatK;                                // P_K^{-1} C^_b per bin: the element-block preconditioned operator
     DBuf Chat32, tw32, PkInv32, PaInv32;       // FP32 copies for reduced-precision inner solves
+    DBuf ChatK32;
     DBuf Chat16[2];                            // 16-bit spectra (bfloat16, binary16) for the 16-bit products,
     double scale16[2] = {1.0, 1.0};            // stored as scale16 * C^ (a power of two)
     bool has_pa = false, has32 = false;
     size_t bytes() const {
-        return T.bytes + Chat.bytes + tw.bytes + PkInv.bytes + PaInv.bytes + Chat32.bytes + tw32.bytes +
-               PkInv32.bytes + PaInv32.bytes + Chat16[0].bytes + Chat16[1].bytes;
+        return T.bytes + Chat.bytes + ChatK.bytes + tw.bytes + PkInv.bytes + PaInv.bytes + Chat32.bytes +
+               ChatK32.bytes + tw32.bytes + PkInv32.bytes + PaInv32.bytes + Chat16[0].bytes + Chat16[1].bytes;
     }
 };
 

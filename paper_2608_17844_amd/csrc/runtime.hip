@@ -178,6 +178,8 @@ static void build_32(OpData& op, Worker& wk) {
     const int64_t MM = (int64_t)g.M * g.M;
     op.Chat32.alloc(sizeof(float2) * g.bins() * MM);
     convert<double2, float2>(op.Chat.as<double2>(), op.Chat32.as<float2>(), g.bins() * MM, wk.stream);
+    op.ChatK32.alloc(sizeof(float2) * g.bins() * MM);
+    convert<double2, float2>(op.ChatK.as<double2>(), op.ChatK32.as<float2>(), g.bins() * MM, wk.stream);
     op.tw32.alloc(sizeof(float2) * (g.Px + g.Py));
     convert<double2, float2>(op.tw.as<double2>(), op.tw32.as<float2>(), g.Px + g.Py, wk.stream);
     op.PkInv32.alloc(sizeof(float2) * MM);
@@ -262,6 +264,13 @@ static std::shared_ptr<OpData> build_op(const mbt_array* arr, double s, Worker& 
         gj_inverse(A, op->PkInv.as<double2>(), g.M, A + MM, piv, piv + g.M, wk.stream);
         MBT_HIP(hipStreamSynchronize(wk.stream));
     }
+    // P_K^{-1} acts on the basis index of every element alike, so it commutes with
+    // the lattice transforms and the crop: P_K^{-1} Z x = crop F^{-1}((P_K^{-1} C^_b) X^_b).
+    // Folding it into the spectra removes the preconditioner pass from each step.
+    op->ChatK.alloc(sizeof(double2) * g.bins() * MM);
+    cgemm_batched<double>(op->PkInv.as<double2>(), 0, op->Chat.as<double2>(), op->ChatK.as<double2>(), g.M, g.M,
+                          g.bins(), 0, wk.stream);
+    MBT_HIP(hipStreamSynchronize(wk.stream));
     return op;
 }
 
@@ -323,6 +332,7 @@ std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const mbt_array* arr, double s, boo
 template <typename T> struct OpV {
     const Geom* g;
     const cplx<T>* Chat;
+    const cplx<T>* ChatA = nullptr;      // spectra of the preconditioned operator, when P is folded in
     const cplx<T>* pinv;
     int64_t pstride;
     const cplx<T>* twx;
@@ -347,6 +357,7 @@ OpV<double> make_view<double>(const OpData& op, int pc, void* Xh, void* Yh, void
     OpV<double> v;
     v.g = &op.g;
     v.Chat = op.Chat.as<double2>();
+    if (pc == MBT_PC_ELEMENT_BLOCK) v.ChatA = op.ChatK.as<double2>();
     v.pinv = pc == MBT_PC_NORMAL_EQ ? op.PaInv.as<double2>() : op.PkInv.as<double2>();
     v.pstride = pc == MBT_PC_NORMAL_EQ ? (int64_t)op.g.M * op.g.M : 0;
     v.twx = op.tw.as<double2>();
@@ -371,6 +382,7 @@ OpV<float> make_view<float>(const OpData& op, int pc, void* Xh, void* Yh, void* 
     }
     v.g = &op.g;
     v.Chat = op.Chat32.as<float2>();
+    if (pc == MBT_PC_ELEMENT_BLOCK && fmt == kFmtNone) v.ChatA = op.ChatK32.as<float2>();
     v.pinv = pc == MBT_PC_NORMAL_EQ ? op.PaInv32.as<float2>() : op.PkInv32.as<float2>();
     v.pstride = pc == MBT_PC_NORMAL_EQ ? (int64_t)op.g.M * op.g.M : 0;
     v.twx = op.tw32.as<float2>();
@@ -384,8 +396,10 @@ OpV<float> make_view<float>(const OpData& op, int pc, void* Xh, void* Yh, void* 
     return v;
 }
 
-// y = Z x (opz 0) or Z^H x (opz 1) by FFT over the lattice, per-bin products, inverse FFT and crop
-template <typename T> static void zmul(const OpV<T>& o, int opz, const cplx<T>* x, cplx<T>* y) {
+// y = Z x (opz 0) or Z^H x (opz 1) by FFT over the lattice, per-bin products, inverse FFT and crop;
+// chat replaces the block spectra (the preconditioned operator's, FP64/FP32 products only)
+template <typename T>
+static void zmul(const OpV<T>& o, int opz, const cplx<T>* x, cplx<T>* y, const cplx<T>* chat = nullptr) {
     const Geom& g = *o.g;
     const int64_t B = (int64_t)g.M * o.R;
     const double sc = sizeof(cplx<T>);
@@ -425,7 +439,7 @@ template <typename T> static void zmul(const OpV<T>& o, int opz, const cplx<T>* 
     }
     {
         ProfScope ps(kKBinProduct, 2 * spec + (double)g.bins() * g.M * g.M * sc, 8.0 * g.bins() * g.M * g.M * o.R, o.s);
-        cgemm_batched<T>(o.Chat, (int64_t)g.M * g.M, o.Xh, o.Yh, g.M, o.R, g.bins(), opz, o.s);
+        cgemm_batched<T>(chat ? chat : o.Chat, (int64_t)g.M * g.M, o.Xh, o.Yh, g.M, o.R, g.bins(), opz, o.s);
     }
     {
         ProfScope ps(kKFftInv, spat + spec, 0.0, o.s);
@@ -443,6 +457,10 @@ template <typename T> static void pinv(const OpV<T>& o, const cplx<T>* x, cplx<T
 
 // preconditioned operator: P_K^{-1} Z  or  P^{-1} Z^H Z
 template <typename T> static void apply_A(const OpV<T>& o, const cplx<T>* x, cplx<T>* y) {
+    if (o.ChatA) {   // P_K^{-1} Z with the preconditioner folded into the spectra
+        zmul<T>(o, 0, x, y, o.ChatA);
+        return;
+    }
     zmul<T>(o, 0, x, o.tmp);
     if (o.pc == MBT_PC_NORMAL_EQ) zmul<T>(o, 1, o.tmp, o.tmp);
     pinv<T>(o, o.tmp, y);
@@ -889,8 +907,8 @@ size_t mbt_footprint(const mbt_array* a, int32_t nrhs, const mbt_solve_opts* o) 
     try {
         const Geom& g = a->g;
         const size_t MM = (size_t)g.M * g.M;
-        size_t opb = (size_t)g.noff() * MM * 16 + (size_t)g.bins() * MM * 16 + (size_t)g.P * MM * 16 * 2;
-        if (o->prec != MBT_FP64) opb += (size_t)g.bins() * MM * 8 + (size_t)g.P * MM * 8;
+        size_t opb = (size_t)g.noff() * MM * 16 + 2 * (size_t)g.bins() * MM * 16 + (size_t)g.P * MM * 16 * 2;
+        if (o->prec != MBT_FP64) opb += 2 * (size_t)g.bins() * MM * 8 + (size_t)g.P * MM * 8;
         if (fmt16_of(o->prec) != kFmtNone) opb += (size_t)g.bins() * MM * 4;
         return solve_bytes(g, padded(nrhs, *o), *o) + opb;
     } catch (...) {
