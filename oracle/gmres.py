@@ -11,6 +11,10 @@ Preconditioners (Sec. III-A):
   as the diagonal M x M blocks of the explicit product Z^H Z, each Cholesky
   factorised (P = L L^H); GMRES then runs on P^{-1} Z^H Z I = P^{-1} Z^H V.
 
+PCG (Sec. II-C, the paper's own solver): conjugate gradients on the normal
+equations Z^H Z I = Z^H V with the preconditioner P_A, stopped on the relative
+residual of the split system of eq. (precond).
+
 GMRES(m) (the solver of the "new M1" configuration; the paper relies on
 MATLAB's implementation and states none of its details, so this reading fixes
 them): x0 = 0, Arnoldi with classical Gram-Schmidt applied twice (CGS2),
@@ -288,6 +292,71 @@ def gmres_all(system: PreconditionedSystem, V: np.ndarray, restart: int = 50, to
     results = []
     for j in range(V.shape[1]):
         r = solver(system.apply, B[:, j], restart, tol, max_cycles)
+        I[:, j] = r.x
+        results.append(r)
+    return I, results
+
+
+# --------------------------------------------------------------------------- PCG
+
+@dataclass
+class PCGResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    relres: List[float] = field(default_factory=list)   # split-system residual after each iteration
+
+
+def pcg(apply_N: Callable[[np.ndarray], np.ndarray], apply_Pinv: Callable[[np.ndarray], np.ndarray],
+        b: np.ndarray, tol: float = 1e-10, maxit: int = 20000) -> PCGResult:
+    """Preconditioned conjugate gradients (Sec. II-C) for N x = b with N Hermitian
+    positive definite (Z^H Z) and preconditioner P (P^{-1} applied by apply_Pinv).
+
+    With P = L L^H these are the iterates of plain CG on the split system of
+    eq. (precond), L^{-1} N L^{-H} w = L^{-1} b with x = L^{-H} w; the stop test
+    is that system's relative residual, ||L^{-1} r|| / ||L^{-1} b|| =
+    sqrt(r^H P^{-1} r / b^H P^{-1} b) <= tol, with x0 = 0.
+    """
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = apply_Pinv(r)
+    p = z.copy()
+    rho = float(np.real(np.vdot(r, z)))
+    rho0 = rho
+    res = PCGResult(x=x, iters=0, converged=(rho0 == 0.0))
+    if res.converged:
+        return res
+    for k in range(1, maxit + 1):
+        q = apply_N(p)
+        mu = float(np.real(np.vdot(p, q)))
+        alpha = rho / mu
+        x += alpha * p
+        r -= alpha * q
+        z = apply_Pinv(r)
+        rho_new = float(np.real(np.vdot(r, z)))
+        res.iters = k
+        rel = np.sqrt(max(rho_new, 0.0) / rho0)
+        res.relres.append(rel)
+        if rel <= tol:
+            res.converged = True
+            break
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    res.x = x
+    return res
+
+
+def pcg_all(Z: np.ndarray, lat, dip, V: np.ndarray, tol: float = 1e-10, maxit: int = 20000):
+    """PCG on the normal equations Z^H Z I = Z^H V with P_A (diagonal blocks of
+    Z^H Z, eq. (precondA)) for every column of V; returns (I, per-RHS results)."""
+    M = dip.nbases
+    f = pa_factors(pa_blocks(Z, lat, dip))
+    ZH = Z.conj().T
+    B = ZH @ V
+    I = np.zeros_like(V)
+    results = []
+    for j in range(V.shape[1]):
+        r = pcg(lambda v: ZH @ (Z @ v), lambda v: pa_apply(f, v, M), B[:, j], tol, maxit)
         I[:, j] = r.x
         results.append(r)
     return I, results

@@ -400,3 +400,65 @@ def test_synthetic_blocks_are_reciprocal():
     T = W.synthetic_blocks(3, 4, 5, seed=1)
     Z = ob.dense_from_blocks(T, 3, 4)
     assert np.array_equal(Z, Z.T)
+
+
+def _plain_cg(A, b, iters):
+    """Textbook conjugate gradients (no preconditioner) for Hermitian positive definite A."""
+    w = np.zeros_like(b)
+    r = b.copy()
+    d = r.copy()
+    out = []
+    for _ in range(iters):
+        Ad = A @ d
+        a = np.vdot(r, r).real / np.vdot(d, Ad).real
+        w = w + a * d
+        r_new = r - a * Ad
+        d = r_new + (np.vdot(r_new, r_new).real / np.vdot(r, r).real) * d
+        r = r_new
+        out.append(w.copy())
+    return out
+
+
+def test_pcg_is_cg_on_the_split_system():
+    """Sec. II-C / eq. (precond): PCG with P = L L^H makes the same progress as
+    plain CG on L^{-1} N L^{-H} w = L^{-1} b (x = L^{-H} w).  The split system's
+    relative residual after each step must agree, and so must the iteration
+    count and the solution."""
+    from oracle import gmres as G
+    rng = np.random.default_rng(11)
+    n, mb = 40, 5
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    N = A.conj().T @ A + 0.05 * np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    P = np.zeros_like(N)
+    for e in range(n // mb):
+        s = slice(e * mb, (e + 1) * mb)
+        P[s, s] = N[s, s]
+    L = np.linalg.cholesky(P)
+    Li = np.linalg.inv(L)
+    At = Li @ N @ Li.conj().T
+    bt = Li @ b
+    res = G.pcg(lambda v: N @ v, lambda v: np.linalg.solve(P, v), b, tol=1e-11, maxit=400)
+    assert res.converged
+    ws = _plain_cg(At, bt, res.iters)
+    rel = [np.linalg.norm(bt - At @ w) / np.linalg.norm(bt) for w in ws]
+    k = min(12, res.iters)
+    assert np.allclose(rel[:k], res.relres[:k], rtol=1e-6, atol=0)
+    x_cg = Li.conj().T @ ws[-1]
+    assert np.linalg.norm(res.x - x_cg) <= 1e-8 * np.linalg.norm(x_cg)
+    assert np.linalg.norm(res.x - np.linalg.solve(N, b)) <= 1e-8 * np.linalg.norm(res.x)
+
+
+def test_pcg_normal_equations_reach_the_lu_solution():
+    """PCG on Z^H Z I = Z^H V with P_A (brute-force diagonal blocks of Z^H Z)
+    converges to the direct solution of Z I = V."""
+    from oracle import gmres as G
+    lat, dip = W.Lattice(3, 3, 0.5, 0.5), W.Dipole(0.5, 0.005, 7)
+    Z = mom.fill_dense(lat, dip, 1.0)
+    V = mom.excitation(lat, dip)
+    I, res = G.pcg_all(Z, lat, dip, V, tol=1e-12)
+    ref = np.linalg.solve(Z, V)
+    assert all(r.converged for r in res)
+    assert np.linalg.norm(I - ref) <= 1e-8 * np.linalg.norm(ref)
+    # the split-system residual falls monotonically only on average; it must reach tol within N steps
+    assert max(r.iters for r in res) <= Z.shape[0]
