@@ -104,6 +104,14 @@ typedef struct {
  * top 24 bits (unit roundoff 2^-16, three quarters of the bytes); an odd
  * number of ports is then solved with one port repeated. */
 #define MBT_FLAG_FP32_BASIS 4
+/* mbt_solve_opts.flags: solve by preconditioned conjugate gradients (Sec. II-C)
+ * instead of GMRES: CG on the normal equations Z^H Z I = Z^H V with the
+ * preconditioner P_A (pc must be MBT_PC_NORMAL_EQ), stopping when the relative
+ * residual of the split system P^{-1/2} Z^H Z P^{-H/2} W = P^{-1/2} Z^H V
+ * (eq. (precond)) is <= tol (inner_tol in the reduced-precision inner solves);
+ * at most restart * max_cycles iterations.  Keeps four work vectors instead of
+ * a Krylov basis. */
+#define MBT_FLAG_PCG 8
 
 typedef struct {
     int32_t nrhs;             /* RHS solved */

@@ -67,4 +67,16 @@ template <typename TB>
 GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, const TB* b, double2* x, TB* Vbasis,
                           int64_t N, int R, const GmresParams& prm, DevArena& arena, hipStream_t s);
 
+// Batched preconditioned conjugate gradients for N x = b (N Hermitian positive
+// definite: the normal equations Z^H Z), P^{-1} applied by applyPinv; x0 = 0;
+// stop on sqrt(r^H P^{-1} r / b^H P^{-1} b) <= tol per RHS (the residual of the
+// split system P^{-1/2} N P^{-H/2} w = P^{-1/2} b).  work holds 4 N x R vectors
+// of type TB; at most maxit iterations.  cycles is 1, matvecs counts Z and Z^H.
+size_t pcg_state_bytes(int64_t N, int R);
+template <typename TB>
+GmresResult pcg_batched(const std::function<void(const TB*, TB*)>& applyN,
+                        const std::function<void(const TB*, TB*)>& applyPinv, const TB* b, double2* x, TB* work,
+                        int64_t N, int R, double tol, int maxit, int* host_count, DevArena& arena, hipStream_t s);
+
+
 }  // namespace mbt

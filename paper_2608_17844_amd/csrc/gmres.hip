@@ -1064,7 +1064,6 @@ inline unsigned ew_grid(int64_t n) {
 
 }  // namespace
 
-// Row chunks depend on N only, so a RHS's reduction order never depends on the batch.
 // Chunks of the row range for the reduction sweeps: a function of N alone, so a
 // right-hand side's sums do not depend on how many others share the batch.  Up
 // to 2048 chunks (at least 128 rows each) keep a few-RHS batch spread over the
@@ -1282,6 +1281,198 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     arena.off = arena_mark;
     return res;
 }
+
+// ------------------------------------------------------------------ batched PCG (Sec. II-C)
+// Conjugate gradients on N x = b (N = Z^H Z, Hermitian positive definite) with
+// the preconditioner P applied as P^{-1}; one independent recurrence per RHS
+// column, FP64 coefficients and dots, vectors of type TB.  With P = L L^H the
+// iterates are those of plain CG on the split system of eq. (precond), and the
+// stop test is that system's relative residual sqrt(r^H P^{-1} r / b^H P^{-1} b).
+namespace {
+
+// partial[chunk][r] = sum over the chunk's rows of conj(a) b
+template <typename TB>
+__global__ void pcg_dot_kernel(const TB* __restrict__ a, const TB* __restrict__ b, int64_t N, int R,
+                               int64_t rows_per_chunk, double2* __restrict__ partial) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t chunk = blockIdx.y;
+    if (r >= R) return;
+    const int64_t n0 = chunk * rows_per_chunk, n1 = min(N, n0 + rows_per_chunk);
+    double2 acc = make_double2(0, 0);
+    for (int64_t n = n0; n < n1; ++n) acc = cfmac(acc, ld2(a + n * R + r), ld2(b + n * R + r));
+    partial[chunk * R + r] = acc;
+}
+
+struct PcgState {
+    double tol;
+    double *rho, *rho0, *alpha, *beta;
+    int *active, *conv, *flag, *iters;
+};
+
+__global__ void pcg_init_kernel(PcgState st, const double2* __restrict__ rz, int R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const double rho = rz[r].x;
+    st.rho[r] = rho;
+    st.rho0[r] = rho;
+    st.iters[r] = 0;
+    st.flag[r] = !(rho == rho) || isinf(rho) || rho < 0.0;
+    st.conv[r] = !st.flag[r] && rho == 0.0;
+    st.active[r] = !st.flag[r] && !st.conv[r];
+    st.alpha[r] = 0.0;
+    st.beta[r] = 0.0;
+}
+
+// alpha = rho / p^H q for the RHS still iterating
+__global__ void pcg_alpha_kernel(PcgState st, const double2* __restrict__ pq, int R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double a = 0.0;
+    if (st.active[r]) {
+        a = st.rho[r] / pq[r].x;
+        if (!(a == a) || isinf(a)) {
+            st.flag[r] = 1;
+            st.active[r] = 0;
+            a = 0.0;
+        }
+    }
+    st.alpha[r] = a;
+}
+
+// x += alpha p (x in FP64), r -= alpha q
+template <typename TB>
+__global__ void pcg_xr_kernel(double2* __restrict__ x, TB* __restrict__ rv, const TB* __restrict__ p,
+                              const TB* __restrict__ q, const double* __restrict__ alpha, int64_t NR, int R) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NR; t += (int64_t)gridDim.x * blockDim.x) {
+        const double a = alpha[t % R];
+        const double2 pv = ld2(p + t), qv = ld2(q + t), xv = x[t], rr = ld2(rv + t);
+        x[t] = make_double2(fma(a, pv.x, xv.x), fma(a, pv.y, xv.y));
+        st2(rv + t, make_double2(fma(-a, qv.x, rr.x), fma(-a, qv.y, rr.y)));
+    }
+}
+
+// rho_new = r^H z: stop test on the split-system residual, then beta
+__global__ void pcg_beta_kernel(PcgState st, const double2* __restrict__ rz, int R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double b = 0.0;
+    if (st.active[r]) {
+        const double rn = rz[r].x;
+        st.iters[r] += 1;
+        if (!(rn == rn) || isinf(rn)) {
+            st.flag[r] = 1;
+            st.active[r] = 0;
+        } else if (sqrt(fmax(rn, 0.0) / st.rho0[r]) <= st.tol) {
+            st.conv[r] = 1;
+            st.active[r] = 0;
+        } else {
+            b = rn / st.rho[r];
+            st.rho[r] = rn;
+        }
+    }
+    st.beta[r] = b;
+}
+
+// p = z + beta p
+template <typename TB>
+__global__ void pcg_p_kernel(TB* __restrict__ p, const TB* __restrict__ z, const double* __restrict__ beta, int64_t NR,
+                             int R) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NR; t += (int64_t)gridDim.x * blockDim.x) {
+        const double b = beta[t % R];
+        const double2 zv = ld2(z + t), pv = ld2(p + t);
+        st2(p + t, make_double2(fma(b, pv.x, zv.x), fma(b, pv.y, zv.y)));
+    }
+}
+
+template <typename TB>
+void pcg_dot(const TB* a, const TB* b, int64_t N, int R, double2* partial, double2* out, hipStream_t s) {
+    const int64_t rpc = gmres_rows_per_chunk(N);
+    const int nchunk = gmres_nchunk(N);
+    hipLaunchKernelGGL((pcg_dot_kernel<TB>), dim3((R + 63) / 64, nchunk), dim3(64), 0, s, a, b, N, R, rpc, partial);
+    MBT_LAUNCH_CHECK();
+    launch_reduce_partials(partial, nchunk, 1, R, out, s);
+}
+
+}  // namespace
+
+size_t pcg_state_bytes(int64_t N, int R) {
+    return sizeof(double2) * (size_t)gmres_nchunk(N) * R + 2 * sizeof(double2) * (size_t)R +
+           4 * sizeof(double) * (size_t)R + 4 * sizeof(int) * (size_t)R + 16 * 256;
+}
+
+template <typename TB>
+GmresResult pcg_batched(const std::function<void(const TB*, TB*)>& applyN,
+                        const std::function<void(const TB*, TB*)>& applyPinv, const TB* b, double2* x, TB* work,
+                        int64_t N, int R, double tol, int maxit, int* host_count, DevArena& arena, hipStream_t s) {
+    const size_t mark = arena.off;
+    const int64_t NR = N * R;
+    TB* rv = work;
+    TB* z = work + NR;
+    TB* p = work + 2 * NR;
+    TB* q = work + 3 * NR;
+    PcgState st;
+    st.tol = tol;
+    st.rho = arena.get<double>(R);
+    st.rho0 = arena.get<double>(R);
+    st.alpha = arena.get<double>(R);
+    st.beta = arena.get<double>(R);
+    st.active = arena.get<int>(R);
+    st.conv = arena.get<int>(R);
+    st.flag = arena.get<int>(R);
+    st.iters = arena.get<int>(R);
+    double2* partial = arena.get<double2>((size_t)gmres_nchunk(N) * R);
+    double2* dot = arena.get<double2>(R);
+    int* d_count = arena.get<int>(16);
+    const dim3 gR((R + 255) / 256), bR(256);
+    auto count_active = [&]() -> int {
+        hipLaunchKernelGGL(count_kernel, dim3(1), dim3(256), 0, s, st.active, R, d_count);
+        MBT_LAUNCH_CHECK();
+        MBT_HIP(hipMemcpyAsync(host_count, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+        MBT_HIP(hipStreamSynchronize(s));
+        return *host_count;
+    };
+    GmresResult res;
+    // x = 0, r = b, z = P^{-1} r, p = z, rho = r^H z
+    hipLaunchKernelGGL(zero_kernel, dim3(ew_grid(NR)), dim3(256), 0, s, x, NR);
+    hipLaunchKernelGGL((copy_kernel<TB>), dim3(ew_grid(NR)), dim3(256), 0, s, b, rv, NR);
+    MBT_LAUNCH_CHECK();
+    applyPinv(rv, z);
+    hipLaunchKernelGGL((copy_kernel<TB>), dim3(ew_grid(NR)), dim3(256), 0, s, z, p, NR);
+    MBT_LAUNCH_CHECK();
+    pcg_dot<TB>(rv, z, N, R, partial, dot, s);
+    hipLaunchKernelGGL(pcg_init_kernel, gR, bR, 0, s, st, dot, R);
+    MBT_LAUNCH_CHECK();
+    res.cycles = 1;
+    for (int it = 0; it < maxit && count_active() > 0; ++it) {
+        applyN(p, q);
+        pcg_dot<TB>(p, q, N, R, partial, dot, s);
+        hipLaunchKernelGGL(pcg_alpha_kernel, gR, bR, 0, s, st, dot, R);
+        hipLaunchKernelGGL((pcg_xr_kernel<TB>), dim3(ew_grid(NR)), dim3(256), 0, s, x, rv, p, q, st.alpha, NR, R);
+        MBT_LAUNCH_CHECK();
+        applyPinv(rv, z);
+        pcg_dot<TB>(rv, z, N, R, partial, dot, s);
+        hipLaunchKernelGGL(pcg_beta_kernel, gR, bR, 0, s, st, dot, R);
+        hipLaunchKernelGGL((pcg_p_kernel<TB>), dim3(ew_grid(NR)), dim3(256), 0, s, p, z, st.beta, NR, R);
+        MBT_LAUNCH_CHECK();
+        res.matvecs += 2;
+    }
+    res.iters.assign(R, 0);
+    res.conv.assign(R, 0);
+    res.flag.assign(R, 0);
+    MBT_HIP(hipMemcpyAsync(res.iters.data(), st.iters, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipMemcpyAsync(res.conv.data(), st.conv, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipMemcpyAsync(res.flag.data(), st.flag, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipStreamSynchronize(s));
+    arena.off = mark;
+    return res;
+}
+
+template GmresResult pcg_batched<double2>(const std::function<void(const double2*, double2*)>&,
+                                          const std::function<void(const double2*, double2*)>&, const double2*,
+                                          double2*, double2*, int64_t, int, double, int, int*, DevArena&, hipStream_t);
+template GmresResult pcg_batched<float2>(const std::function<void(const float2*, float2*)>&,
+                                         const std::function<void(const float2*, float2*)>&, const float2*, double2*,
+                                         float2*, int64_t, int, double, int, int*, DevArena&, hipStream_t);
 
 template GmresResult gmres_batched<double2>(const std::function<void(const double2*, double2*)>&, const double2*,
                                             double2*, double2*, int64_t, int, const GmresParams&, DevArena&, hipStream_t);

@@ -134,7 +134,10 @@ void validate_opts(const mbt_solve_opts& o) {
     MBT_REQUIRE(o.max_cycles >= 1, "max_cycles must be >= 1");
     MBT_REQUIRE(o.prec == MBT_FP64 || (o.refine_max >= 1 && o.refine_tol > 0), "refinement options invalid");
     MBT_REQUIRE(o.rhs_chunk >= 0, "rhs_chunk must be >= 0");
-    MBT_REQUIRE((o.flags & ~(MBT_FLAG_NO_CACHE | MBT_FLAG_CGS2 | MBT_FLAG_FP32_BASIS)) == 0, "unknown flags");
+    MBT_REQUIRE((o.flags & ~(MBT_FLAG_NO_CACHE | MBT_FLAG_CGS2 | MBT_FLAG_FP32_BASIS | MBT_FLAG_PCG)) == 0,
+                "unknown flags");
+    MBT_REQUIRE(!(o.flags & MBT_FLAG_PCG) || o.pc == MBT_PC_NORMAL_EQ,
+                "PCG solves the normal equations: pc must be MBT_PC_NORMAL_EQ");
 }
 
 static double inner_tol(const mbt_solve_opts& o) {
@@ -481,14 +484,14 @@ size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o) {
     const size_t NR = (size_t)g.N * R;
     const size_t tb = o.prec == MBT_FP64 ? 16 : 8;
     size_t b = 0;
-    b += (size_t)(o.restart + 1) * NR * tb;            // Krylov basis
+    b += (size_t)std::max(o.restart + 1, 5) * NR * tb; // Krylov basis (PCG: four work vectors and b)
     b += 2 * (size_t)g.bins() * g.M * R * 16;          // spectral buffers (FP64-sized, shared)
     b += NR * 16;                                      // operator temp
     b += NR * tb;                                      // preconditioned rhs
     b += 2 * NR * 16;                                  // V, X
     b += NR * 16;                                      // FP64 residual
     if (o.prec != MBT_FP64) b += NR * 16 + NR * 8;     // d, r32
-    b += gmres_state_bytes(g.N, R, o.restart);
+    b += std::max(gmres_state_bytes(g.N, R, o.restart), pcg_state_bytes(g.N, R));
     b += (size_t)R * 64 + ((size_t)g.N / 256 + 2) * R * 8 + (size_t)g.P * R * 16 + (1 << 20);
     return b;
 }
@@ -497,7 +500,7 @@ size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o) {
 // batch is solved with its last port repeated (the extra column is identical
 // and dropped).
 static bool pads_odd(const mbt_solve_opts& o) {
-    return o.prec != MBT_FP64 && !(o.flags & MBT_FLAG_FP32_BASIS) && !(o.flags & MBT_FLAG_CGS2);
+    return o.prec != MBT_FP64 && !(o.flags & (MBT_FLAG_FP32_BASIS | MBT_FLAG_CGS2 | MBT_FLAG_PCG));
 }
 int padded(int R, const mbt_solve_opts& o) { return R + ((pads_odd(o) && (R & 1)) ? 1 : 0); }
 
@@ -557,15 +560,34 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
     std::vector<double> vn;
     norms_host(V, g.N, R, arena, vn, s);
 
+    const bool use_pcg = (o.flags & MBT_FLAG_PCG) != 0;
+    const int pcg_maxit = o.restart * o.max_cycles;
     if (o.prec == MBT_FP64) {
-        double2* basis = arena.get<double2>((size_t)(m + 1) * NR);
+        double2* basis = arena.get<double2>((size_t)std::max(m + 1, 5) * NR);
         double2* b = arena.get<double2>(NR);
         OpV<double> ov = make_view<double>(op, o.pc, Xh, Yh, tmp, R, s);
-        apply_rhs<double>(ov, V, b);
-        out.matvecs += o.pc == MBT_PC_NORMAL_EQ ? 1 : 0;
-        prm.tol = o.tol;
-        std::function<void(const double2*, double2*)> f = [&](const double2* x, double2* y) { apply_A<double>(ov, x, y); };
-        GmresResult gr = gmres_batched<double2>(f, b, X, basis, g.N, R, prm, arena, s);
+        GmresResult gr;
+        if (use_pcg) {
+            // Z^H Z I = Z^H V with P_A (Sec. II-C)
+            zmul<double>(ov, 1, V, b);
+            out.matvecs += 1;
+            std::function<void(const double2*, double2*)> fn = [&](const double2* x, double2* y) {
+                zmul<double>(ov, 0, x, ov.tmp);
+                zmul<double>(ov, 1, ov.tmp, y);
+            };
+            std::function<void(const double2*, double2*)> fp = [&](const double2* x, double2* y) {
+                pinv<double>(ov, x, y);
+            };
+            gr = pcg_batched<double2>(fn, fp, b, X, basis, g.N, R, o.tol, pcg_maxit, wk.host_count, arena, s);
+        } else {
+            apply_rhs<double>(ov, V, b);
+            out.matvecs += o.pc == MBT_PC_NORMAL_EQ ? 1 : 0;
+            prm.tol = o.tol;
+            std::function<void(const double2*, double2*)> f = [&](const double2* x, double2* y) {
+                apply_A<double>(ov, x, y);
+            };
+            gr = gmres_batched<double2>(f, b, X, basis, g.N, R, prm, arena, s);
+        }
         out.iters = gr.iters;
         out.cycles = gr.cycles;
         out.matvecs += gr.matvecs;
@@ -577,7 +599,7 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
             out.nflag += out.flag[r];
         }
     } else {
-        float2* basis = arena.get<float2>((size_t)(m + 1) * NR);
+        float2* basis = arena.get<float2>((size_t)std::max(m + 1, 5) * NR);
         float2* b32 = arena.get<float2>(NR);
         float2* r32 = arena.get<float2>(NR);
         double2* r64 = arena.get<double2>(NR);
@@ -616,9 +638,23 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
             MBT_HIP(hipMemcpyAsync(unscale, hmask.data() + R, sizeof(double) * R, hipMemcpyHostToDevice, s));
             scale_columns_d(r64, mask, g.N, R, s);
             convert<double2, float2>(r64, r32, NR, s);
-            apply_rhs<float>(ov32, r32, b32);
-            out.matvecs += o.pc == MBT_PC_NORMAL_EQ ? 1 : 0;
-            GmresResult gr = gmres_batched<float2>(f, b32, d, basis, g.N, R, prm, arena, s);
+            GmresResult gr;
+            if (use_pcg) {
+                zmul<float>(ov32, 1, r32, b32);
+                out.matvecs += 1;
+                std::function<void(const float2*, float2*)> fn = [&](const float2* x, float2* y) {
+                    zmul<float>(ov32, 0, x, ov32.tmp);
+                    zmul<float>(ov32, 1, ov32.tmp, y);
+                };
+                std::function<void(const float2*, float2*)> fp = [&](const float2* x, float2* y) {
+                    pinv<float>(ov32, x, y);
+                };
+                gr = pcg_batched<float2>(fn, fp, b32, d, basis, g.N, R, prm.tol, pcg_maxit, wk.host_count, arena, s);
+            } else {
+                apply_rhs<float>(ov32, r32, b32);
+                out.matvecs += o.pc == MBT_PC_NORMAL_EQ ? 1 : 0;
+                gr = gmres_batched<float2>(f, b32, d, basis, g.N, R, prm, arena, s);
+            }
             scale_columns_d(d, unscale, g.N, R, s);
             add_to_f64<double2>(X, d, NR, s);
             out.outer = outer + 1;

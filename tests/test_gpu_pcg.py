@@ -1,0 +1,114 @@
+"""Batched PCG on the normal equations (Sec. II-C) on the GPU: per-RHS iteration
+counts against the oracle's PCG, the admittance and port quantities against the
+dense LU oracle, FP32 inner solves with FP64 refinement, agreement with GMRES,
+and option checking."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gmres as og
+from oracle import mom
+from paper_2608_17844_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2608_17844_amd import mbt
+    h = mbt.mbt_ctx_create(0)
+    yield h
+    mbt.mbt_ctx_destroy(h)
+
+
+def _opts(mbt, prec, **kw):
+    return mbt.mbt_default_opts(prec=prec, pc=mbt.MBT_PC_NORMAL_EQ, flags=mbt.MBT_FLAG_PCG, **kw)
+
+
+def test_pcg_iteration_parity_and_admittance_cfg_5x5(ctx, cfg1, cfg1_oracle):
+    """Every RHS stops within two iterations of the oracle's PCG.  Conjugate
+    gradients on the normal equations (condition number squared) is sensitive
+    to rounding order: the oracle itself moves by one iteration on many RHS when
+    Z^H Z is applied as one matrix instead of Z^H (Z v)."""
+    from paper_2608_17844_amd import mbt
+    lat, dip = cfg1.lattice, cfg1.dipole
+    a = mbt.mbt_array_create_dipole(ctx, dip, lat)
+    try:
+        Y, iters, st = mbt.mbt_port_admittance(ctx, a, 1.0, None, _opts(mbt, mbt.MBT_FP64, tol=1e-10))
+    finally:
+        mbt.mbt_array_destroy(a)
+    _, res = og.pcg_all(cfg1_oracle.Z, lat, dip, mom.excitation(lat, dip), tol=1e-10)
+    ref_it = np.array([r.iters for r in res])
+    _say("pcg iterations gpu %s" % iters.tolist())
+    _say("pcg iterations oracle %s" % ref_it.tolist())
+    bad = [(j, int(iters[j]), r.iters) for j, r in enumerate(res) if abs(int(iters[j]) - r.iters) > 2]
+    assert not bad, bad
+    # where the GPU stopped, the oracle's split residual was already within two decades of tol
+    for j, r in enumerate(res):
+        k = min(int(iters[j]), len(r.relres))
+        assert r.relres[k - 1] <= 1e-8, (j, k, r.relres[k - 1])
+    err = np.linalg.norm(Y - cfg1_oracle.Yp) / np.linalg.norm(cfg1_oracle.Yp)
+    _say("pcg fp64 |dY|/|Y| %.2e" % err)
+    assert err <= 1e-8
+    assert st["nconverged"] == 25 and st["cycles"] == 1
+
+
+def test_pcg_port_quantities_fp64_and_refined_fp32(ctx, cfg1, cfg1_oracle):
+    from paper_2608_17844_amd import mbt
+    a = mbt.mbt_array_create_dipole(ctx, cfg1.dipole, cfg1.lattice)
+    try:
+        out64 = mbt.mbt_solve(ctx, a, 1.0, _opts(mbt, mbt.MBT_FP64, tol=1e-12), cfg1.theta, cfg1.phi, cfg1.z0)
+        out32 = mbt.mbt_solve(ctx, a, 1.0, _opts(mbt, mbt.MBT_FP32, refine_tol=1e-11, refine_max=6),
+                              cfg1.theta, cfg1.phi, cfg1.z0)
+    finally:
+        mbt.mbt_array_destroy(a)
+    ref = cfg1_oracle
+    for name, out, bound in (("fp64", out64, 1e-9), ("fp32", out32, 1e-9)):
+        ez = np.linalg.norm(out["Zp"] - ref.Zp) / np.linalg.norm(ref.Zp)
+        eg = np.max(np.abs(out["Gamma"] - ref.Gamma))
+        _say("pcg %s: |dZp|/|Zp| %.2e, |dGamma| %.2e, outer %d" % (name, ez, eg, out["stats"]["outer_steps"]))
+        assert ez <= bound and eg <= 10 * bound
+
+
+def test_pcg_agrees_with_gmres_16x16(ctx):
+    """PCG and GMRES on the same 16x16 array reach the LU solution of the oracle."""
+    from paper_2608_17844_amd import mbt
+    lat, dip = W.Lattice(16, 16, 0.5, 0.5), W.Dipole(0.5, 0.005, 15)
+    ref = mom.solve_array(lat, dip, 1.0)
+    ports = list(range(0, 256, 7))
+    a = mbt.mbt_array_create_dipole(ctx, dip, lat)
+    try:
+        Yp, itp, stp = mbt.mbt_port_admittance(ctx, a, 1.0, ports, _opts(mbt, mbt.MBT_FP64, tol=1e-11))
+        og_opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK, tol=1e-11)
+        Yg, itg, stg = mbt.mbt_port_admittance(ctx, a, 1.0, ports, og_opts)
+    finally:
+        mbt.mbt_array_destroy(a)
+    Yr = ref.Yp[:, ports]
+    ep = np.linalg.norm(Yp - Yr) / np.linalg.norm(Yr)
+    eg = np.linalg.norm(Yg - Yr) / np.linalg.norm(Yr)
+    _say("16x16: pcg iters %d..%d err %.2e; gmres(P_K) iters %d..%d err %.2e" % (
+        itp.min(), itp.max(), ep, itg.min(), itg.max(), eg))
+    assert ep <= 1e-8 and eg <= 1e-8
+    assert stp["nconverged"] == len(ports)
+
+
+def test_pcg_option_checks(ctx, cfg1):
+    from paper_2608_17844_amd import mbt
+    a = mbt.mbt_array_create_dipole(ctx, cfg1.dipole, cfg1.lattice)
+    try:
+        bad = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK, flags=mbt.MBT_FLAG_PCG)
+        with pytest.raises(mbt.MbtError) as e:
+            mbt.mbt_port_admittance(ctx, a, 1.0, [0, 1], bad)
+        assert e.value.status == mbt.MBT_EINVAL
+        # an iteration cap below what the system needs reports non-convergence with the last iterate
+        few = _opts(mbt, mbt.MBT_FP64, tol=1e-12, restart=2, max_cycles=1)
+        Y, it, st = mbt.mbt_port_admittance(ctx, a, 1.0, [0, 12], few, allow_noconv=True)
+        assert st["nconverged"] == 0 and it.max() == 2 and np.all(np.isfinite(Y))
+    finally:
+        mbt.mbt_array_destroy(a)
