@@ -164,13 +164,20 @@ def headline(args):
     w = W.gpu_size_32x32()
     ref = np.load(os.path.join(ROOT, "tests", "golden", "dipole_32x32_m31_reference.npz"))
     pc = mbt.MBT_PC_ELEMENT_BLOCK if args.pc == "element_block" else mbt.MBT_PC_NORMAL_EQ
+    sflags = 0
+    if args.solver == "pcg":
+        # the paper's PCG solves the normal equations with P_A
+        pc, sflags = mbt.MBT_PC_NORMAL_EQ, mbt.MBT_FLAG_PCG
+        args.pc = "normal_eq"
+        if args.kernel == "arnoldi_update_dots":
+            args.kernel = "fft_inv_crop"
     ctx = mbt.mbt_ctx_create(0)
     arr = mbt.mbt_array_create_dipole(ctx, w.dipole, w.lattice)
     P = w.lattice.nx * w.lattice.ny
     result = {}
     try:
         o32 = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=pc, restart=args.restart, refine_tol=args.refine_tol,
-                                   inner_tol=args.inner_tol, flags=mbt.MBT_FLAG_NO_CACHE)
+                                   inner_tol=args.inner_tol, flags=mbt.MBT_FLAG_NO_CACHE | sflags)
         log("fp32-mfma path: warmup %d, steps %d" % (args.warmup, args.steps))
         total, times, out, prof = run_steps(mbt, ctx, arr, w, o32, args.steps, args.warmup, args.kernel)
         err32 = zp_errors(out, ref)
@@ -180,7 +187,7 @@ def headline(args):
         fp64 = None
         if not args.no_fp64:
             o64 = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=pc, restart=args.fp64_restart, tol=args.fp64_tol,
-                                       flags=mbt.MBT_FLAG_NO_CACHE)
+                                       flags=mbt.MBT_FLAG_NO_CACHE | sflags)
             log("fp64 path (tol %g): warmup %d, steps %d" % (args.fp64_tol, args.warmup, args.steps))
             t64, times64, out64, _ = run_steps(mbt, ctx, arr, w, o64, args.steps, args.warmup)
             err64 = zp_errors(out64, ref)
@@ -192,8 +199,8 @@ def headline(args):
         kernels = {}
         if not args.no_kernel_table:
             log("per-kernel rooflines (one untimed step per kernel class)")
-            kernels = kernel_rooflines(mbt, ctx, arr, w, o32, ["arnoldi_dots", "fft_fwd_pad", "fft_inv_crop",
-                                                                 "bin_product", "precond_apply"])
+            classes = ["fft_fwd_pad", "fft_inv_crop", "bin_product", "precond_apply"]
+            kernels = kernel_rooflines(mbt, ctx, arr, w, o32, (["arnoldi_dots"] if args.solver == "gmres" else []) + classes)
         achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof and prof["ms"] > 0 else None
         traffic = measured_traffic(args.kernel, args.restart)
         roofline = {"kernel": args.kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -209,9 +216,11 @@ def headline(args):
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": w.name, "nx": w.lattice.nx, "ny": w.lattice.ny, "nbases": w.dipole.nbases,
                        "unknowns": P * w.dipole.nbases, "ports": P, "nscan": int(len(w.theta)),
-                       "preconditioner": args.pc, "restart": args.restart, "fp64_restart": args.fp64_restart,
-                       "precision": "FP32 lattice FFT + FP32 MFMA block products, FP32-stored Krylov basis with "
-                                    "FP64 dot products/Givens, FP64 refinement residual and extraction",
+                       "solver": args.solver, "preconditioner": args.pc, "restart": args.restart,
+                       "fp64_restart": args.fp64_restart,
+                       "precision": "FP32 lattice FFT + FP32 MFMA block products, Krylov basis packed to 24 bits "
+                                    "per component with FP32 work vectors and FP64 dot products/Givens, FP64 "
+                                    "refinement residual and extraction",
                        "refine_tol": args.refine_tol, "inner_tol": args.inner_tol,
                        "accuracy_target": "Z_p entries and center ARC within 1e-6 relative of the FP64 oracle"},
             "accuracy": err32, "iters_max": st32["iters_max"], "outer_steps": st32["outer_steps"],
@@ -446,6 +455,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--pc", choices=["element_block", "normal_eq"], default="element_block")
+    ap.add_argument("--solver", choices=["gmres", "pcg"], default="gmres",
+                    help="pcg: the paper's PCG on the normal equations with P_A (both paths)")
     ap.add_argument("--kernel", choices=sorted(KERNEL_CODES), default="arnoldi_update_dots")
     ap.add_argument("--restart", type=int, default=32, help="restart length of the mixed path's inner GMRES")
     ap.add_argument("--fp64-restart", type=int, default=50, help="restart length of the FP64 path (the workload's)")
