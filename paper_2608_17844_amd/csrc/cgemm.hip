@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restric
                                                         int R) {
     using C = cplx<T>;
     using V = typename Acc<T>::type;
-    constexpr int KC = 32;         // complex K per LDS stage
+    constexpr int KC = 16;         // complex K per LDS stage (13 KB at M = 96: eight workgroups per CU)
     constexpr int NRT = MP / 8;    // 16-row tiles of the 2MP-row real matrix
     constexpr int RTW = NRT / 4;   // row tiles per wave
     // CT: column tiles per workgroup (1, 2 or 4)
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restric
             As[p * LDA + j] = c;
         }
         __syncthreads();
-#pragma unroll 2
+#pragma unroll
         for (int s4 = 0; s4 < KC / 4; ++s4) {
             const int q = kc + 4 * s4 + g;
             C bv[CT];
