@@ -112,3 +112,24 @@ def test_pcg_option_checks(ctx, cfg1):
         assert st["nconverged"] == 0 and it.max() == 2 and np.all(np.isfinite(Y))
     finally:
         mbt.mbt_array_destroy(a)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_pcg_with_16bit_products_refines(ctx, cfg1, cfg1_oracle, prec):
+    """PCG inner solves on 16-bit per-bin products (Z and Z^H both) inside the
+    FP64 refinement: FP16 reaches the FP64 answer, BF16 contracts."""
+    from paper_2608_17844_amd import mbt
+    code = mbt.MBT_FP16 if prec == "fp16" else mbt.MBT_BF16
+    a = mbt.mbt_array_create_dipole(ctx, cfg1.dipole, cfg1.lattice)
+    try:
+        errs = []
+        for rmax in (1, 6):
+            out = mbt.mbt_solve(ctx, a, 1.0, _opts(mbt, code, refine_tol=1e-11, refine_max=rmax), cfg1.theta,
+                                cfg1.phi, cfg1.z0, allow_noconv=True)
+            errs.append(np.linalg.norm(out["Zp"] - cfg1_oracle.Zp) / np.linalg.norm(cfg1_oracle.Zp))
+    finally:
+        mbt.mbt_array_destroy(a)
+    _say("pcg %s: |dZp|/|Zp| after 1 and 6 refinement steps %.2e %.2e" % (prec, errs[0], errs[1]))
+    assert errs[1] < errs[0] / 10
+    if prec == "fp16":
+        assert errs[1] <= 1e-8
