@@ -157,9 +157,10 @@ void launch_mp(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, 
 // Blocks too large for register-resident fragments: one workgroup per batch
 // entry and group of up to four 16-column tiles; A is staged through LDS in
 // chunks of KC complex columns, the four waves split the 16-row tiles of the
-// real 2M x 2M product, and the X fragments are read straight from memory.  At
-// M = 96 and 32 columns a bin moves 123 KB (FP32) for 2.4 MFLOP, at the FP32
-// MFMA ridge.
+// real 2M x 2M product, and the X fragments are read straight from memory into
+// registers; the next chunk's A elements and X fragments are loaded while the
+// current chunk computes.  At M = 96 and 32 columns a bin moves 123 KB (FP32)
+// for 2.4 MFLOP, at the FP32 MFMA ridge.
 template <typename T, int MP, bool HERM, int CT>
 __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restrict__ A, int64_t strideA,
                                                         const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Y, int M,
@@ -206,27 +207,53 @@ __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restric
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[i][c] = V{0, 0, 0, 0};
 
-    for (int kc = 0; kc < M; kc += KC) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < MP * KC; e += 256) {
+    // the next chunk's A elements and X fragments are loaded while this chunk computes
+    constexpr int AE = (MP * KC + 255) / 256;
+    C areg[AE];
+    C xcur[KC / 4][CT], xnxt[KC / 4][CT];
+    auto load_a = [&](int kc) {
+#pragma unroll
+        for (int t = 0; t < AE; ++t) {
+            const int e = threadIdx.x + 256 * t;
             const int p = e / KC, j = e - p * KC, q = kc + j;
             C c = mk<T>(0, 0);
-            if (p < M && q < M) {
+            if (e < MP * KC && p < M && q < M) {
                 c = HERM ? Ab[(int64_t)q * M + p] : Ab[(int64_t)p * M + q];
                 if (HERM) c.y = -c.y;
             }
-            As[p * LDA + j] = c;
+            areg[t] = c;
+        }
+    };
+    auto load_x = [&](int kc, C (&xb)[KC / 4][CT]) {
+#pragma unroll
+        for (int s4 = 0; s4 < KC / 4; ++s4) {
+            const int q = kc + 4 * s4 + g;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int col = (ct0 + c) * 16 + li;
+                xb[s4][c] = (c < nct && q < M && col < R) ? Xb[(int64_t)q * R + col] : mk<T>(0, 0);
+            }
+        }
+    };
+    load_a(0);
+    load_x(0, xcur);
+    for (int kc = 0; kc < M; kc += KC) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < AE; ++t) {
+            const int e = threadIdx.x + 256 * t;
+            if (e < MP * KC) As[(e / KC) * LDA + (e % KC)] = areg[t];
+        }
+        if (kc + KC < M) {
+            load_a(kc + KC);
+            load_x(kc + KC, xnxt);
         }
         __syncthreads();
 #pragma unroll
         for (int s4 = 0; s4 < KC / 4; ++s4) {
-            const int q = kc + 4 * s4 + g;
             C bv[CT];
 #pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const int col = (ct0 + c) * 16 + li;
-                bv[c] = (c < nct && q < M && col < R) ? Xb[(int64_t)q * R + col] : mk<T>(0, 0);
-            }
+            for (int c = 0; c < CT; ++c) bv[c] = xcur[s4][c];
 #pragma unroll
             for (int i = 0; i < RTW; ++i) {
                 const C a = As[pr[i] * LDA + 4 * s4 + g];
@@ -239,6 +266,10 @@ __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restric
                 }
             }
         }
+#pragma unroll
+        for (int s4 = 0; s4 < KC / 4; ++s4)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) xcur[s4][c] = xnxt[s4][c];
     }
 #pragma unroll
     for (int i = 0; i < RTW; ++i) {
