@@ -416,6 +416,45 @@ def blocks_shape(args):
     return out
 
 
+def shard(args):
+    """One GPU's share of the all-port workload under a split of the ports over
+    GPUs: the admittance columns of R ports of the 32x32 array (ports 0..R-1),
+    mixed and FP64 paths with the headline settings; no extraction (Z_p needs
+    every column, gathered across GPUs)."""
+    from paper_2608_17844_amd import mbt
+    from paper_2608_17844_amd import workloads as W
+    w = W.gpu_size_32x32()
+    ctx = mbt.mbt_ctx_create(0)
+    arr = mbt.mbt_array_create_dipole(ctx, w.dipole, w.lattice)
+    ports = list(range(args.shard))
+    out = {}
+    try:
+        for name, opts in (
+                ("mixed", mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=args.restart,
+                                               refine_tol=args.refine_tol, inner_tol=args.inner_tol)),
+                ("fp64", mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK,
+                                              restart=args.fp64_restart, tol=args.fp64_tol))):
+            mbt.mbt_port_admittance(ctx, arr, 1.0, ports, opts)   # builds the operator, warms up
+            ts = []
+            for _ in range(args.steps):
+                t0 = time.perf_counter()
+                Y, it, st = mbt.mbt_port_admittance(ctx, arr, 1.0, ports, opts)
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts))
+            out[name] = {"solves_per_s": len(ports) / t, "seconds": t, "iters_max": int(it.max()),
+                         "outer_steps": st["outer_steps"]}
+            log("shard %s: R=%d, %.3f s, %.1f solves/s, iters %d" % (name, len(ports), t, len(ports) / t, it.max()))
+    finally:
+        mbt.mbt_array_destroy(arr)
+        mbt.mbt_ctx_destroy(ctx)
+    return {"metric": "port-excitation solves/s of one GPU's port share (admittance columns only)",
+            "value": out["mixed"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "dipole_32x32_m31_port_share", "rhs": len(ports), "steps": args.steps,
+                       "operator_cached": True},
+            "paths": out}
+
+
 def sweep(args):
     """Precision form: the 5x5 array at 21 frequencies (one request, served
     concurrently) in FP64, FP32, FP16 and BF16 products with at most three FP64
@@ -476,6 +515,8 @@ def main():
                     help="stream rates as fractions of saturation, comma-separated (the first is the headline "
                          "of the JSON line; 0: report the saturation run only)")
     ap.add_argument("--sweep", action="store_true", help="run the 21-frequency precision sweep instead")
+    ap.add_argument("--shard", type=int, default=0,
+                    help="time one GPU's share of the ports (this many RHS, admittance only) instead")
     ap.add_argument("--blocks", type=int, default=0,
                     help="run the 64x64x96 synthetic-block shape with this many operators (1..5) instead")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -499,6 +540,8 @@ def main():
         result = serve(args)
     elif args.sweep:
         result = sweep(args)
+    elif args.shard > 0:
+        result = shard(args)
     elif args.blocks > 0:
         result = blocks_shape(args)
     else:
