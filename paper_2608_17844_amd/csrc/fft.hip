@@ -307,13 +307,14 @@ __device__ __forceinline__ void fft_reg(cplx<T> (&v)[L], const cplx<T>* __restri
 // only twiddles the input).  The row spectra pass through one LDS tile.
 // Phase 2: thread (bin b, column w) transforms its column for both
 // y-parities and writes the four parity bins.  Two LDS round trips per block.
-// FMT selects the spectrum's storage: FP32 complex, or 16-bit complex words.
-template <int LX, int LY, int W, int FMT>
-__global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_fwd_reg_kernel(const float2* __restrict__ X,
+// T is float or double; FMT selects the FP32 spectrum's storage: FP32 complex,
+// or 16-bit complex words.
+template <typename T, int LX, int LY, int W, int FMT>
+__global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_fwd_reg_kernel(const cplx<T>* __restrict__ X,
                                                                               void* __restrict__ Xh_, int nx, int ny,
-                                                                              int64_t B, const float2* __restrict__ twx,
-                                                                              const float2* __restrict__ twy) {
-    using C = float2;
+                                                                              int64_t B, const cplx<T>* __restrict__ twx,
+                                                                              const cplx<T>* __restrict__ twy) {
+    using C = cplx<T>;
     constexpr int PX = 2 * LX;
     // rows of the tile are padded by one W-slot so that the rows that one
     // half-wave touches at once fall on different LDS banks
@@ -322,19 +323,27 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_fwd_reg_kernel(co
     const int w = threadIdx.x % W, r = threadIdx.x / W;
     const int64_t c = (int64_t)blockIdx.x * W + w;
     const bool cv = c < B;
-    C row[LX];
-    if (r < LY) {
+    // FP32 keeps the row in registers for both x-parities; FP64 (twice the
+    // registers per value) reads it again for the second parity
+    constexpr bool KEEP = sizeof(T) == 4;
+    C row[KEEP ? LX : 1];
+    if (KEEP && r < LY) {
 #pragma unroll
         for (int ix = 0; ix < LX; ++ix)
-            row[ix] = (cv && r < ny && ix < nx) ? X[(int64_t)(r * nx + ix) * B + c] : mk<float>(0, 0);
+            row[ix] = (cv && r < ny && ix < nx) ? X[(int64_t)(r * nx + ix) * B + c] : mk<T>(0, 0);
     }
 #pragma unroll
     for (int be = 0; be < 2; ++be) {
         if (r < LY) {
             C f[LX];
 #pragma unroll
-            for (int ix = 0; ix < LX; ++ix) f[ix] = (be && ix) ? cmul(row[ix], twx[ix]) : row[ix];
-            fft_reg<float, LX, false>(f, twx);
+            for (int ix = 0; ix < LX; ++ix) {
+                C v;
+                if constexpr (KEEP) v = row[ix];
+                else v = (cv && r < ny && ix < nx) ? X[(int64_t)(r * nx + ix) * B + c] : mk<T>(0, 0);
+                f[ix] = (be && ix) ? cmul(v, twx[ix]) : v;
+            }
+            fft_reg<T, LX, false>(f, twx);
 #pragma unroll
             for (int b = 0; b < LX; ++b) tile[r * RS + b * W + w] = f[b];
         }
@@ -350,13 +359,13 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_fwd_reg_kernel(co
                     const C t = tile[iy * RS + r * W + w];
                     g[iy] = (al && iy) ? cmul(t, twy[iy]) : t;
                 }
-                fft_reg<float, LY, false>(g, twy);
+                fft_reg<T, LY, false>(g, twy);
                 if (cv) {
 #pragma unroll
                     for (int a = 0; a < LY; ++a) {
                         const int64_t o = ((int64_t)(2 * a + al) * PX + (2 * r + be)) * B + c;
-                        if constexpr (FMT == kFmtNone)
-                            static_cast<float2*>(Xh_)[o] = g[a];
+                        if constexpr (FMT == kFmtNone || sizeof(T) != 4)
+                            static_cast<C*>(Xh_)[o] = g[a];
                         else
                             static_cast<uint32_t*>(Xh_)[o] = pack16<FMT>(g[a]);
                     }
@@ -372,12 +381,12 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_fwd_reg_kernel(co
 // columns of bin b and sums them with their twiddles.  Phase B: thread (row iy,
 // column w) inverse-transforms the row and accumulates the x-parity with its
 // twiddle; only rows iy < ny and columns ix < nx are written.
-template <int LX, int LY, int W>
-__global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_inv_reg_kernel(const float2* __restrict__ Yh,
-                                                                              float2* __restrict__ Y, int nx, int ny,
-                                                                              int64_t B, const float2* __restrict__ twx,
-                                                                              const float2* __restrict__ twy) {
-    using C = float2;
+template <typename T, int LX, int LY, int W>
+__global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_inv_reg_kernel(const cplx<T>* __restrict__ Yh,
+                                                                              cplx<T>* __restrict__ Y, int nx, int ny,
+                                                                              int64_t B, const cplx<T>* __restrict__ twx,
+                                                                              const cplx<T>* __restrict__ twy) {
+    using C = cplx<T>;
     constexpr int PX = 2 * LX;
     // rows of the tile are padded by one W-slot so that the rows that one
     // half-wave touches at once fall on different LDS banks
@@ -388,20 +397,20 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_inv_reg_kernel(co
     const bool cv = c < B;
     C out[LX];
 #pragma unroll
-    for (int ix = 0; ix < LX; ++ix) out[ix] = mk<float>(0, 0);
+    for (int ix = 0; ix < LX; ++ix) out[ix] = mk<T>(0, 0);
 #pragma unroll
     for (int be = 0; be < 2; ++be) {
         if (r < LX) {
             C acc[LY];
 #pragma unroll
-            for (int iy = 0; iy < LY; ++iy) acc[iy] = mk<float>(0, 0);
+            for (int iy = 0; iy < LY; ++iy) acc[iy] = mk<T>(0, 0);
 #pragma unroll
             for (int al = 0; al < 2; ++al) {
                 C g[LY];
 #pragma unroll
                 for (int a = 0; a < LY; ++a)
-                    g[a] = cv ? Yh[((int64_t)(2 * a + al) * PX + (2 * r + be)) * B + c] : mk<float>(0, 0);
-                fft_reg<float, LY, true>(g, twy);
+                    g[a] = cv ? Yh[((int64_t)(2 * a + al) * PX + (2 * r + be)) * B + c] : mk<T>(0, 0);
+                fft_reg<T, LY, true>(g, twy);
 #pragma unroll
                 for (int iy = 0; iy < LY; ++iy) acc[iy] = cadd(acc[iy], (al && iy) ? cmul(g[iy], cconj(twy[iy])) : g[iy]);
             }
@@ -413,7 +422,7 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_inv_reg_kernel(co
             C h[LX];
 #pragma unroll
             for (int b = 0; b < LX; ++b) h[b] = tile[r * RS + b * W + w];
-            fft_reg<float, LX, true>(h, twx);
+            fft_reg<T, LX, true>(h, twx);
 #pragma unroll
             for (int ix = 0; ix < LX; ++ix) out[ix] = cadd(out[ix], (be && ix) ? cmul(h[ix], cconj(twx[ix])) : h[ix]);
         }
@@ -652,6 +661,9 @@ __global__ void embed_y_kernel(const double2* __restrict__ tmp, double2* __restr
 // Columns per workgroup: fill a 128 KB LDS tile (one workgroup per CU), at
 // most 16 columns.  At the 64x64 grid this gives 128 contiguous bytes per
 // lattice point in FP64 (8 columns) and in FP32 (16 columns).
+// columns per workgroup of the FP64 register transforms
+constexpr int kRegW64 = 4;
+
 template <typename T> constexpr int tile_w(int lx, int ly) {
     int w = (int)(131072 / (lx * ly * (int)sizeof(cplx<T>)));
     return w > 16 ? 16 : (w < 1 ? 1 : w);
@@ -669,17 +681,31 @@ void launch_fft_t(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, con
             return;
         }
     }
+    if constexpr (sizeof(T) == 8 && LX <= 32 && LY <= 32) {
+        // FP64 inverse: the register transform with fewer columns per workgroup
+        // (a row of 32 values fills 128 registers), two workgroups per CU.  The
+        // FP64 forward stays on the LDS kernel, which measured faster.
+        if (!FWD) {
+            constexpr int WD = W > kRegW64 ? kRegW64 : W;
+            constexpr int NT = (LX > LY ? LX : LY) * WD;
+            const int64_t nb = (B + WD - 1) / WD;
+            hipLaunchKernelGGL((fft_inv_reg_kernel<T, LX, LY, WD>), dim3((unsigned)nb), dim3(NT), 0, s, in, out, g.nx,
+                               g.ny, B, twx, twy);
+            MBT_LAUNCH_CHECK();
+            return;
+        }
+    }
     if constexpr (sizeof(T) == 4 && LX <= 32 && LY <= 32) {
         constexpr int NT = (LX > LY ? LX : LY) * W;
         if (FWD)
-            hipLaunchKernelGGL((fft_fwd_reg_kernel<LX, LY, W, kFmtNone>), dim3((unsigned)blocks), dim3(NT), 0, s, in,
+            hipLaunchKernelGGL((fft_fwd_reg_kernel<T, LX, LY, W, kFmtNone>), dim3((unsigned)blocks), dim3(NT), 0, s, in,
                                (void*)out, g.nx, g.ny, B, twx, twy);
         else {
             // the inverse reads four times what it writes: half-size tiles put two
             // workgroups on a CU, so one loads while the other transforms (pairs of
             // workgroups that share 128-byte lines run on one XCD)
             constexpr int WI = W > 8 ? 8 : W;
-            hipLaunchKernelGGL((fft_inv_reg_kernel<LX, LY, WI>), dim3((unsigned)((B + WI - 1) / WI)),
+            hipLaunchKernelGGL((fft_inv_reg_kernel<T, LX, LY, WI>), dim3((unsigned)((B + WI - 1) / WI)),
                                dim3((LX > LY ? LX : LY) * WI), 0, s, in, out, g.nx, g.ny, B, twx, twy);
         }
         MBT_LAUNCH_CHECK();
@@ -727,7 +753,7 @@ void launch_fwd16(const Geom& g, const float2* X, uint32_t* Xh, int64_t B, const
         constexpr int NT = (LX > LY ? LX : LY) * W;
         const int64_t blocks = (B + W - 1) / W;
         MBT_REQUIRE(blocks < (1LL << 31), "fft: batch too large");
-        hipLaunchKernelGGL((fft_fwd_reg_kernel<LX, LY, W, FMT>), dim3((unsigned)blocks), dim3(NT), 0, s, X, (void*)Xh,
+        hipLaunchKernelGGL((fft_fwd_reg_kernel<float, LX, LY, W, FMT>), dim3((unsigned)blocks), dim3(NT), 0, s, X, (void*)Xh,
                            g.nx, g.ny, B, twx, twy);
         MBT_LAUNCH_CHECK();
     } else {
