@@ -80,7 +80,7 @@ typedef struct { int32_t nx, ny; double dx, dy; } mbt_lattice;
 typedef struct {
     int32_t prec;         /* mbt_prec */
     int32_t pc;           /* mbt_pc */
-    int32_t restart;      /* GMRES restart length m (>= 1), default 50 */
+    int32_t restart;      /* GMRES restart length m (>= 1), default 50 (PCG: iteration cap restart * max_cycles) */
     double tol;           /* FP64 path: relative preconditioned residual, default 1e-10 */
     int32_t max_cycles;   /* restart cycles per (inner) solve, default 400 */
     int32_t refine_max;   /* reduced precision: max outer refinement steps, default 3 */
@@ -116,10 +116,10 @@ typedef struct {
 typedef struct {
     int32_t nrhs;             /* RHS solved */
     int32_t nconverged;       /* RHS that met the tolerance */
-    int32_t cycles;           /* restart cycles (max over RHS, summed over outer steps) */
+    int32_t cycles;           /* restart cycles (max over RHS, summed over outer steps; PCG: 1 per solve) */
     int32_t outer_steps;      /* refinement steps (1 for FP64) */
     int32_t iters_min, iters_max;
-    int64_t iters_total;      /* Arnoldi steps summed over RHS */
+    int64_t iters_total;      /* Arnoldi (or PCG) steps summed over RHS */
     int64_t matvecs;          /* batched operator applications (Z or Z^H, each counted) */
     double true_relres_max;   /* max over RHS of ||V - Z I|| / ||V||, FP64 */
     double t_setup, t_solve, t_extract;   /* seconds (device-synchronised phases) */
