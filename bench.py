@@ -416,6 +416,40 @@ def blocks_shape(args):
     return out
 
 
+def small(args):
+    """The 5x5 array of 15-basis dipoles (25 ports, broadside + 10 scans): the
+    whole path per request, operator rebuilt each time; latency-bound.  (Its
+    accuracy against the oracle is checked by the GPU tests.)"""
+    from paper_2608_17844_amd import mbt
+    from paper_2608_17844_amd import workloads as W
+    w = W.cpu_size_5x5()
+    ctx = mbt.mbt_ctx_create(0)
+    arr = mbt.mbt_array_create_dipole(ctx, w.dipole, w.lattice)
+    out = {}
+    try:
+        for name, opts in (("mixed", mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK,
+                                                          flags=mbt.MBT_FLAG_NO_CACHE)),
+                           ("fp64", mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK,
+                                                         flags=mbt.MBT_FLAG_NO_CACHE))):
+            mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
+            ts = []
+            for _ in range(max(args.steps, 5)):
+                t0 = time.perf_counter()
+                r = mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts))
+            out[name] = {"solves_per_s": 25 / t, "ms_per_request": 1e3 * t, "iters_max": r["stats"]["iters_max"],
+                         "outer_steps": r["stats"]["outer_steps"]}
+            log("small %s: %.2f ms per request, %.0f solves/s" % (name, 1e3 * t, 25 / t))
+    finally:
+        mbt.mbt_array_destroy(arr)
+        mbt.mbt_ctx_destroy(ctx)
+    return {"metric": "port-excitation solves/s, 5x5 dipoles (latency-bound, whole path per request)",
+            "value": out["mixed"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic", "config": {"workload": w.name, "ports": 25, "nscan": len(w.theta)},
+            "paths": out}
+
+
 def shard(args):
     """One GPU's share of the all-port workload under a split of the ports over
     GPUs: the admittance columns of R ports of the 32x32 array (ports 0..R-1),
@@ -515,6 +549,7 @@ def main():
                     help="stream rates as fractions of saturation, comma-separated (the first is the headline "
                          "of the JSON line; 0: report the saturation run only)")
     ap.add_argument("--sweep", action="store_true", help="run the 21-frequency precision sweep instead")
+    ap.add_argument("--small", action="store_true", help="time the 5x5 array's whole path instead")
     ap.add_argument("--shard", type=int, default=0,
                     help="time one GPU's share of the ports (this many RHS, admittance only) instead")
     ap.add_argument("--blocks", type=int, default=0,
@@ -542,6 +577,8 @@ def main():
         result = sweep(args)
     elif args.shard > 0:
         result = shard(args)
+    elif args.small:
+        result = small(args)
     elif args.blocks > 0:
         result = blocks_shape(args)
     else:
