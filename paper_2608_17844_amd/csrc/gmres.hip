@@ -15,7 +15,8 @@
 // every per-RHS dot product is accumulated in a fixed order that does not
 // depend on how many other RHS share the batch (bit-identical results alone or
 // batched).  Rows are split into fixed chunks (a function of N only) whose
-// partial sums are reduced in chunk order by a second kernel.
+// partial sums are reduced by a second kernel in a fixed order (groups of 64
+// chunks, then the groups).
 //
 // HBM traffic per Arnoldi step is dominated by the basis reads.  DCGS2 step k
 // reads V_{0..k-1}, the candidate u and w = A u once for all dot products
@@ -25,14 +26,17 @@
 // w <- w - V h2 together with ||w||^2.  In the dot sweeps the waves of a
 // workgroup share rows and RHS and split the basis vectors; the DCGS2 update
 // gives each wave its own rows and all vectors.
-// The basis may be stored in FP32 (reduced-precision inner solves) while all
-// dot products, norms and the Hessenberg/Givens recurrences stay FP64.
+// The reduced-precision inner solves keep the basis packed (FP32 components
+// rounded to 24 bits, two RHS per 12-byte word) or in FP32, with FP32 work
+// vectors; all dot products, norms and the Hessenberg/Givens recurrences stay
+// FP64.  The file also holds the batched PCG on the normal equations (Sec.
+// II-C), which reuses the chunked reductions.
 #include "common.h"
 #include "gmres.h"
 
 #include <algorithm>
-#include <type_traits>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 namespace mbt {
