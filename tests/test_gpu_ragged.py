@@ -100,3 +100,19 @@ def test_packed_basis_against_fp32_basis(setup):
     assert Y3.shape == (256, 3) and it3.shape == (3,)
     assert st3["nrhs"] == 3 and st3["nconverged"] == 3
     assert np.linalg.norm(Y3 - ref.Yp[:, odd]) <= 1e-8 * np.linalg.norm(ref.Yp[:, odd])
+
+
+@pytest.mark.parametrize("case", ["fp32_basis", "cgs2"])
+def test_mixed_path_without_packed_basis(setup, case):
+    """The plain FP32 basis layout is taken where the packed one does not apply
+    (asked for, or classical CGS2): both reach the refined accuracy, and an odd
+    port count is solved as it is (no padding)."""
+    mbt, ctx, arr, ref = setup
+    kw = dict(flags=mbt.MBT_FLAG_FP32_BASIS if case == "fp32_basis" else mbt.MBT_FLAG_CGS2)
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, tol=1e-11, refine_tol=1e-10,
+                                refine_max=5, **kw)
+    ports = [1, 100, 255]
+    Y, it, st = mbt.mbt_port_admittance(ctx, arr, 1.0, ports, opts)
+    err = np.linalg.norm(Y - ref.Yp[:, ports]) / np.linalg.norm(ref.Yp[:, ports])
+    _say("%s: iters %d..%d outer %d err %.2e" % (case, it.min(), it.max(), st["outer_steps"], err))
+    assert err <= 1e-8 and st["nconverged"] == 3 and st["nrhs"] == 3
