@@ -312,7 +312,7 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 // covers the vectors i0 .. i0+nv-1 (the sweep may be split into launches of at
 // most NW*G vectors); alpha and beta come from the launch with i0 = 0.
 template <typename TB, typename TV, int NW, int G, int RPL, bool HASW>
-__global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TV* __restrict__ V, int64_t vstride, int k,
+__global__ __launch_bounds__(NW * 64, (std::is_same<TV, p24x2>::value && G <= 4 ? 4 : 1)) void dcgs2_dots_kernel(const TV* __restrict__ V, int64_t vstride, int k,
                                                              int i0, int nv, const TB* __restrict__ u,
                                                              const TB* __restrict__ w, int64_t N, int R,
                                                              int64_t rows_per_chunk, double2* __restrict__ partial) {
@@ -345,9 +345,17 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TV* __restric
         }
     };
     const bool ab_here = (i0 == 0) && (wave == 0);
-    if (live && n0 < n1) load_row(n0, cur, cu, cw);
+    // The packed basis (up to four vectors per wave) loads each row when it is
+    // used and runs four waves per SIMD, whose interleaving hides the load
+    // latency (a register prefetch would limit it to three); the other cases
+    // prefetch the next row.
+    constexpr bool kPrefetch = !(std::is_same<TV, p24x2>::value && G <= 4);
+    if (kPrefetch && live && n0 < n1) load_row(n0, cur, cu, cw);
     for (int64_t n = n0; n < n1; ++n) {
-        if (live && n + 1 < n1) load_row(n + 1, nxt, nu_, nw_);
+        if (live) {
+            if (!kPrefetch) load_row(n, cur, cu, cw);
+            else if (n + 1 < n1) load_row(n + 1, nxt, nu_, nw_);
+        }
         if (live) {
 #pragma unroll
             for (int k2 = 0; k2 < RPL; ++k2) {
@@ -365,10 +373,12 @@ __global__ __launch_bounds__(NW * 64) void dcgs2_dots_kernel(const TV* __restric
                 }
             }
         }
+        if (kPrefetch) {
 #pragma unroll
-        for (int g = 0; g < G; ++g) cur[g] = nxt[g];
-        cu = nu_;
-        cw = nw_;
+            for (int g = 0; g < G; ++g) cur[g] = nxt[g];
+            cu = nu_;
+            cw = nw_;
+        }
     }
     if (!live) return;
 #pragma unroll
