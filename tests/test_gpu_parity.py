@@ -52,6 +52,8 @@ SHAPES = [
     (W.Lattice(40, 2, 0.5, 0.5), W.Dipole(0.5, 0.005, 7)),
     (W.Lattice(3, 36, 0.5, 0.5), W.Dipole(0.5, 0.005, 5)),
     (W.Lattice(33, 34, 0.5, 0.5), W.Dipole(0.5, 0.005, 3)),
+    # one basis per element: the port basis is the only unknown of an element
+    (W.Lattice(4, 3, 0.5, 0.5), W.Dipole(0.5, 0.005, 1)),
 ]
 
 
@@ -218,6 +220,23 @@ def test_single_element_one_iteration(ctx, make_array):
         assert iters[0] == 1
         Z = mom.fill_dense(lat, dip, 1.0)
         assert abs(Y[0, 0] - np.linalg.solve(Z, mom.excitation(lat, dip))[7, 0]) < 1e-12
+
+
+def test_single_basis_elements_solve(ctx, make_array):
+    """M = 1 (two segments per wire, one rooftop at the gap): the 1x1 element blocks,
+    both preconditioners, FP64 and the refined FP32 path against the dense LU."""
+    from paper_2608_17844_amd import mbt
+    lat, dip = W.Lattice(4, 3, 0.5, 0.5), W.Dipole(0.5, 0.005, 1)
+    theta, phi = np.array([0.0, 0.3, 0.7]), np.array([0.0, 1.0, 2.5])
+    ref = mom.solve_array(lat, dip, 1.0, theta=theta, phi=phi)
+    a = make_array(lat, dip)
+    for prec, tol in ((mbt.MBT_FP64, 1e-9), (mbt.MBT_FP32, 1e-6)):
+        for pc in (0, 1):
+            _say("M=1 prec=%d pc=%d" % (prec, pc))
+            out = mbt.mbt_solve(ctx, a, 1.0, mbt.mbt_default_opts(prec=prec, pc=pc), theta, phi, 50.0)
+            assert np.linalg.norm(out["Zp"] - ref.Zp) / np.linalg.norm(ref.Zp) <= tol
+            assert np.max(np.abs(out["Gamma"] - ref.Gamma)) <= tol
+            assert np.max(np.abs(out["Gamma_wave"] - ref.Gamma_wave)) <= tol
 
 
 def test_gauss_jordan_inverse(ctx):
