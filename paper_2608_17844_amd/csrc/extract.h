@@ -6,7 +6,8 @@
 namespace mbt {
 
 // Inverse of the n x n array A (overwritten) into out, Gauss-Jordan with partial pivoting.
-// colbuf: n complex; piv: n ints; flag: 1 int.  Throws on a singular matrix.
+// colbuf: n complex; piv: n ints; flag: 1 int; out (n x n, not overlapping A) serves as
+// workspace until the result is written.  Throws on a singular matrix.
 void gj_inverse(double2* A, double2* out, int n, double2* colbuf, int* piv, int* flag, hipStream_t s);
 // S = I - 2 z0 (Zp + z0 I)^{-1}; work: n*n complex scratch.
 void s_matrix(const double2* Zp, double2* S, double2* work, int n, double z0, double2* colbuf, int* piv, int* flag,

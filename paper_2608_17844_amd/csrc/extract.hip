@@ -9,11 +9,16 @@
 //   (eq. (ARC)), and the wave-excited reflection coefficient, the phased S-sum
 //   of Sec. II-D.
 //
-// The dense inverses use Gauss-Jordan elimination with partial pivoting: one
-// pivot/scale kernel and one rank-1 elimination kernel per column.
+// The dense inverses use Gauss-Jordan elimination with partial pivoting.  For
+// 64 <= n <= 1024 it is blocked: a panel of eight columns is factored in LDS by
+// one workgroup, which then applies the panel's row interchanges and pivot
+// rows to the other columns; a rank-8 update of the remaining rows follows, so
+// the matrix is streamed once per panel instead of once per column.  Other
+// sizes use one pivot kernel and one rank-1 elimination kernel per column.
 #include "common.h"
 #include "extract.h"
 
+#include <algorithm>
 #include <vector>
 
 namespace mbt {
@@ -77,6 +82,226 @@ __global__ void gj_elim_kernel(double2* __restrict__ A, int n, int k, const doub
     if (i == k) return;
     const double2 base = (j == k) ? make_double2(0, 0) : A[t];
     A[t] = csub(base, cmul(colbuf[i], A[(int64_t)k * n + j]));
+}
+
+// ---- blocked form (n <= kPanT: one row per thread of the panel workgroup)
+constexpr int kPanT = 1024;       // threads of the panel workgroup
+constexpr int kMaxPan = 8;        // columns per panel
+constexpr int kPanLds = 8192;     // complex values of the LDS panel (128 KB)
+constexpr int kBlockedMinN = 64;
+constexpr int kUpdRows = 4;       // rows per thread of the rank-nb update
+
+// Steps k0 .. k0+NB-1 of the elimination.  Panel columns, held column by
+// column in LDS, take the steps in the order and with the arithmetic of the
+// unblocked kernels; thread i owns row i and keeps its multipliers L[c][i]
+// (A[i][k] before the elimination of step c, 0 at i = k) in registers, so a
+// row interchange swaps them between two threads through LDS.  The scaled
+// pivot row is written by its owner after the step's last barrier (no later
+// step of the panel reads it before then).  At the end: the panel columns,
+// L, piv and 1/pivot go to memory, and every other column j takes the panel's
+// row interchanges and its pivot rows (row k scaled, then eliminated from the
+// other pivot rows); RK[c][j] keeps row k0+c as it is right after its scaling,
+// the value the remaining rows are eliminated with (gj_update_kernel).
+template <int NB>
+__global__ __launch_bounds__(kPanT) void gj_panel_kernel(double2* __restrict__ A, int n, int k0,
+                                                         double2* __restrict__ L, int* __restrict__ piv,
+                                                         int* __restrict__ singular, double2* __restrict__ RK) {
+    __shared__ double2 pan[kPanLds];   // pan[c * n + i] = A[i][k0 + c]
+    __shared__ double rv[kPanT / 64];
+    __shared__ int ri[kPanT / 64];
+    __shared__ int pv[NB];
+    __shared__ double2 dv[NB];
+    __shared__ double2 xl[2][NB];      // multipliers of the two interchanged rows
+    __shared__ double2 lp[NB][NB];     // lp[c][q] = L[c][k0 + q]
+    __shared__ int psrc[NB], exd[NB], exs[NB], nex;
+    const int tid = threadIdx.x;
+    const int i = tid;
+    const bool own = i < n;
+    for (int t = tid; t < n * NB; t += kPanT) pan[(t % NB) * n + t / NB] = A[(int64_t)(t / NB) * n + k0 + t % NB];
+    __syncthreads();
+    double2 lreg[NB], rk[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) lreg[c] = rk[c] = make_double2(0, 0);
+    bool pend = false;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const int k = k0 + c;
+        {
+            if (pend) {
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    pan[j * n + i] = rk[j];
+                pend = false;
+            }
+            double best = -1.0;
+            int bi = n;
+            if (own && i >= k) {
+                const double2 v = pan[c * n + i];
+                best = v.x * v.x + v.y * v.y;
+                bi = i;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if ((tid & 63) == 0) { rv[tid >> 6] = best; ri[tid >> 6] = bi; }
+            __syncthreads();
+            double pb[kPanT / 64];
+            int pi[kPanT / 64];
+#pragma unroll
+            for (int w = 0; w < kPanT / 64; ++w) { pb[w] = rv[w]; pi[w] = ri[w]; }
+            double bb = pb[0];
+            int p = pi[0];
+#pragma unroll
+            for (int w = 1; w < kPanT / 64; ++w) {
+                const bool take = pb[w] > bb || (pb[w] == bb && pi[w] < p);
+                bb = take ? pb[w] : bb;
+                p = take ? pi[w] : p;
+            }
+            if (tid == 0) {
+                pv[c] = p;
+                if (!(bb > 0.0)) singular[0] = 1;
+            }
+            const bool swp = p != k && p < n;
+            if (swp) {
+                if (tid < NB) {
+                    const double2 t = pan[tid * n + k];
+                    pan[tid * n + k] = pan[tid * n + p];
+                    pan[tid * n + p] = t;
+                }
+                if (i == k || i == p)
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) xl[i == k ? 0 : 1][q] = lreg[q];
+            }
+            __syncthreads();
+            if (swp && (i == k || i == p))
+#pragma unroll
+                for (int q = 0; q < NB; ++q) lreg[q] = xl[i == k ? 1 : 0][q];
+            const double2 d = pan[c * n + k];
+            const double den = d.x * d.x + d.y * d.y;
+            const double2 di = den > 0.0 ? make_double2(d.x / den, -d.y / den) : make_double2(0, 0);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                rk[j] = cmul((j == c) ? make_double2(1.0, 0.0) : pan[j * n + k], di);
+            if (tid == 0) dv[c] = di;
+            if (own) {
+                if (i == k) {
+                    lreg[c] = make_double2(0, 0);
+                    pend = true;
+                } else {
+                    const double2 l = pan[c * n + i];
+                    lreg[c] = l;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        const double2 base = (j == c) ? make_double2(0, 0) : pan[j * n + i];
+                        pan[j * n + i] = csub(base, cmul(l, rk[j]));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (pend)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            pan[j * n + i] = rk[j];
+    if (own) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            L[(int64_t)c * n + i] = lreg[c];
+        if (i >= k0 && i < k0 + NB)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) lp[c][i - k0] = lreg[c];
+    }
+    if (tid < NB) piv[k0 + tid] = pv[tid];
+    if (tid == 0) {
+        // compose the interchanges on the rows they touch
+        int rows[2 * NB], srcr[2 * NB];
+        int m = 0;
+        for (int c = 0; c < NB; ++c) { rows[m] = k0 + c; srcr[m] = k0 + c; ++m; }
+        for (int c = 0; c < NB; ++c) {
+            const int q = pv[c];
+            if (q < 0 || q >= n || (q >= k0 && q < k0 + NB)) continue;
+            bool seen = false;
+            for (int x = NB; x < m; ++x) seen = seen || rows[x] == q;
+            if (!seen) { rows[m] = q; srcr[m] = q; ++m; }
+        }
+        for (int c = 0; c < NB; ++c) {
+            const int q = pv[c];
+            if (q == k0 + c || q < 0 || q >= n) continue;
+            int xa = 0, xb = 0;
+            for (int x = 0; x < m; ++x) {
+                if (rows[x] == k0 + c) xa = x;
+                if (rows[x] == q) xb = x;
+            }
+            const int t = srcr[xa];
+            srcr[xa] = srcr[xb];
+            srcr[xb] = t;
+        }
+        int ne = 0;
+        for (int c = 0; c < NB; ++c) psrc[c] = srcr[c];
+        for (int x = NB; x < m; ++x)
+            if (srcr[x] != rows[x]) { exd[ne] = rows[x]; exs[ne] = srcr[x]; ++ne; }
+        nex = ne;
+    }
+    __syncthreads();
+    for (int t = tid; t < n * NB; t += kPanT) A[(int64_t)(t / NB) * n + k0 + t % NB] = pan[(t % NB) * n + t / NB];
+    // the other columns: row interchanges (all sources read before any row is
+    // written), then the pivot rows
+    const int j = tid;
+    if (!own || (j >= k0 && j < k0 + NB)) return;
+    const int ne = nex;
+    double2 r[NB], ex[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) r[c] = A[(int64_t)psrc[c] * n + j];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) ex[e] = e < ne ? A[(int64_t)exs[e] * n + j] : make_double2(0, 0);
+#pragma unroll
+    for (int e = 0; e < NB; ++e)
+        if (e < ne) A[(int64_t)exd[e] * n + j] = ex[e];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        {
+            r[c] = cmul(r[c], dv[c]);
+            RK[(int64_t)c * n + j] = r[c];
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q != c) r[q] = csub(r[q], cmul(lp[c][q], r[c]));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+        A[(int64_t)(k0 + c) * n + j] = r[c];
+}
+
+// The rest: A[i][j] -= L[c][i] RK[c][j] over the panel's steps in order, for
+// rows i and columns j outside the panel; a thread keeps RK[.][j] in registers
+// for kUpdRows rows.
+template <int NB>
+__global__ void gj_update_kernel(double2* __restrict__ A, int n, int k0, const double2* __restrict__ L,
+                                 const double2* __restrict__ RK) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i0 = blockIdx.y * kUpdRows;
+    if (j >= n || (j >= k0 && j < k0 + NB)) return;
+    double2 rk[NB], a[kUpdRows];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) rk[c] = RK[(int64_t)c * n + j];
+#pragma unroll
+    for (int u = 0; u < kUpdRows; ++u) {
+        const int i = i0 + u;
+        a[u] = (i < n && !(i >= k0 && i < k0 + NB)) ? A[(int64_t)i * n + j] : make_double2(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kUpdRows; ++u) {
+        const int i = i0 + u;
+        if (i < n && !(i >= k0 && i < k0 + NB)) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                a[u] = csub(a[u], cmul(L[(int64_t)c * n + i], rk[c]));
+            A[(int64_t)i * n + j] = a[u];
+        }
+    }
 }
 
 // out[i][j] = in[i][src[j]]
@@ -150,15 +375,42 @@ __global__ __launch_bounds__(256) void scan_kernel(const double2* __restrict__ Z
 
 inline unsigned g1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+template <int NB>
+void launch_panel(double2* A, int n, int k0, double2* L, int* piv, int* flag, double2* RK, dim3 ug, hipStream_t s) {
+    hipLaunchKernelGGL((gj_panel_kernel<NB>), dim3(1), dim3(kPanT), 0, s, A, n, k0, L, piv, flag, RK);
+    hipLaunchKernelGGL((gj_update_kernel<NB>), ug, dim3(256), 0, s, A, n, k0, L, RK);
+}
+
 }  // namespace
 
 // In-place Gauss-Jordan on A (n x n, any consistent layout: the inverse of the
-// stored array is returned in the same layout).  Workspace: n complex + 2n ints.
+// stored array is returned in the same layout).  Workspace: n complex + 2n ints;
+// the blocked form also uses out (which must not overlap A) until the end.
 void gj_inverse(double2* A, double2* out, int n, double2* colbuf, int* piv, int* flag, hipStream_t s) {
     MBT_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-    for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(gj_pivot_kernel, dim3(1), dim3(kPivT), 0, s, A, n, k, colbuf, piv, flag);
-        hipLaunchKernelGGL(gj_elim_kernel, dim3(g1((int64_t)n * n)), dim3(256), 0, s, A, n, k, colbuf);
+    const int nb = n > 0 ? std::min(kMaxPan, kPanLds / n) : 0;
+    if (n >= kBlockedMinN && n <= kPanT && nb >= 2) {
+        // out: L (nb x n), RK (nb x n); n >= 64 leaves room
+        double2* L = out;
+        double2* RK = out + (size_t)nb * n;
+        const dim3 ug(g1(n), (unsigned)((n + kUpdRows - 1) / kUpdRows));
+        for (int k0 = 0; k0 < n; k0 += nb) {
+            switch (std::min(nb, n - k0)) {
+            case 8: launch_panel<8>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 7: launch_panel<7>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 6: launch_panel<6>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 5: launch_panel<5>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 4: launch_panel<4>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 3: launch_panel<3>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 2: launch_panel<2>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            default: launch_panel<1>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            }
+        }
+    } else {
+        for (int k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(gj_pivot_kernel, dim3(1), dim3(kPivT), 0, s, A, n, k, colbuf, piv, flag);
+            hipLaunchKernelGGL(gj_elim_kernel, dim3(g1((int64_t)n * n)), dim3(256), 0, s, A, n, k, colbuf);
+        }
     }
     MBT_LAUNCH_CHECK();
     std::vector<int> hp(n);

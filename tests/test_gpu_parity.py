@@ -240,12 +240,24 @@ def test_single_basis_elements_solve(ctx, make_array):
 
 
 def test_gauss_jordan_inverse(ctx):
+    """Unblocked below 64; blocked from 64 on, with full panels of eight columns,
+    a one-column last panel (1001) and three-column panels (2304, the LDS limit)."""
     from paper_2608_17844_amd import mbt
     rng = np.random.default_rng(11)
-    for n in (1, 5, 64, 300):
+    for n in (1, 5, 63, 64, 300, 1001, 2304):
+        _say("inverse n=%d" % n)
         A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 2 * np.eye(n)
         Ai = mbt.mbt_dbg_inverse(ctx, A)
         assert np.linalg.norm(Ai @ A - np.eye(n)) <= 1e-11 * n
+    # pivoting: a permuted diagonal, whose pivots lie off the diagonal at almost every step
+    n = 200
+    perm = rng.permutation(n)
+    A = np.zeros((n, n), complex)
+    A[np.arange(n), perm] = 1.0 + rng.random(n)
+    Ai = mbt.mbt_dbg_inverse(ctx, A)
+    assert np.linalg.norm(Ai @ A - np.eye(n)) <= 1e-13 * n
+    with pytest.raises(mbt.MbtError):
+        mbt.mbt_dbg_inverse(ctx, np.zeros((100, 100), complex))
 
 
 def test_subset_of_ports_and_errors(ctx, make_array, cfg1, cfg1_oracle):
