@@ -10,11 +10,13 @@
 //   of Sec. II-D.
 //
 // The dense inverses use Gauss-Jordan elimination with partial pivoting.  For
-// 64 <= n <= 1024 it is blocked: a panel of eight columns is factored in LDS by
-// one workgroup, which then applies the panel's row interchanges and pivot
-// rows to the other columns; a rank-8 update of the remaining rows follows, so
-// the matrix is streamed once per panel instead of once per column.  Other
-// sizes use one pivot kernel and one rank-1 elimination kernel per column.
+// 64 <= n <= 1024 it is blocked: one workgroup factors a panel of eight
+// columns with each row in its owner thread's registers, then applies the
+// panel's row interchanges and pivot rows to the other columns; a rank-8
+// update of the remaining rows follows, so the matrix is streamed once per
+// panel instead of once per column.  Other sizes use one pivot kernel and one
+// rank-1 elimination kernel per column.  The blocked pivot search compares
+// magnitudes rounded to FP32 (ties: smallest row), the unblocked one in FP64.
 #include "common.h"
 #include "extract.h"
 
@@ -87,133 +89,154 @@ __global__ void gj_elim_kernel(double2* __restrict__ A, int n, int k, const doub
 // ---- blocked form (n <= kPanT: one row per thread of the panel workgroup)
 constexpr int kPanT = 1024;       // threads of the panel workgroup
 constexpr int kMaxPan = 8;        // columns per panel
-constexpr int kPanLds = 8192;     // complex values of the LDS panel (128 KB)
 constexpr int kBlockedMinN = 64;
 constexpr int kUpdRows = 4;       // rows per thread of the rank-nb update
 
-// Steps k0 .. k0+NB-1 of the elimination.  Panel columns, held column by
-// column in LDS, take the steps in the order and with the arithmetic of the
-// unblocked kernels; thread i owns row i and keeps its multipliers L[c][i]
-// (A[i][k] before the elimination of step c, 0 at i = k) in registers, so a
-// row interchange swaps them between two threads through LDS.  The scaled
-// pivot row is written by its owner after the step's last barrier (no later
-// step of the panel reads it before then).  At the end: the panel columns,
-// L, piv and 1/pivot go to memory, and every other column j takes the panel's
-// row interchanges and its pivot rows (row k scaled, then eliminated from the
-// other pivot rows); RK[c][j] keeps row k0+c as it is right after its scaling,
-// the value the remaining rows are eliminated with (gj_update_kernel).
+// Wave-wide maximum of a 64-bit key through DPP lane permutations (pairs,
+// quads, eight, sixteen lanes) and the four row results read out of lanes 0,
+// 16, 32 and 48.  Called by all 64 lanes.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_max_step(uint64_t key) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)key, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(key >> 32), CTRL, 0xF, 0xF, false);
+    const uint64_t o = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    return o > key ? o : key;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t key) {
+    key = dpp_max_step<0xB1>(key);    // quad_perm [1,0,3,2]
+    key = dpp_max_step<0x4E>(key);    // quad_perm [2,3,0,1]
+    key = dpp_max_step<0x141>(key);   // row_half_mirror
+    key = dpp_max_step<0x140>(key);   // row_mirror
+    uint64_t best = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, 16 * r);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), 16 * r);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        best = o > best ? o : best;
+    }
+    return best;
+}
+
+// Pivot key of row i: the FP32 bits of |v|^2 above the complement of i, so
+// that the largest key is the largest magnitude and, among equal magnitudes
+// (to FP32 rounding), the smallest row; rows out of the search have key 0.
+__device__ __forceinline__ uint64_t pivot_key(double m, int i) {
+    return ((uint64_t)__float_as_uint((float)m) << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
+}
+
+// Steps k0 .. k0+NB-1 of the elimination.  Thread i owns row i and keeps, in
+// registers, its NB panel values and its multipliers L[c][i] (A[i][k] before
+// the elimination of step c, 0 at i = k); the panel columns take the steps
+// with the arithmetic of the unblocked kernels.  Per step, between two
+// barriers: the pivot search, the interchange of two rows between their
+// owners and the pivot row broadcast, both through LDS; then every row's
+// update in its owner's registers.  At the end: the panel columns, L and piv
+// go to memory, and every other column j takes the panel's row interchanges
+// and its pivot rows (row k scaled, then eliminated from the other pivot
+// rows); RK[c][j] keeps row k0+c as it is right after its scaling, the value
+// the remaining rows are eliminated with (gj_update_kernel).
 template <int NB>
 __global__ __launch_bounds__(kPanT) void gj_panel_kernel(double2* __restrict__ A, int n, int k0,
                                                          double2* __restrict__ L, int* __restrict__ piv,
                                                          int* __restrict__ singular, double2* __restrict__ RK) {
-    __shared__ double2 pan[kPanLds];   // pan[c * n + i] = A[i][k0 + c]
-    __shared__ double rv[kPanT / 64];
-    __shared__ int ri[kPanT / 64];
+    __shared__ uint64_t wkey[kPanT / 64];
     __shared__ int pv[NB];
     __shared__ double2 dv[NB];
-    __shared__ double2 xl[2][NB];      // multipliers of the two interchanged rows
-    __shared__ double2 lp[NB][NB];     // lp[c][q] = L[c][k0 + q]
+    __shared__ double2 bcast[NB];              // the pivot row of the step, unscaled
+    __shared__ double2 xk[2 * NB];             // old row k: values and multipliers
+    __shared__ double2 xpl[NB];                // multipliers of old row p
+    __shared__ double2 lp[NB][NB];             // lp[c][q] = L[c][k0 + q]
     __shared__ int psrc[NB], exd[NB], exs[NB], nex;
     const int tid = threadIdx.x;
     const int i = tid;
     const bool own = i < n;
-    for (int t = tid; t < n * NB; t += kPanT) pan[(t % NB) * n + t / NB] = A[(int64_t)(t / NB) * n + k0 + t % NB];
-    __syncthreads();
-    double2 lreg[NB], rk[NB];
+    double2 rowv[NB], lreg[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) lreg[c] = rk[c] = make_double2(0, 0);
-    bool pend = false;
+    for (int j = 0; j < NB; ++j) {
+        rowv[j] = own ? A[(int64_t)i * n + k0 + j] : make_double2(0, 0);
+        lreg[j] = make_double2(0, 0);
+    }
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         const int k = k0 + c;
-        {
-            if (pend) {
+        uint64_t key = 0;
+        if (own && i >= k) {
+            const double m = rowv[c].x * rowv[c].x + rowv[c].y * rowv[c].y;
+            key = pivot_key(m, i);
+        }
+        key = wave_max_u64(key);
+        if ((tid & 63) == 0) wkey[tid >> 6] = key;
+        __syncthreads();
+        uint64_t kk[kPanT / 64];
 #pragma unroll
-                for (int j = 0; j < NB; ++j)
-                    pan[j * n + i] = rk[j];
-                pend = false;
-            }
-            double best = -1.0;
-            int bi = n;
-            if (own && i >= k) {
-                const double2 v = pan[c * n + i];
-                best = v.x * v.x + v.y * v.y;
-                bi = i;
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off);
-                const int oi = __shfl_xor(bi, off);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-            }
-            if ((tid & 63) == 0) { rv[tid >> 6] = best; ri[tid >> 6] = bi; }
-            __syncthreads();
-            double pb[kPanT / 64];
-            int pi[kPanT / 64];
+        for (int w = 0; w < kPanT / 64; ++w) kk[w] = wkey[w];
+        uint64_t best = 0;
 #pragma unroll
-            for (int w = 0; w < kPanT / 64; ++w) { pb[w] = rv[w]; pi[w] = ri[w]; }
-            double bb = pb[0];
-            int p = pi[0];
+        for (int w = 0; w < kPanT / 64; ++w) best = kk[w] > best ? kk[w] : best;
+        const int p = (int)(0xFFFFFFFFu - (uint32_t)best);
+        const bool valid = best != 0 && p >= k && p < n;
+        if (tid == 0) {
+            pv[c] = valid ? p : n;
+            if (!valid || !(__uint_as_float((uint32_t)(best >> 32)) > 0.0f)) singular[0] = 1;
+        }
+        const int pr = valid ? p : k;          // the row that becomes the pivot row
+        if (own && i == pr)
 #pragma unroll
-            for (int w = 1; w < kPanT / 64; ++w) {
-                const bool take = pb[w] > bb || (pb[w] == bb && pi[w] < p);
-                bb = take ? pb[w] : bb;
-                p = take ? pi[w] : p;
-            }
-            if (tid == 0) {
-                pv[c] = p;
-                if (!(bb > 0.0)) singular[0] = 1;
-            }
-            const bool swp = p != k && p < n;
-            if (swp) {
-                if (tid < NB) {
-                    const double2 t = pan[tid * n + k];
-                    pan[tid * n + k] = pan[tid * n + p];
-                    pan[tid * n + p] = t;
-                }
-                if (i == k || i == p)
+            for (int j = 0; j < NB; ++j) bcast[j] = rowv[j];
+        if (pr != k) {
+            if (own && i == k)
 #pragma unroll
-                    for (int q = 0; q < NB; ++q) xl[i == k ? 0 : 1][q] = lreg[q];
-            }
-            __syncthreads();
-            if (swp && (i == k || i == p))
+                for (int j = 0; j < NB; ++j) { xk[j] = rowv[j]; xk[NB + j] = lreg[j]; }
+            if (own && i == pr)
 #pragma unroll
-                for (int q = 0; q < NB; ++q) lreg[q] = xl[i == k ? 1 : 0][q];
-            const double2 d = pan[c * n + k];
-            const double den = d.x * d.x + d.y * d.y;
-            const double2 di = den > 0.0 ? make_double2(d.x / den, -d.y / den) : make_double2(0, 0);
+                for (int j = 0; j < NB; ++j) xpl[j] = lreg[j];
+        }
+        __syncthreads();
+        double2 prow[NB];
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
-                rk[j] = cmul((j == c) ? make_double2(1.0, 0.0) : pan[j * n + k], di);
-            if (tid == 0) dv[c] = di;
-            if (own) {
-                if (i == k) {
-                    lreg[c] = make_double2(0, 0);
-                    pend = true;
-                } else {
-                    const double2 l = pan[c * n + i];
-                    lreg[c] = l;
+        for (int j = 0; j < NB; ++j) prow[j] = bcast[j];
+        if (pr != k) {
+            if (own && i == k)
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) {
-                        const double2 base = (j == c) ? make_double2(0, 0) : pan[j * n + i];
-                        pan[j * n + i] = csub(base, cmul(l, rk[j]));
-                    }
+                for (int j = 0; j < NB; ++j) { rowv[j] = prow[j]; lreg[j] = xpl[j]; }
+            if (own && i == pr)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) { rowv[j] = xk[j]; lreg[j] = xk[NB + j]; }
+        }
+        const double2 d = prow[c];
+        const double den = d.x * d.x + d.y * d.y;
+        const double2 di = den > 0.0 ? make_double2(d.x / den, -d.y / den) : make_double2(0, 0);
+        double2 rk[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) rk[j] = cmul((j == c) ? make_double2(1.0, 0.0) : prow[j], di);
+        if (tid == 0) dv[c] = di;
+        if (own) {
+            if (i == k) {
+                lreg[c] = make_double2(0, 0);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) rowv[j] = rk[j];
+            } else {
+                const double2 l = rowv[c];
+                lreg[c] = l;
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const double2 base = (j == c) ? make_double2(0, 0) : rowv[j];
+                    rowv[j] = csub(base, cmul(l, rk[j]));
                 }
             }
-            __syncthreads();
         }
     }
-    if (pend)
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-            pan[j * n + i] = rk[j];
     if (own) {
 #pragma unroll
-        for (int c = 0; c < NB; ++c)
-            L[(int64_t)c * n + i] = lreg[c];
+        for (int j = 0; j < NB; ++j) A[(int64_t)i * n + k0 + j] = rowv[j];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) L[(int64_t)c * n + i] = lreg[c];
         if (i >= k0 && i < k0 + NB)
 #pragma unroll
             for (int c = 0; c < NB; ++c) lp[c][i - k0] = lreg[c];
     }
+    __syncthreads();
     if (tid < NB) piv[k0 + tid] = pv[tid];
     if (tid == 0) {
         // compose the interchanges on the rows they touch
@@ -246,7 +269,6 @@ __global__ __launch_bounds__(kPanT) void gj_panel_kernel(double2* __restrict__ A
         nex = ne;
     }
     __syncthreads();
-    for (int t = tid; t < n * NB; t += kPanT) A[(int64_t)(t / NB) * n + k0 + t % NB] = pan[(t % NB) * n + t / NB];
     // the other columns: row interchanges (all sources read before any row is
     // written), then the pivot rows
     const int j = tid;
@@ -388,8 +410,8 @@ void launch_panel(double2* A, int n, int k0, double2* L, int* piv, int* flag, do
 // the blocked form also uses out (which must not overlap A) until the end.
 void gj_inverse(double2* A, double2* out, int n, double2* colbuf, int* piv, int* flag, hipStream_t s) {
     MBT_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-    const int nb = n > 0 ? std::min(kMaxPan, kPanLds / n) : 0;
-    if (n >= kBlockedMinN && n <= kPanT && nb >= 2) {
+    const int nb = kMaxPan;
+    if (n >= kBlockedMinN && n <= kPanT) {
         // out: L (nb x n), RK (nb x n); n >= 64 leaves room
         double2* L = out;
         double2* RK = out + (size_t)nb * n;
