@@ -57,3 +57,13 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(mbt.mbt_lattice) == 24
     assert ctypes.sizeof(mbt.mbt_solve_opts) == 56
     assert ctypes.sizeof(mbt.mbt_stats) == 72
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No fallback: with the HIP library absent every entry point raises."""
+    monkeypatch.setattr(mbt, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libmbt.so"))
+    monkeypatch.setattr(mbt, "_lib", None)
+    with pytest.raises(RuntimeError):
+        mbt.lib()
+    with pytest.raises(RuntimeError):
+        mbt.mbt_ctx_create(0)
