@@ -162,3 +162,24 @@ def test_request_validation(ctx, cfg1):
         assert r["status"] == mbt.MBT_OK and r["nscan"] == 0 and r["Zp"].shape == (1, 6, 6)
     finally:
         mbt.mbt_server_destroy(srv)
+
+
+def test_unconverged_request_returns_its_last_iterate(ctx, cfg1, cfg1_oracle):
+    """A request that cannot meet its tolerance within its cycle limit ends
+    MBT_ENOCONV with finite outputs, and the server goes on serving."""
+    from paper_2608_17844_amd import mbt
+    srv = mbt.mbt_server_create(ctx, 2)
+    try:
+        tight = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=2, max_cycles=1)
+        _say("serving: request limited to one GMRES(2) cycle")
+        r = mbt.mbt_server_wait(srv, _submit(mbt, srv, cfg1.dipole, cfg1.lattice, [1.0], cfg1.theta, cfg1.phi,
+                                             tight))
+        assert r["status"] == mbt.MBT_ENOCONV
+        assert np.all(np.isfinite(r["Zp"])) and np.all(np.isfinite(r["Gamma"]))
+        assert int(np.max(r["iters_max"])) == 2
+        ok = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK)
+        r2 = mbt.mbt_server_wait(srv, _submit(mbt, srv, cfg1.dipole, cfg1.lattice, [1.0], cfg1.theta, cfg1.phi, ok))
+        assert r2["status"] == mbt.MBT_OK
+        assert _rel(r2["Zp"][0], cfg1_oracle.Zp) <= 1e-9
+    finally:
+        mbt.mbt_server_destroy(srv)
