@@ -112,6 +112,15 @@ typedef struct {
  * at most restart * max_cycles iterations.  Keeps four work vectors instead of
  * a Krylov basis. */
 #define MBT_FLAG_PCG 8
+/* mbt_solve_opts.flags: solve Z I = V by conjugate orthogonal conjugate
+ * gradients (COCG: CG with the bilinear form x^T y, for complex symmetric
+ * systems; van der Vorst and Melissen, 1990) with the element-block
+ * preconditioner P_K (pc must be MBT_PC_ELEMENT_BLOCK; Z and P_K are complex
+ * symmetric by Galerkin reciprocity), stopping when ||V - Z I|| <= tol ||V||
+ * (inner_tol in the reduced-precision inner solves); at most
+ * restart * max_cycles iterations.  One operator application per iteration
+ * and four work vectors instead of a Krylov basis.  Not in the paper. */
+#define MBT_FLAG_COCG 16
 
 typedef struct {
     int32_t nrhs;             /* RHS solved */

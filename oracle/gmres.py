@@ -15,6 +15,9 @@ PCG (Sec. II-C, the paper's own solver): conjugate gradients on the normal
 equations Z^H Z I = Z^H V with the preconditioner P_A, stopped on the relative
 residual of the split system of eq. (precond).
 
+COCG (not in the paper; van der Vorst and Melissen, 1990): CG with the bilinear
+form on the complex symmetric Z itself, preconditioned by the symmetric P_K.
+
 GMRES(m) (the solver of the "new M1" configuration; the paper relies on
 MATLAB's implementation and states none of its details, so this reading fixes
 them): x0 = 0, Arnoldi with classical Gram-Schmidt applied twice (CGS2),
@@ -357,6 +360,69 @@ def pcg_all(Z: np.ndarray, lat, dip, V: np.ndarray, tol: float = 1e-10, maxit: i
     results = []
     for j in range(V.shape[1]):
         r = pcg(lambda v: ZH @ (Z @ v), lambda v: pa_apply(f, v, M), B[:, j], tol, maxit)
+        I[:, j] = r.x
+        results.append(r)
+    return I, results
+
+
+# --------------------------------------------------------------------------- COCG
+
+@dataclass
+class COCGResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    relres: List[float] = field(default_factory=list)   # ||r|| / ||b|| after each iteration
+
+
+def cocg(apply_A: Callable[[np.ndarray], np.ndarray], apply_Minv: Callable[[np.ndarray], np.ndarray],
+         b: np.ndarray, tol: float = 1e-10, maxit: int = 20000) -> COCGResult:
+    """Conjugate orthogonal conjugate gradients (van der Vorst and Melissen,
+    IEEE Trans. Magn. 26, 1990) for A x = b with A complex symmetric (A = A^T)
+    and a complex symmetric preconditioner M (M^{-1} applied by apply_Minv).
+
+    Not part of the paper: an alternative Krylov solver for the symmetric MoM
+    matrix.  It is preconditioned CG with the bilinear form u^T v in place of
+    u^H v (for real symmetric positive definite A it is CG itself); x0 = 0,
+    stop when ||r|| <= tol ||b||.
+    """
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = apply_Minv(r)
+    p = z.copy()
+    rho = r @ z                      # bilinear: no conjugation
+    bn = np.linalg.norm(b)
+    res = COCGResult(x=x, iters=0, converged=(bn == 0.0))
+    if res.converged:
+        return res
+    for k in range(1, maxit + 1):
+        q = apply_A(p)
+        alpha = rho / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        z = apply_Minv(r)
+        rho_new = r @ z
+        res.iters = k
+        rel = np.linalg.norm(r) / bn
+        res.relres.append(rel)
+        if rel <= tol:
+            res.converged = True
+            break
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    res.x = x
+    return res
+
+
+def cocg_all(Z: np.ndarray, lat, dip, V: np.ndarray, tol: float = 1e-10, maxit: int = 20000):
+    """COCG on Z I = V with the element-block preconditioner P_K for every
+    column of V; returns (I, per-RHS results)."""
+    M = dip.nbases
+    f = pk_factors(Z, lat, dip)
+    I = np.zeros_like(V)
+    results = []
+    for j in range(V.shape[1]):
+        r = cocg(lambda v: Z @ v, lambda v: pk_apply(f, v, M), V[:, j], tol, maxit)
         I[:, j] = r.x
         results.append(r)
     return I, results

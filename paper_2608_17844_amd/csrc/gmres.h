@@ -72,6 +72,14 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
 // stop on sqrt(r^H P^{-1} r / b^H P^{-1} b) <= tol per RHS (the residual of the
 // split system P^{-1/2} N P^{-H/2} w = P^{-1/2} b).  work holds 4 N x R vectors
 // of type TB; at most maxit iterations.  cycles is 1, matvecs counts Z and Z^H.
+// Batched COCG on complex symmetric Z with a complex symmetric preconditioner
+// (x = 0 start, stop at ||r|| <= tol ||b||); work: four N x R vectors of TB.
+size_t cocg_state_bytes(int64_t N, int R);
+template <typename TB>
+GmresResult cocg_batched(const std::function<void(const TB*, TB*)>& applyZ,
+                         const std::function<void(const TB*, TB*)>& applyMinv, const TB* b, double2* x, TB* work,
+                         int64_t N, int R, double tol, int maxit, int* host_count, DevArena& arena, hipStream_t s);
+
 size_t pcg_state_bytes(int64_t N, int R);
 template <typename TB>
 GmresResult pcg_batched(const std::function<void(const TB*, TB*)>& applyN,

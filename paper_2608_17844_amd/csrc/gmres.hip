@@ -1481,6 +1481,214 @@ GmresResult pcg_batched(const std::function<void(const TB*, TB*)>& applyN,
     return res;
 }
 
+// ------------------------------------------------------------------ batched COCG
+// Conjugate orthogonal conjugate gradients (van der Vorst and Melissen, 1990)
+// on Z x = b for complex symmetric Z with a complex symmetric preconditioner M
+// applied as M^{-1}: the CG recurrences with the bilinear form a^T b in place
+// of a^H b.  One operator application and one preconditioner application per
+// step, no Krylov basis.  Stop test: ||r|| <= tol ||b||.  The element-block
+// P_K is symmetric (Galerkin self block), so M = P_K keeps the recurrence
+// valid.  One independent recurrence per RHS column, FP64 coefficients.
+namespace {
+
+// partial[chunk][v][r]: v = 0: sum a b (bilinear); NORM: v = 1: sum |a|^2
+template <typename TB, bool NORM>
+__global__ void cocg_dot_kernel(const TB* __restrict__ a, const TB* __restrict__ b, int64_t N, int R,
+                                int64_t rows_per_chunk, double2* __restrict__ partial) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t chunk = blockIdx.y;
+    if (r >= R) return;
+    const int64_t n0 = chunk * rows_per_chunk, n1 = min(N, n0 + rows_per_chunk);
+    double2 ab = make_double2(0, 0);
+    double aa = 0.0;
+    for (int64_t n = n0; n < n1; ++n) {
+        const double2 av = ld2(a + n * R + r);
+        ab = cfma(ab, av, ld2(b + n * R + r));
+        if (NORM) aa = fma(av.y, av.y, fma(av.x, av.x, aa));
+    }
+    constexpr int nv = NORM ? 2 : 1;
+    partial[(chunk * nv) * R + r] = ab;
+    if (NORM) partial[(chunk * nv + 1) * R + r] = make_double2(aa, 0.0);
+}
+
+struct CocgState {
+    double tol;
+    double2 *rho, *alpha, *beta;
+    double* bnorm2;
+    int *active, *conv, *flag, *iters;
+};
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// red = [r^T z, |r|^2] of the initial residual r = b
+__global__ void cocg_init_kernel(CocgState st, const double2* __restrict__ red, int R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const double2 rho = red[r];
+    const double bb = red[R + r].x;
+    st.rho[r] = rho;
+    st.bnorm2[r] = bb;
+    st.iters[r] = 0;
+    st.flag[r] = !(bb == bb) || isinf(bb) || !(rho.x == rho.x) || !(rho.y == rho.y);
+    st.conv[r] = !st.flag[r] && bb == 0.0;
+    st.active[r] = !st.flag[r] && !st.conv[r];
+    st.alpha[r] = make_double2(0, 0);
+    st.beta[r] = make_double2(0, 0);
+}
+
+// alpha = rho / p^T q for the RHS still iterating (a vanishing p^T q is a breakdown)
+__global__ void cocg_alpha_kernel(CocgState st, const double2* __restrict__ pq, int R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double2 a = make_double2(0, 0);
+    if (st.active[r]) {
+        a = cdiv(st.rho[r], pq[r]);
+        if (!(a.x == a.x) || !(a.y == a.y) || isinf(a.x) || isinf(a.y)) {
+            st.flag[r] = 1;
+            st.active[r] = 0;
+            a = make_double2(0, 0);
+        }
+    }
+    st.alpha[r] = a;
+}
+
+// x += alpha p (x in FP64), r -= alpha q
+template <typename TB>
+__global__ void cocg_xr_kernel(double2* __restrict__ x, TB* __restrict__ rv, const TB* __restrict__ p,
+                               const TB* __restrict__ q, const double2* __restrict__ alpha, int64_t NR, int R) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NR; t += (int64_t)gridDim.x * blockDim.x) {
+        const double2 a = alpha[t % R];
+        const double2 na = make_double2(-a.x, -a.y);
+        x[t] = cfma(x[t], a, ld2(p + t));
+        st2(rv + t, cfma(ld2(rv + t), na, ld2(q + t)));
+    }
+}
+
+// red = [r^T z, |r|^2]: stop test on ||r|| / ||b||, then beta = rho_new / rho
+__global__ void cocg_beta_kernel(CocgState st, const double2* __restrict__ red, int R) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double2 b = make_double2(0, 0);
+    if (st.active[r]) {
+        const double2 rz = red[r];
+        const double rr = red[R + r].x;
+        st.iters[r] += 1;
+        if (!(rr == rr) || isinf(rr) || !(rz.x == rz.x) || !(rz.y == rz.y)) {
+            st.flag[r] = 1;
+            st.active[r] = 0;
+        } else if (sqrt(rr / st.bnorm2[r]) <= st.tol) {
+            st.conv[r] = 1;
+            st.active[r] = 0;
+        } else {
+            b = cdiv(rz, st.rho[r]);
+            st.rho[r] = rz;
+        }
+    }
+    st.beta[r] = b;
+}
+
+// p = z + beta p
+template <typename TB>
+__global__ void cocg_p_kernel(TB* __restrict__ p, const TB* __restrict__ z, const double2* __restrict__ beta,
+                              int64_t NR, int R) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NR; t += (int64_t)gridDim.x * blockDim.x)
+        st2(p + t, cfma(ld2(z + t), beta[t % R], ld2(p + t)));
+}
+
+template <typename TB, bool NORM>
+void cocg_dot(const TB* a, const TB* b, int64_t N, int R, double2* partial, double2* out, hipStream_t s) {
+    const int64_t rpc = gmres_rows_per_chunk(N);
+    const int nchunk = gmres_nchunk(N);
+    hipLaunchKernelGGL((cocg_dot_kernel<TB, NORM>), dim3((R + 63) / 64, nchunk), dim3(64), 0, s, a, b, N, R, rpc,
+                       partial);
+    MBT_LAUNCH_CHECK();
+    launch_reduce_partials(partial, nchunk, NORM ? 2 : 1, R, out, s);
+}
+
+}  // namespace
+
+size_t cocg_state_bytes(int64_t N, int R) {
+    return 2 * sizeof(double2) * (size_t)gmres_nchunk(N) * R + 2 * sizeof(double2) * (size_t)R +
+           3 * sizeof(double2) * (size_t)R + sizeof(double) * (size_t)R + 4 * sizeof(int) * (size_t)R + 16 * 256;
+}
+
+template <typename TB>
+GmresResult cocg_batched(const std::function<void(const TB*, TB*)>& applyZ,
+                         const std::function<void(const TB*, TB*)>& applyMinv, const TB* b, double2* x, TB* work,
+                         int64_t N, int R, double tol, int maxit, int* host_count, DevArena& arena, hipStream_t s) {
+    const size_t mark = arena.off;
+    const int64_t NR = N * R;
+    TB* rv = work;
+    TB* z = work + NR;
+    TB* p = work + 2 * NR;
+    TB* q = work + 3 * NR;
+    CocgState st;
+    st.tol = tol;
+    st.rho = arena.get<double2>(R);
+    st.alpha = arena.get<double2>(R);
+    st.beta = arena.get<double2>(R);
+    st.bnorm2 = arena.get<double>(R);
+    st.active = arena.get<int>(R);
+    st.conv = arena.get<int>(R);
+    st.flag = arena.get<int>(R);
+    st.iters = arena.get<int>(R);
+    double2* partial = arena.get<double2>(2 * (size_t)gmres_nchunk(N) * R);
+    double2* red = arena.get<double2>(2 * (size_t)R);
+    int* d_count = arena.get<int>(16);
+    const dim3 gR((R + 255) / 256), bR(256);
+    auto count_active = [&]() -> int {
+        hipLaunchKernelGGL(count_kernel, dim3(1), dim3(256), 0, s, st.active, R, d_count);
+        MBT_LAUNCH_CHECK();
+        MBT_HIP(hipMemcpyAsync(host_count, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+        MBT_HIP(hipStreamSynchronize(s));
+        return *host_count;
+    };
+    GmresResult res;
+    // x = 0, r = b, z = M^{-1} r, p = z, rho = r^T z
+    hipLaunchKernelGGL(zero_kernel, dim3(ew_grid(NR)), dim3(256), 0, s, x, NR);
+    hipLaunchKernelGGL((copy_kernel<TB>), dim3(ew_grid(NR)), dim3(256), 0, s, b, rv, NR);
+    MBT_LAUNCH_CHECK();
+    applyMinv(rv, z);
+    hipLaunchKernelGGL((copy_kernel<TB>), dim3(ew_grid(NR)), dim3(256), 0, s, z, p, NR);
+    MBT_LAUNCH_CHECK();
+    cocg_dot<TB, true>(rv, z, N, R, partial, red, s);
+    hipLaunchKernelGGL(cocg_init_kernel, gR, bR, 0, s, st, red, R);
+    MBT_LAUNCH_CHECK();
+    res.cycles = 1;
+    for (int it = 0; it < maxit && count_active() > 0; ++it) {
+        applyZ(p, q);
+        cocg_dot<TB, false>(p, q, N, R, partial, red, s);
+        hipLaunchKernelGGL(cocg_alpha_kernel, gR, bR, 0, s, st, red, R);
+        hipLaunchKernelGGL((cocg_xr_kernel<TB>), dim3(ew_grid(NR)), dim3(256), 0, s, x, rv, p, q, st.alpha, NR, R);
+        MBT_LAUNCH_CHECK();
+        applyMinv(rv, z);
+        cocg_dot<TB, true>(rv, z, N, R, partial, red, s);
+        hipLaunchKernelGGL(cocg_beta_kernel, gR, bR, 0, s, st, red, R);
+        hipLaunchKernelGGL((cocg_p_kernel<TB>), dim3(ew_grid(NR)), dim3(256), 0, s, p, z, st.beta, NR, R);
+        MBT_LAUNCH_CHECK();
+        res.matvecs += 1;
+    }
+    res.iters.assign(R, 0);
+    res.conv.assign(R, 0);
+    res.flag.assign(R, 0);
+    MBT_HIP(hipMemcpyAsync(res.iters.data(), st.iters, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipMemcpyAsync(res.conv.data(), st.conv, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipMemcpyAsync(res.flag.data(), st.flag, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipStreamSynchronize(s));
+    arena.off = mark;
+    return res;
+}
+
+template GmresResult cocg_batched<double2>(const std::function<void(const double2*, double2*)>&,
+                                           const std::function<void(const double2*, double2*)>&, const double2*,
+                                           double2*, double2*, int64_t, int, double, int, int*, DevArena&, hipStream_t);
+template GmresResult cocg_batched<float2>(const std::function<void(const float2*, float2*)>&,
+                                          const std::function<void(const float2*, float2*)>&, const float2*, double2*,
+                                          float2*, int64_t, int, double, int, int*, DevArena&, hipStream_t);
+
 template GmresResult pcg_batched<double2>(const std::function<void(const double2*, double2*)>&,
                                           const std::function<void(const double2*, double2*)>&, const double2*,
                                           double2*, double2*, int64_t, int, double, int, int*, DevArena&, hipStream_t);

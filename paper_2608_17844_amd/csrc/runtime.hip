@@ -134,10 +134,14 @@ void validate_opts(const mbt_solve_opts& o) {
     MBT_REQUIRE(o.max_cycles >= 1, "max_cycles must be >= 1");
     MBT_REQUIRE(o.prec == MBT_FP64 || (o.refine_max >= 1 && o.refine_tol > 0), "refinement options invalid");
     MBT_REQUIRE(o.rhs_chunk >= 0, "rhs_chunk must be >= 0");
-    MBT_REQUIRE((o.flags & ~(MBT_FLAG_NO_CACHE | MBT_FLAG_CGS2 | MBT_FLAG_FP32_BASIS | MBT_FLAG_PCG)) == 0,
+    MBT_REQUIRE((o.flags & ~(MBT_FLAG_NO_CACHE | MBT_FLAG_CGS2 | MBT_FLAG_FP32_BASIS | MBT_FLAG_PCG |
+                             MBT_FLAG_COCG)) == 0,
                 "unknown flags");
     MBT_REQUIRE(!(o.flags & MBT_FLAG_PCG) || o.pc == MBT_PC_NORMAL_EQ,
                 "PCG solves the normal equations: pc must be MBT_PC_NORMAL_EQ");
+    MBT_REQUIRE(!(o.flags & MBT_FLAG_COCG) || o.pc == MBT_PC_ELEMENT_BLOCK,
+                "COCG takes the complex symmetric P_K: pc must be MBT_PC_ELEMENT_BLOCK");
+    MBT_REQUIRE(!((o.flags & MBT_FLAG_COCG) && (o.flags & MBT_FLAG_PCG)), "PCG and COCG exclude each other");
 }
 
 static double inner_tol(const mbt_solve_opts& o) {
@@ -491,7 +495,7 @@ size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o) {
     b += 2 * NR * 16;                                  // V, X
     b += NR * 16;                                      // FP64 residual
     if (o.prec != MBT_FP64) b += NR * 16 + NR * 8;     // d, r32
-    b += std::max(gmres_state_bytes(g.N, R, o.restart), pcg_state_bytes(g.N, R));
+    b += std::max(gmres_state_bytes(g.N, R, o.restart), std::max(pcg_state_bytes(g.N, R), cocg_state_bytes(g.N, R)));
     b += (size_t)R * 64 + ((size_t)g.N / 256 + 2) * R * 8 + (size_t)g.P * R * 16 + (1 << 20);
     return b;
 }
@@ -500,7 +504,7 @@ size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o) {
 // batch is solved with its last port repeated (the extra column is identical
 // and dropped).
 static bool pads_odd(const mbt_solve_opts& o) {
-    return o.prec != MBT_FP64 && !(o.flags & (MBT_FLAG_FP32_BASIS | MBT_FLAG_CGS2 | MBT_FLAG_PCG));
+    return o.prec != MBT_FP64 && !(o.flags & (MBT_FLAG_FP32_BASIS | MBT_FLAG_CGS2 | MBT_FLAG_PCG | MBT_FLAG_COCG));
 }
 int padded(int R, const mbt_solve_opts& o) { return R + ((pads_odd(o) && (R & 1)) ? 1 : 0); }
 
@@ -561,6 +565,7 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
     norms_host(V, g.N, R, arena, vn, s);
 
     const bool use_pcg = (o.flags & MBT_FLAG_PCG) != 0;
+    const bool use_cocg = (o.flags & MBT_FLAG_COCG) != 0;
     const int pcg_maxit = o.restart * o.max_cycles;
     if (o.prec == MBT_FP64) {
         double2* basis = arena.get<double2>((size_t)std::max(m + 1, 5) * NR);
@@ -579,6 +584,15 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
                 pinv<double>(ov, x, y);
             };
             gr = pcg_batched<double2>(fn, fp, b, X, basis, g.N, R, o.tol, pcg_maxit, wk.host_count, arena, s);
+        } else if (use_cocg) {
+            // Z I = V with M = P_K, both complex symmetric
+            std::function<void(const double2*, double2*)> fz = [&](const double2* x, double2* y) {
+                zmul<double>(ov, 0, x, y);
+            };
+            std::function<void(const double2*, double2*)> fm = [&](const double2* x, double2* y) {
+                pinv<double>(ov, x, y);
+            };
+            gr = cocg_batched<double2>(fz, fm, V, X, basis, g.N, R, o.tol, pcg_maxit, wk.host_count, arena, s);
         } else {
             apply_rhs<double>(ov, V, b);
             out.matvecs += o.pc == MBT_PC_NORMAL_EQ ? 1 : 0;
@@ -650,6 +664,14 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
                     pinv<float>(ov32, x, y);
                 };
                 gr = pcg_batched<float2>(fn, fp, b32, d, basis, g.N, R, prm.tol, pcg_maxit, wk.host_count, arena, s);
+            } else if (use_cocg) {
+                std::function<void(const float2*, float2*)> fz = [&](const float2* x, float2* y) {
+                    zmul<float>(ov32, 0, x, y);
+                };
+                std::function<void(const float2*, float2*)> fm = [&](const float2* x, float2* y) {
+                    pinv<float>(ov32, x, y);
+                };
+                gr = cocg_batched<float2>(fz, fm, r32, d, basis, g.N, R, prm.tol, pcg_maxit, wk.host_count, arena, s);
             } else {
                 apply_rhs<float>(ov32, r32, b32);
                 out.matvecs += o.pc == MBT_PC_NORMAL_EQ ? 1 : 0;

@@ -24,6 +24,7 @@ MBT_FLAG_NO_CACHE = 1
 MBT_FLAG_CGS2 = 2
 MBT_FLAG_FP32_BASIS = 4
 MBT_FLAG_PCG = 8
+MBT_FLAG_COCG = 16
 STATUS_NAMES = {0: "MBT_OK", -1: "MBT_EINVAL", -2: "MBT_ENOMEM", -3: "MBT_ENOCONV", -4: "MBT_EDEVICE",
                 -5: "MBT_EBUSY", -6: "MBT_EBREAKDOWN", -7: "MBT_ETIMEOUT"}
 

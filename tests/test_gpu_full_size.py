@@ -88,3 +88,15 @@ def test_mixed_path_full_size_in_bench_configuration(setup):
     _say({k: "%.2e" % v for k, v in e.items()}, out["stats"]["outer_steps"], out["stats"]["iters_max"])
     assert out["stats"]["nconverged"] == 1024 and out["stats"]["outer_steps"] <= 3
     assert e["zp_samples_elementwise"] <= 1e-6 and e["zp_diag"] <= 1e-6 and e["gamma_rel"] <= 1e-6
+
+
+def test_fp64_cocg_full_size(setup):
+    """COCG with P_K (FP64, ||r|| <= 1e-9 ||V||): Z_p entries and the center ARC
+    within 1e-6 relative of the oracle."""
+    mbt, ctx, arr, w, ref = setup
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK, tol=1e-9, flags=mbt.MBT_FLAG_COCG)
+    out = mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
+    e = _errors(out, ref)
+    _say({k: "%.2e" % v for k, v in e.items()}, out["stats"]["iters_max"])
+    assert out["stats"]["nconverged"] == 1024
+    assert e["zp_samples_elementwise"] <= 1e-6 and e["zp_diag"] <= 1e-6 and e["gamma_rel"] <= 1e-6

@@ -462,3 +462,61 @@ def test_pcg_normal_equations_reach_the_lu_solution():
     assert np.linalg.norm(I - ref) <= 1e-8 * np.linalg.norm(ref)
     # the split-system residual falls monotonically only on average; it must reach tol within N steps
     assert max(r.iters for r in res) <= Z.shape[0]
+
+
+# ----------------------------------------------------------------- COCG (not in the paper)
+
+def test_cocg_is_cg_on_a_real_spd_system():
+    """COCG with the identity preconditioner on a real symmetric positive
+    definite system is textbook CG: the same iterates, step by step."""
+    rng = np.random.default_rng(5)
+    n = 40
+    Q = rng.standard_normal((n, n))
+    A = (Q @ Q.T + n * np.eye(n)).astype(complex)
+    b = rng.standard_normal(n).astype(complex)
+    r = og.cocg(lambda v: A @ v, lambda v: v.copy(), b, tol=1e-13, maxit=n)
+    ref = _plain_cg(A, b, r.iters)
+    assert r.converged
+    assert np.linalg.norm(r.x - ref[-1]) <= 1e-12 * np.linalg.norm(ref[-1])
+    assert np.linalg.norm(A @ r.x - b) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_cocg_uses_the_bilinear_form():
+    """On a complex symmetric, non-Hermitian system (a well-conditioned
+    Hermitian part plus a symmetric imaginary part) COCG reaches the solution
+    within n steps and its residuals are M^{-1}-orthogonal in the bilinear form
+    (r_i^T M^{-1} r_j = 0), which a conjugated inner product would not give."""
+    rng = np.random.default_rng(6)
+    n = 30
+    S = rng.standard_normal((n, n))
+    T = rng.standard_normal((n, n))
+    A = (S + S.T) / 4 + 6 * np.eye(n) + 1j * (T + T.T) / 4
+    assert np.allclose(A, A.T) and not np.allclose(A, A.conj().T)
+    d = 1.0 + rng.random(n)
+    Minv = lambda v: v / d
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    r = og.cocg(lambda v: A @ v, Minv, b, tol=1e-12, maxit=n)
+    assert r.converged and r.iters <= n
+    assert np.linalg.norm(r.x - np.linalg.solve(A, b)) <= 1e-10 * np.linalg.norm(r.x)
+    # residual sequence, recomputed from scratch with the same recurrence
+    x = np.zeros_like(b); rr = b.copy(); z = Minv(rr); p = z.copy(); rho = rr @ z
+    res = [rr.copy()]
+    for _ in range(6):
+        q = A @ p; a = rho / (p @ q); x = x + a * p; rr = rr - a * q; z = Minv(rr)
+        res.append(rr.copy()); rn = rr @ z; p = z + (rn / rho) * p; rho = rn
+    G = np.array([[ri @ Minv(rj) for rj in res] for ri in res])
+    off = np.abs(G - np.diag(np.diag(G))).max() / np.abs(np.diag(G)).max()
+    assert off <= 1e-10
+
+
+def test_cocg_with_pk_reaches_the_lu_solution(cfg1, cfg1_dense, cfg1_oracle):
+    """The MoM matrix and P_K are complex symmetric (Galerkin reciprocity), so
+    COCG applies; with tol 1e-12 it returns the LU currents."""
+    lat, dip = cfg1.lattice, cfg1.dipole
+    Z = cfg1_dense
+    assert np.linalg.norm(Z - Z.T) <= 1e-13 * np.linalg.norm(Z)
+    V = mom.excitation(lat, dip)
+    I, res = og.cocg_all(Z, lat, dip, V[:, [0, 12, 24]], tol=1e-12)
+    assert all(r.converged for r in res)
+    ref = mom.solve_lu(Z, V[:, [0, 12, 24]])
+    assert np.linalg.norm(I - ref) / np.linalg.norm(ref) <= 1e-9
