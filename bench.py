@@ -9,9 +9,11 @@ active impedance / ARC at 64 scan angles -- with nothing reused across steps
 and per-bin block products in FP32 on the matrix cores (FP64 Arnoldi
 accumulation, FP64 iterative refinement); the plain FP64 path is timed beside
 it at the same accuracy target (Z_p entries and the center ARC within 1e-6
-relative of the FP64 oracle).  Prints one JSON line.
+relative of the FP64 oracle), and so is FP64 COCG with the element-block
+preconditioner, the fastest FP64 configuration.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]     headline 32x32 workload
+  python bench.py --solver pcg | cocg                      the same workload with PCG or COCG on both paths
   python bench.py --serve 40 [--load 0.8] [--slots 4]     Poisson serving stream
   python bench.py --sweep                                  21-frequency precision sweep
   python bench.py --blocks 5                               64x64 elements of 96 bases (synthetic blocks)
@@ -171,6 +173,12 @@ def headline(args):
         args.pc = "normal_eq"
         if args.kernel == "arnoldi_update_dots":
             args.kernel = "fft_inv_crop"
+    elif args.solver == "cocg":
+        # COCG on the complex symmetric Z with the symmetric P_K
+        pc, sflags = mbt.MBT_PC_ELEMENT_BLOCK, mbt.MBT_FLAG_COCG
+        args.pc = "element_block"
+        if args.kernel == "arnoldi_update_dots":
+            args.kernel = "fft_inv_crop"
     ctx = mbt.mbt_ctx_create(0)
     arr = mbt.mbt_array_create_dipole(ctx, w.dipole, w.lattice)
     P = w.lattice.nx * w.lattice.ny
@@ -196,6 +204,18 @@ def headline(args):
                     "errors": err64, "iters_max": out64["stats"]["iters_max"],
                     "matvecs": out64["stats"]["matvecs"]}
             log("fp64: %.3f s/step  %.1f solves/s  err %s" % (t64 / args.steps, fp64["value"], err64))
+        fp64_cocg = None
+        if not args.no_fp64 and args.solver == "gmres":
+            # the fastest FP64 configuration measured here: COCG with P_K, ||r|| <= tol ||V||
+            oc = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK, tol=args.fp64_tol,
+                                      flags=mbt.MBT_FLAG_NO_CACHE | mbt.MBT_FLAG_COCG)
+            log("fp64 COCG path (tol %g): warmup %d, steps %d" % (args.fp64_tol, args.warmup, args.steps))
+            tc, _, outc, _ = run_steps(mbt, ctx, arr, w, oc, args.steps, args.warmup)
+            fp64_cocg = {"value": P * args.steps / tc, "ms_per_step": 1e3 * tc / args.steps, "tol": args.fp64_tol,
+                         "solver": "cocg", "errors": zp_errors(outc, ref), "iters_max": outc["stats"]["iters_max"],
+                         "matvecs": outc["stats"]["matvecs"]}
+            log("fp64 cocg: %.3f s/step  %.1f solves/s  err %s" % (tc / args.steps, fp64_cocg["value"],
+                                                                      fp64_cocg["errors"]))
         kernels = {}
         if not args.no_kernel_table:
             log("per-kernel rooflines (one untimed step per kernel class)")
@@ -230,6 +250,8 @@ def headline(args):
                            "what": "per 1024-port request, whole hot path"},
             "fp64": fp64,
             "speedup_vs_fp64": (value / fp64["value"]) if fp64 else None,
+            "fp64_cocg": fp64_cocg,
+            "speedup_vs_fp64_cocg": (value / fp64_cocg["value"]) if fp64_cocg else None,
             "roofline": roofline,
             "kernels": kernels,
         }
@@ -528,8 +550,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--pc", choices=["element_block", "normal_eq"], default="element_block")
-    ap.add_argument("--solver", choices=["gmres", "pcg"], default="gmres",
-                    help="pcg: the paper's PCG on the normal equations with P_A (both paths)")
+    ap.add_argument("--solver", choices=["gmres", "pcg", "cocg"], default="gmres",
+                    help="pcg: the paper's PCG on the normal equations with P_A (both paths); "
+                         "cocg: COCG on Z with P_K (both paths)")
     ap.add_argument("--kernel", choices=sorted(KERNEL_CODES), default="arnoldi_update_dots")
     ap.add_argument("--restart", type=int, default=32, help="restart length of the mixed path's inner GMRES")
     ap.add_argument("--fp64-restart", type=int, default=50, help="restart length of the FP64 path (the workload's)")
