@@ -12,7 +12,7 @@ Toeplitz/FFT/Krylov machinery reaches up to rounding and iteration tolerance:
   is the thin-wire dipole of the benchmark workloads because the paper gives no
   fill formulas for its RWG elements);
 * the all-port multi-RHS system Z I = V with one unit delta-gap excitation per
-  port (Sec. II-C, eq. (eqProb), one feed per element, F = 1), solved by LAPACK
+  port (Sec. II-D, eq. (eqProb), one feed per element, F = 1), solved by LAPACK
   LU (zgetrf/zgetrs);
 * the port admittance from the port-basis currents, the open-circuit port
   impedance Z_p = Y_p^{-1} (eq. (passZ), read as the inverse of the
@@ -20,7 +20,7 @@ Toeplitz/FFT/Krylov machinery reaches up to rounding and iteration tolerance:
 * the scattering matrix S from eq. (S2Z) solved for S;
 * the active impedance of the center element (eqs. (actZ), (actZmat)) for
   phased port currents, its active reflection coefficient (eq. (ARC)) and the
-  wave-excited variant built from the phased S-sum of Sec. II-D.
+  wave-excited variant built from the phased S-sum of Sec. II-E.
 """
 from __future__ import annotations
 
@@ -206,14 +206,20 @@ def z_from_s(S: np.ndarray, z0: float = 50.0) -> np.ndarray:
 
 
 def scan_phases(lat, s: float, theta, phi) -> np.ndarray:
-    """Phased port excitation I_e = exp(+j k (x_e u + y_e v)), u = sin(th)cos(ph), v = sin(th)sin(ph).
+    """Progressive port phases that point the main beam at (theta, phi) (Sec. II-E:
+    the scan angle is the direction the excitation steers the beam to).
 
-    Shape (P, nscan)."""
+    The fill's kernel is e^{-jkR}/(4 pi R) (time factor e^{+j omega t}); far from
+    the array a source at rho_e then contributes with phase exp(+j k rhat.rho_e),
+    so the contributions add in phase at rhat(theta, phi) when
+    I_e = exp(-j k (x_e u + y_e v)), u = sin(th)cos(ph), v = sin(th)sin(ph).
+    The paper's printed exp(+j n psi) is the same excitation written with the
+    opposite time factor.  Shape (P, nscan)."""
     k = wavenumber(s)
     xy = element_xy(lat)
     u = np.sin(theta) * np.cos(phi)
     v = np.sin(theta) * np.sin(phi)
-    return np.exp(1j * k * (np.outer(xy[:, 0], u) + np.outer(xy[:, 1], v)))
+    return np.exp(-1j * k * (np.outer(xy[:, 0], u) + np.outer(xy[:, 1], v)))
 
 
 def active_impedance(Zp: np.ndarray, lat, s: float, theta, phi, center: Optional[int] = None) -> np.ndarray:
@@ -229,7 +235,7 @@ def arc(Za: np.ndarray, z0: float = 50.0) -> np.ndarray:
 
 
 def wave_arc(S: np.ndarray, lat, s: float, theta, phi, center: Optional[int] = None) -> np.ndarray:
-    """Phased S-sum of Sec. II-D: Gamma_wave,c = sum_e S_ce a_e / a_c with incident
+    """Phased S-sum of Sec. II-E: Gamma_wave,c = sum_e S_ce a_e / a_c with incident
     waves a_e carrying the same progressive phases as the port currents."""
     c = center_element(lat) if center is None else center
     a = scan_phases(lat, s, np.atleast_1d(theta), np.atleast_1d(phi))

@@ -4,10 +4,11 @@
 //   the short-circuit admittance that unit delta-gap excitations give;
 // * S = (Z_p - z0)(Z_p + z0)^{-1} = I - 2 z0 (Z_p + z0)^{-1}, eq. (S2Z) solved
 //   for S;
-// * the center element's active impedance for phased port currents
-//   I_j = exp(+j k (x_j u + y_j v)) (eqs. (actZ), (actZmat)), its ARC
+// * the center element's active impedance for port currents phased to steer
+//   the main beam at (theta, phi) (Sec. II-E), I_j = exp(-j k (x_j u + y_j v))
+//   under the e^{-jkR} kernel of the fill (eqs. (actZ), (actZmat)), its ARC
 //   (eq. (ARC)), and the wave-excited reflection coefficient, the phased S-sum
-//   of Sec. II-D.
+//   of Sec. II-E.
 //
 // The dense inverses use Gauss-Jordan elimination with partial pivoting.  For
 // 64 <= n <= 1024 it is blocked: one workgroup factors a panel of eight
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(256) void scan_kernel(const double2* __restrict__ Z
         const double xj = (j % nx) * dx, yj = (j / nx) * dy;
         double sn, cs;
         sincos(k * (xj * u + yj * v), &sn, &cs);
-        const double2 ph = make_double2(cs, sn);
+        const double2 ph = make_double2(cs, -sn);   // I_j = exp(-j k (x_j u + y_j v))
         az = cadd(az, cmul(Zp[(int64_t)j * P + c], ph));
         if (S) as = cadd(as, cmul(S[(int64_t)j * P + c], ph));
     }
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(256) void scan_kernel(const double2* __restrict__ Z
         const double xc = (c % nx) * dx, yc = (c / nx) * dy;
         double sn, cs;
         sincos(k * (xc * u + yc * v), &sn, &cs);
-        const double2 pc = make_double2(cs, -sn);   // 1 / I_c
+        const double2 pc = make_double2(cs, sn);    // 1 / I_c
         const double2 za = cmul(sz[0], pc);
         Za[sidx] = za;
         const double2 num = make_double2(za.x - z0, za.y), den = make_double2(za.x + z0, za.y);

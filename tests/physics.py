@@ -41,3 +41,23 @@ def radiated_power(lat, dip, s, I, eta=ETA_FREE_SPACE, nmu=128, nphi=128):
     integrand = (1.0 - mu[:, None] ** 2) * np.abs(Nz) ** 2
     total = np.sum(wmu[:, None] * integrand) * (2.0 * np.pi / nphi)
     return k ** 2 * eta / (32.0 * np.pi ** 2) * total
+
+
+def distant_field(lat, s, I, theta, phi, r=1.0e5):
+    """Array factor of port currents I (P,) evaluated by summing the fill's own
+    kernel exp(-j k R)/(4 pi R) over point sources at the element positions,
+    with R the exact distance to a point at range r in direction (theta, phi),
+    normalised by the single-source value at the origin.  No plane-wave
+    approximation: the sign of the progressive phase comes from the kernel."""
+    k = 2.0 * np.pi * s
+    iy, ix = np.divmod(np.arange(lat.nx * lat.ny), lat.nx)
+    xe, ye = ix * lat.dx, iy * lat.dy
+    theta = np.atleast_1d(theta)
+    phi = np.atleast_1d(phi)
+    px = r * np.sin(theta) * np.cos(phi)
+    py = r * np.sin(theta) * np.sin(phi)
+    pz = r * np.cos(theta)
+    R = np.sqrt((px[:, None] - xe[None, :]) ** 2 + (py[:, None] - ye[None, :]) ** 2 + pz[:, None] ** 2)
+    g = np.exp(-1j * k * R) / R
+    g0 = np.exp(-1j * k * r) / r
+    return (g @ np.asarray(I)) / g0

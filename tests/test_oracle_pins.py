@@ -9,7 +9,7 @@ from oracle import gmres as og
 from oracle import mom
 from paper_2608_17844_amd import workloads as W
 
-from physics import radiated_power
+from physics import distant_field, radiated_power
 
 
 # ----------------------------------------------------------------- quadrature rule
@@ -224,6 +224,61 @@ def test_scan_center_symmetry_odd_array(cfg1, cfg1_oracle):
     base = f(ph)
     for other in (ph + np.pi, np.pi / 2 - ph, np.pi - ph):
         assert np.max(np.abs(f(other) - base)) < 1e-11 * np.max(np.abs(base))
+
+
+@pytest.mark.parametrize("lat", [W.Lattice(4, 4, 0.5, 0.5), W.Lattice(6, 5, 0.5, 0.6)])
+def test_scan_phases_point_the_main_beam_even_arrays(lat):
+    """Sec. II-E: the scan angle is the direction the excitation steers the main
+    beam to.  On even arrays (no symmetry point at the center element) the field
+    of the phased currents, summed with the fill's own e^{-jkR} kernel at a
+    distant point, must peak at (theta0, phi0) and not at the mirror direction
+    (theta0, phi0 + pi) that the opposite phase sign gives."""
+    P = lat.nx * lat.ny
+    th = np.linspace(0.0, np.pi / 2, 91)
+    ph = np.linspace(0.0, 2 * np.pi, 181)[:-1]
+    TH, PH = [a.ravel() for a in np.meshgrid(th, ph, indexing="ij")]
+    for th0, ph0 in ((0.35, 0.5), (0.7, 2.2), (0.5, 4.0)):
+        I = mom.scan_phases(lat, 1.0, np.array([th0]), np.array([ph0]))[:, 0]
+        main = abs(distant_field(lat, 1.0, I, th0, ph0)[0])
+        mirror = abs(distant_field(lat, 1.0, I, th0, ph0 + np.pi)[0])
+        assert abs(main - P) < 1e-3 * P
+        assert mirror < 0.5 * P
+        grid = np.abs(distant_field(lat, 1.0, I, TH, PH))
+        assert grid.max() <= main * (1 + 1e-9)
+        i = int(np.argmax(grid))
+        u0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)])
+        u1 = np.array([np.sin(TH[i]) * np.cos(PH[i]), np.sin(TH[i]) * np.sin(PH[i]), np.cos(TH[i])])
+        assert np.arccos(min(1.0, u0 @ u1)) < np.deg2rad(3.0)
+
+
+def test_active_impedance_of_beam_steering_currents_even_array():
+    """Z_a,c and Gamma_wave,c at (theta0, phi0) equal eq. (actZ) and the phased
+    S-sum evaluated with the currents that make every element's contribution
+    arrive in phase at a distant point in that direction (phases read off the
+    fill's kernel e^{-jkR} with exact distances), on an even 6 x 4 array."""
+    lat = W.Lattice(6, 4, 0.5, 0.55)
+    dip = W.Dipole(0.5, 0.005, 7)
+    th0 = np.array([0.3, 0.6, 0.9])
+    ph0 = np.array([0.4, 2.0, 5.0])
+    r = mom.solve_array(lat, dip, 1.0, th0, ph0)
+    c = mom.center_element(lat)
+    k = 2 * np.pi
+    iy, ix = np.divmod(np.arange(lat.nx * lat.ny), lat.nx)
+    xe, ye = ix * lat.dx, iy * lat.dy
+    rr = 1.0e10
+    for i in range(th0.size):
+        p = rr * np.array([np.sin(th0[i]) * np.cos(ph0[i]), np.sin(th0[i]) * np.sin(ph0[i]), np.cos(th0[i])])
+        R = np.sqrt((p[0] - xe) ** 2 + (p[1] - ye) ** 2 + p[2] ** 2)
+        # R_e - R_c without cancellation: (R_e^2 - R_c^2) / (R_e + R_c)
+        dR2 = (xe ** 2 + ye ** 2) - (xe[c] ** 2 + ye[c] ** 2) - 2 * (p[0] * (xe - xe[c]) + p[1] * (ye - ye[c]))
+        I = np.exp(1j * k * dR2 / (R + R[c]))    # cancels each path's e^{-jkR} phase
+        za = (r.Zp[c, :] @ I) / I[c]
+        gw = (r.S[c, :] @ I) / I[c]
+        assert abs(r.Za[i] - za) < 1e-6 * abs(za)
+        assert abs(r.Gamma_wave[i] - gw) < 1e-6
+    # the mirror direction gives a different value on this even array
+    zm = mom.active_impedance(r.Zp, lat, 1.0, th0, ph0 + np.pi)
+    assert np.min(np.abs(zm - r.Za)) > 1e-3 * np.max(np.abs(r.Za))
 
 
 def test_wave_arc_consistent_with_impedance_form(cfg1, cfg1_oracle):
