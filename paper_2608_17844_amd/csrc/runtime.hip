@@ -191,12 +191,17 @@ static void build_32(OpData& op, Worker& wk) {
     convert<double2, float2>(op.tw.as<double2>(), op.tw32.as<float2>(), g.Px + g.Py, wk.stream);
     op.PkInv32.alloc(sizeof(float2) * MM);
     convert<double2, float2>(op.PkInv.as<double2>(), op.PkInv32.as<float2>(), MM, wk.stream);
-    if (op.has_pa) {
-        op.PaInv32.alloc(sizeof(float2) * g.P * MM);
-        convert<double2, float2>(op.PaInv.as<double2>(), op.PaInv32.as<float2>(), g.P * MM, wk.stream);
-    }
     MBT_HIP(hipStreamSynchronize(wk.stream));
     op.has32 = true;
+}
+
+// FP32 copy of the normal-equation preconditioner inverses (needs build_pa first).
+static void build_32_pa(OpData& op, Worker& wk) {
+    const Geom& g = op.g;
+    const int64_t MM = (int64_t)g.M * g.M;
+    op.PaInv32.alloc(sizeof(float2) * g.P * MM);
+    convert<double2, float2>(op.PaInv.as<double2>(), op.PaInv32.as<float2>(), g.P * MM, wk.stream);
+    MBT_HIP(hipStreamSynchronize(wk.stream));
 }
 
 // 16-bit copy of the block spectra, scaled by a power of two that puts the
@@ -309,15 +314,20 @@ std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const mbt_array* arr, double s, boo
             ctx->cache_bytes += op->bytes();
         }
     }
-    // extend under the cache lock so concurrent workers do not race on the same entry
-    if ((need_pa && !op->has_pa) || (need32 && (!op->has32 || (need_pa && !op->PaInv32.p))) ||
-        (fmt != kFmtNone && !op->Chat16[fmt].p)) {
+    // Extend under the cache lock.  Every piece is built only where it is still
+    // missing, into a buffer that did not exist before: other workers may be
+    // running kernels on the pieces that exist, so nothing already built is
+    // ever reallocated.  The flags and pointers are read under the same lock,
+    // after the builder's stream has synchronised.
+    {
         std::lock_guard<std::mutex> lk(ctx->cache_mu);
         const size_t before = op->bytes();
         if (need_pa && !op->has_pa) build_pa(*op, wk);
-        if (need32 && (!op->has32 || (op->has_pa && !op->PaInv32.p))) build_32(*op, wk);
+        if (need32 && !op->has32) build_32(*op, wk);
+        if (need32 && need_pa && !op->PaInv32.p) build_32_pa(*op, wk);
         if (fmt != kFmtNone && !op->Chat16[fmt].p) build_16(*op, fmt, wk);
-        ctx->cache_bytes += op->bytes() - before;
+        auto it = ctx->cache.find(key);
+        if (it != ctx->cache.end() && it->second == op) ctx->cache_bytes += op->bytes() - before;
     }
     // evict least recently used entries beyond the limit (entries in use stay alive through shared_ptr)
     {

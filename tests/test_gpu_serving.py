@@ -66,17 +66,18 @@ def test_served_request_matches_oracle_alone_and_in_mix(ctx, cfg1):
         others = [mbt.mbt_server_wait(srv, t) for t in tickets]
     finally:
         mbt.mbt_server_destroy(srv)
-    # the same request gives the same result alone and in the mix
+    # the same request gives bit-identical results alone and in the mix (every
+    # reduction runs in a fixed order that does not depend on what else runs)
     assert inmix["status"] == mbt.MBT_OK
     for key in ("Zp", "Za", "Gamma", "Gamma_wave"):
-        d = np.max(np.abs(inmix[key] - alone[key]))
-        assert d <= 1e-12 * max(1.0, np.max(np.abs(alone[key]))), (key, d)
-    # and both match the oracle at every frequency
+        assert np.array_equal(inmix[key], alone[key]), (key, np.max(np.abs(inmix[key] - alone[key])))
+    # and both match the oracle at every frequency (the ARC sums a row of Z_p
+    # with unit-modulus phases: 1e-8 relative to max(1, |Gamma|) at this size)
     for fi, s in enumerate(freqs):
         ref = mom.solve_array(cfg1.lattice, cfg1.dipole, s, cfg1.theta, cfg1.phi)
         assert _rel(alone["Zp"][fi], ref.Zp) <= 1e-9
-        assert np.max(np.abs(alone["Gamma"][fi] - ref.Gamma)) <= 1e-9
-        assert np.max(np.abs(alone["Gamma_wave"][fi] - ref.Gamma_wave)) <= 1e-9
+        assert np.max(np.abs(alone["Gamma"][fi] - ref.Gamma) / np.maximum(1.0, np.abs(ref.Gamma))) <= 1e-8
+        assert np.max(np.abs(alone["Gamma_wave"][fi] - ref.Gamma_wave)) <= 1e-8
     # every other request of the mix matches its own oracle
     for (dip, lat, fr, th, ph), res in zip(mix, others):
         assert res["status"] == mbt.MBT_OK
@@ -85,7 +86,7 @@ def test_served_request_matches_oracle_alone_and_in_mix(ctx, cfg1):
             e = _rel(res["Zp"][fi], ref.Zp)
             _say("  %dx%d m%d s=%.2f |dZp|=%.2e" % (lat.nx, lat.ny, dip.nbases, s, e))
             assert e <= 1e-9
-            assert np.max(np.abs(res["Gamma"][fi] - ref.Gamma)) <= 1e-9
+            assert np.max(np.abs(res["Gamma"][fi] - ref.Gamma) / np.maximum(1.0, np.abs(ref.Gamma))) <= 1e-8
     # requests submitted together ran concurrently
     spans = sorted((r["t_start"], r["t_done"]) for r in others + [inmix])
     assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
@@ -183,3 +184,35 @@ def test_unconverged_request_returns_its_last_iterate(ctx, cfg1, cfg1_oracle):
         assert _rel(r2["Zp"][0], cfg1_oracle.Zp) <= 1e-9
     finally:
         mbt.mbt_server_destroy(srv)
+
+
+def test_concurrent_requests_extending_one_cached_operator(ctx):
+    """Requests for the same array and frequency with different operator
+    needs (FP32 with P_K, FP32 with P_A, FP64 with P_A, FP16 products) in flight at once:
+    each extends the shared cached operator with the pieces it lacks while the
+    others run kernels on the pieces that exist; every result matches the
+    oracle."""
+    from paper_2608_17844_amd import mbt
+    lat, dip = W.Lattice(6, 5, 0.5, 0.5), W.Dipole(0.5, 0.005, 15)
+    s = 1.07
+    th, ph = W.scan_angles(5, seed=3)
+    ref = mom.solve_array(lat, dip, s, th, ph)
+    variants = [
+        ("fp32 P_K", mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, refine_tol=1e-11,
+                                           refine_max=6), 1e-9),
+        ("fp32 P_A", mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_NORMAL_EQ, refine_tol=1e-11,
+                                           refine_max=6), 1e-9),
+        ("fp64 P_A", mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_NORMAL_EQ, tol=1e-12), 1e-9),
+        ("fp16 P_K", mbt.mbt_default_opts(prec=mbt.MBT_FP16, pc=mbt.MBT_PC_ELEMENT_BLOCK, refine_tol=1e-11,
+                                           refine_max=8), 1e-9),
+    ]
+    srv = mbt.mbt_server_create(ctx, 4)
+    try:
+        tickets = [_submit(mbt, srv, dip, lat, [s], th, ph, o) for _, o, _ in variants]
+        results = [mbt.mbt_server_wait(srv, t) for t in tickets]
+    finally:
+        mbt.mbt_server_destroy(srv)
+    for (name, _, bound), res in zip(variants, results):
+        e = _rel(res["Zp"][0], ref.Zp)
+        _say("  %s: status %d |dZp|/|Zp| %.2e" % (name, res["status"], e))
+        assert e <= bound, (name, e)
