@@ -21,8 +21,12 @@ form on the complex symmetric Z itself, preconditioned by the symmetric P_K.
 GMRES(m) (the solver of the "new M1" configuration; the paper relies on
 MATLAB's implementation and states none of its details, so this reading fixes
 them): x0 = 0, Arnoldi with classical Gram-Schmidt applied twice (CGS2),
-complex Givens rotations, stop as soon as the least-squares residual
-|g_{j+1}| <= tol * ||b||, explicit residual recomputed at every restart.
+complex Givens rotations, stop a cycle as soon as the least-squares residual
+|g_{j+1}| <= tol * ||b||, explicit residual recomputed at every restart.  The
+verdict is taken on the explicit residual r = b - A x of the restart: converged
+when ||r|| <= tol ||b||, or ||r|| <= 2 tol ||b|| after a cycle whose
+least-squares residual met the tolerance (the two differ by rounding; a larger
+gap means the Arnoldi relation was lost, and the solve restarts from r).
 """
 from __future__ import annotations
 
@@ -72,17 +76,58 @@ def pa_apply(factors, x: np.ndarray, M: int) -> np.ndarray:
     return y
 
 
+def refined_inverse(B: np.ndarray) -> np.ndarray:
+    """Inverse of a small matrix in extended precision (numpy clongdouble, a
+    64-bit significand on x86): the FP64 inverse refined by three Newton-Schulz
+    steps X <- X (2 I - B X), each of which squares the residual I - B X."""
+    Bl = B.astype(np.clongdouble)
+    X = np.linalg.inv(B.astype(np.complex128)).astype(np.clongdouble)
+    E = np.eye(B.shape[0], dtype=np.clongdouble)
+    for _ in range(3):
+        X = X @ (2 * E - Bl @ X)
+    return X
+
+
+def block_apply(inv, x: np.ndarray, M: int) -> np.ndarray:
+    """y = blockdiag(inv) x with one M x M inverse per element."""
+    y = np.empty_like(x)
+    for e, X in enumerate(inv):
+        y[e * M:(e + 1) * M] = X @ x[e * M:(e + 1) * M]
+    return y
+
+
 class PreconditionedSystem:
     """The system GMRES runs on, for one of the two strategies.
 
     'element_block':  A = P_K^{-1} Z,        b = P_K^{-1} V
     'normal_eq':      A = P^{-1} Z^H Z,      b = P^{-1} Z^H V
+
+    extended=True runs the same system in numpy's extended precision
+    (clongdouble): Z as given, every product and preconditioner block formed
+    and applied with a 64-bit significand.  On the normal equations (condition
+    number squared) the step at which a Krylov recurrence crosses tol depends
+    on the arithmetic itself; the extended run stands in for exact arithmetic.
     """
 
-    def __init__(self, Z: np.ndarray, lat, dip, kind: str):
-        self.Z = Z
+    def __init__(self, Z: np.ndarray, lat, dip, kind: str, extended: bool = False):
         self.M = dip.nbases
         self.kind = kind
+        self.extended = extended
+        P = mom.n_elements(lat)
+        M = self.M
+        if extended:
+            Zl = Z.astype(np.clongdouble)
+            self.Z = Zl
+            if kind == "element_block":
+                inv = [refined_inverse(Zl[e * M:(e + 1) * M, e * M:(e + 1) * M]) for e in range(P)]
+            elif kind == "normal_eq":
+                inv = [refined_inverse(Zl[:, e * M:(e + 1) * M].conj().T @ Zl[:, e * M:(e + 1) * M])
+                       for e in range(P)]
+            else:
+                raise ValueError(kind)
+            self.pinv = lambda x: block_apply(inv, x, M)
+            return
+        self.Z = Z
         if kind == "element_block":
             self.f = pk_factors(Z, lat, dip)
             self.pinv = lambda x: pk_apply(self.f, x, self.M)
@@ -98,6 +143,7 @@ class PreconditionedSystem:
         return self.pinv(self.Z.conj().T @ (self.Z @ x))
 
     def rhs(self, v: np.ndarray) -> np.ndarray:
+        v = v.astype(self.Z.dtype)
         if self.kind == "element_block":
             return self.pinv(v)
         return self.pinv(self.Z.conj().T @ v)
@@ -130,7 +176,8 @@ def gmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, restart: i
           tol: float = 1e-10, max_cycles: int = 400) -> GmresResult:
     n = b.shape[0]
     m = restart
-    x = np.zeros(n, dtype=np.complex128)
+    ct = b.dtype                       # complex128, or clongdouble for the extended-precision run
+    x = np.zeros(n, dtype=ct)
     bnorm = np.linalg.norm(b)
     res = GmresResult(x, 0, False, 0)
     if bnorm == 0.0:
@@ -138,17 +185,20 @@ def gmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, restart: i
         return res
     r = b.copy()
     beta = np.linalg.norm(r)
-    for cycle in range(max_cycles):
+    candidate = False
+    for cycle in range(max_cycles + 1):
         res.restart_residuals.append(beta)
-        if beta <= tol * bnorm:
+        if _accept(beta, bnorm, tol, candidate):
             res.converged = True
             break
+        if cycle == max_cycles:
+            break
         res.cycles = cycle + 1
-        V = np.zeros((m + 1, n), dtype=np.complex128)
-        H = np.zeros((m + 1, m), dtype=np.complex128)
-        cs = np.zeros(m)
-        sn = np.zeros(m, dtype=np.complex128)
-        g = np.zeros(m + 1, dtype=np.complex128)
+        V = np.zeros((m + 1, n), dtype=ct)
+        H = np.zeros((m + 1, m), dtype=ct)
+        cs = np.zeros(m, dtype=bnorm.dtype)
+        sn = np.zeros(m, dtype=ct)
+        g = np.zeros(m + 1, dtype=ct)
         g[0] = beta
         V[0] = r / beta
         k = 0
@@ -180,15 +230,27 @@ def gmres(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, restart: i
             if abs(g[j + 1]) <= tol * bnorm or hn == 0.0:
                 break
             V[j + 1] = w / hn
-        y = sla.solve_triangular(H[:k, :k], g[:k], lower=False)
+        y = _back_substitute(H[:k, :k], g[:k])
         x = x + V[:k].T @ y
-        if abs(g[k]) <= tol * bnorm:
-            res.converged = True
-            break
+        candidate = abs(g[k]) <= tol * bnorm
         r = b - apply_A(x)
         beta = np.linalg.norm(r)
     res.x = x
     return res
+
+
+def _back_substitute(Rm: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """y = R^{-1} g for upper triangular R (k <= 63), in the dtype of R."""
+    k = g.shape[0]
+    y = np.zeros(k, dtype=Rm.dtype)
+    for i in range(k - 1, -1, -1):
+        y[i] = (g[i] - Rm[i, i + 1:k] @ y[i + 1:k]) / Rm[i, i]
+    return y
+
+
+def _accept(beta: float, bnorm: float, tol: float, candidate: bool) -> bool:
+    """Convergence verdict on the explicit residual of a restart."""
+    return beta <= tol * bnorm or (candidate and beta <= 2.0 * tol * bnorm)
 
 
 def _rotate_column(H, cs, sn, g, j):
@@ -220,7 +282,8 @@ def gmres_dcgs2(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, rest
     the stopping rule and x0 are the same as in gmres()."""
     n = b.shape[0]
     m = restart
-    x = np.zeros(n, dtype=np.complex128)
+    ct = b.dtype                       # complex128, or clongdouble for the extended-precision run
+    x = np.zeros(n, dtype=ct)
     bnorm = np.linalg.norm(b)
     res = GmresResult(x, 0, False, 0)
     if bnorm == 0.0:
@@ -228,18 +291,21 @@ def gmres_dcgs2(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, rest
         return res
     r = b.copy()
     beta = np.linalg.norm(r)
-    for cycle in range(max_cycles):
+    candidate = False
+    for cycle in range(max_cycles + 1):
         res.restart_residuals.append(beta)
-        if beta <= tol * bnorm:
+        if _accept(beta, bnorm, tol, candidate):
             res.converged = True
             break
+        if cycle == max_cycles:
+            break
         res.cycles = cycle + 1
-        V = np.zeros((m + 1, n), dtype=np.complex128)
-        Hraw = np.zeros((m + 1, m), dtype=np.complex128)    # unrotated Hessenberg
-        Hrot = np.zeros((m + 1, m), dtype=np.complex128)    # rotated copy (upper triangular part used)
-        cs = np.zeros(m)
-        sn = np.zeros(m, dtype=np.complex128)
-        g = np.zeros(m + 1, dtype=np.complex128)
+        V = np.zeros((m + 1, n), dtype=ct)
+        Hraw = np.zeros((m + 1, m), dtype=ct)    # unrotated Hessenberg
+        Hrot = np.zeros((m + 1, m), dtype=ct)    # rotated copy (upper triangular part used)
+        cs = np.zeros(m, dtype=bnorm.dtype)
+        sn = np.zeros(m, dtype=ct)
+        g = np.zeros(m + 1, dtype=ct)
         u = r / beta
         k = 0
         steps = 0
@@ -249,7 +315,10 @@ def gmres_dcgs2(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, rest
             Vf = V[:k]
             s = Vf.conj() @ u
             alpha = np.vdot(u, u).real
-            nu = np.sqrt(max(alpha - np.vdot(s, s).real, 0.0))
+            # nu^2 by Pythagoras: below 1e-12 alpha it has cancelled to rounding
+            # noise, the candidate lies in span(V) (breakdown, the cycle ends)
+            nu2 = alpha - np.vdot(s, s).real
+            nu = np.sqrt(nu2) if nu2 > 1e-12 * alpha else 0.0
             if k == 0:
                 g[0] = beta * nu
             else:
@@ -267,7 +336,7 @@ def gmres_dcgs2(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, rest
             bet = np.vdot(u, w)
             V[k] = (u - Vf.T @ s) / nu
             t = Hraw[:k + 1, :k] @ s
-            h = np.zeros(k + 1, dtype=np.complex128)
+            h = np.zeros(k + 1, dtype=ct)
             h[:k] = (z - t[:k]) / nu
             h[k] = ((bet - np.vdot(s, z)) / nu - t[k]) / nu
             c = t / nu + h
@@ -275,11 +344,9 @@ def gmres_dcgs2(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray, rest
             Hraw[:k + 1, k] = h
             av_norm = np.linalg.norm(u + V[:k + 1].T @ h)
             k += 1
-        y = sla.solve_triangular(Hrot[:steps, :steps], g[:steps], lower=False)
+        y = _back_substitute(Hrot[:steps, :steps], g[:steps])
         x = x + V[:steps].T @ y
-        if abs(g[steps]) <= tol * bnorm:
-            res.converged = True
-            break
+        candidate = abs(g[steps]) <= tol * bnorm
         r = b - apply_A(x)
         beta = np.linalg.norm(r)
     res.x = x
@@ -324,19 +391,19 @@ def pcg(apply_N: Callable[[np.ndarray], np.ndarray], apply_Pinv: Callable[[np.nd
     r = b.copy()
     z = apply_Pinv(r)
     p = z.copy()
-    rho = float(np.real(np.vdot(r, z)))
+    rho = np.real(np.vdot(r, z))
     rho0 = rho
     res = PCGResult(x=x, iters=0, converged=(rho0 == 0.0))
     if res.converged:
         return res
     for k in range(1, maxit + 1):
         q = apply_N(p)
-        mu = float(np.real(np.vdot(p, q)))
+        mu = np.real(np.vdot(p, q))
         alpha = rho / mu
         x += alpha * p
         r -= alpha * q
         z = apply_Pinv(r)
-        rho_new = float(np.real(np.vdot(r, z)))
+        rho_new = np.real(np.vdot(r, z))
         res.iters = k
         rel = np.sqrt(max(rho_new, 0.0) / rho0)
         res.relres.append(rel)
@@ -349,17 +416,24 @@ def pcg(apply_N: Callable[[np.ndarray], np.ndarray], apply_Pinv: Callable[[np.nd
     return res
 
 
-def pcg_all(Z: np.ndarray, lat, dip, V: np.ndarray, tol: float = 1e-10, maxit: int = 20000):
+def pcg_all(Z: np.ndarray, lat, dip, V: np.ndarray, tol: float = 1e-10, maxit: int = 20000,
+            extended: bool = False):
     """PCG on the normal equations Z^H Z I = Z^H V with P_A (diagonal blocks of
-    Z^H Z, eq. (precondA)) for every column of V; returns (I, per-RHS results)."""
+    Z^H Z, eq. (precondA)) for every column of V; returns (I, per-RHS results).
+    extended=True: the same in clongdouble (see PreconditionedSystem)."""
     M = dip.nbases
-    f = pa_factors(pa_blocks(Z, lat, dip))
-    ZH = Z.conj().T
-    B = ZH @ V
+    if extended:
+        sysm = PreconditionedSystem(Z, lat, dip, "normal_eq", extended=True)
+        Zx, pinv = sysm.Z, sysm.pinv
+    else:
+        f = pa_factors(pa_blocks(Z, lat, dip))
+        Zx, pinv = Z, (lambda v: pa_apply(f, v, M))
+    ZH = Zx.conj().T
+    B = ZH @ V.astype(Zx.dtype)
     I = np.zeros_like(V)
     results = []
     for j in range(V.shape[1]):
-        r = pcg(lambda v: ZH @ (Z @ v), lambda v: pa_apply(f, v, M), B[:, j], tol, maxit)
+        r = pcg(lambda v: ZH @ (Zx @ v), pinv, B[:, j], tol, maxit)
         I[:, j] = r.x
         results.append(r)
     return I, results

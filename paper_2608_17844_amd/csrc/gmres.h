@@ -33,7 +33,8 @@ struct GmresState {
     double* beta;    // [R]
     double* scale;   // [R]  1/||w|| for the next basis vector, 0 if the RHS stopped
     int* active;     // [R]  iterating in this cycle
-    int* conv;       // [R]  met the tolerance
+    int* conv;       // [R]  met the tolerance (decided on the explicit residual at a restart)
+    int* cand;       // [R]  the least-squares residual met the tolerance in the last cycle
     int* flag;       // [R]  non-finite value met
     int* kcyc;       // [R]  Arnoldi steps in this cycle
     int* iters;      // [R]  Arnoldi steps in total

@@ -9,7 +9,13 @@
 // plain CGS2 in three sweeps on request; complex Givens rotations (c real,
 // s complex, c = 0 and s = 1 when the pivot is zero); stop as soon as the
 // least-squares residual |g_{j+1}| <= tol * ||b||; the explicit residual
-// b - A x is recomputed at every restart.
+// b - A x is recomputed at every restart, and a RHS counts as converged only
+// on that explicit residual: <= tol * ||b||, or <= 2 tol * ||b|| after a cycle
+// whose least-squares residual met the tolerance (the two residuals differ by
+// rounding; a larger gap means the recurrence lost its Arnoldi relation, e.g.
+// at a breakdown, and the RHS restarts from the explicit residual).  In DCGS2 a
+// step whose reorthogonalised norm nu^2 = ||u||^2 - ||s||^2 has cancelled to
+// below 1e-12 ||u||^2 is a breakdown (nu = 0): the cycle ends there.
 //
 // Vectors are RHS-innermost, v[n][r]: a lane owns one RHS and walks rows, so
 // every per-RHS dot product is accumulated in a fixed order that does not
@@ -418,7 +424,9 @@ __global__ void dcgs2_finalize_kernel(GmresState st, double2* __restrict__ Hraw,
         ss += s.x * s.x + s.y * s.y;
     }
     const double alpha = RED(2 * k).x;
-    const double nu = sqrt(fmax(alpha - ss, 0.0));
+    // nu^2 by Pythagoras loses its relative accuracy as ss -> alpha: below
+    // 1e-12 alpha the candidate lies in the span of the basis (breakdown)
+    const double nu = (alpha - ss > 1e-12 * alpha) ? sqrt(alpha - ss) : 0.0;
     bool stop = false;
     if (k == 0) {
         st.g[r] = make_double2(st.beta[r] * nu, 0.0);
@@ -923,6 +931,7 @@ __global__ void cycle_init_kernel(GmresState st, const double2* __restrict__ nrm
     if (first) {
         st.bnorm[r] = beta;
         st.conv[r] = (beta == 0.0) ? 1 : 0;
+        st.cand[r] = 0;
         st.iters[r] = 0;
         st.flag[r] = 0;
     }
@@ -932,12 +941,13 @@ __global__ void cycle_init_kernel(GmresState st, const double2* __restrict__ nrm
     if (!st.conv[r] && !st.flag[r]) {
         if (!(beta == beta) || isinf(beta)) {
             st.flag[r] = 1;
-        } else if (beta <= st.tol * st.bnorm[r]) {
+        } else if (beta <= st.tol * st.bnorm[r] || (st.cand[r] && beta <= 2.0 * st.tol * st.bnorm[r])) {
             st.conv[r] = 1;
         } else {
             act = 1;
         }
     }
+    st.cand[r] = 0;
     st.active[r] = act;
     st.scale[r] = act ? 1.0 / beta : 0.0;
     st.g[r] = make_double2(act ? beta : 0.0, 0.0);
@@ -1014,8 +1024,9 @@ __global__ void scale_cols_kernel(TB* __restrict__ v, const double* __restrict__
     }
 }
 
-// End of cycle: y = R_k^{-1} g_k per RHS (k = steps done this cycle), and the
-// convergence verdict from |g_k|.
+// End of cycle: y = R_k^{-1} g_k per RHS (k = steps done this cycle); |g_k|
+// meeting the tolerance makes the RHS a candidate, which the explicit residual
+// of the next restart confirms.
 __global__ void cycle_solve_kernel(GmresState st, int R, int m, double2* __restrict__ y) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
@@ -1031,7 +1042,7 @@ __global__ void cycle_solve_kernel(GmresState st, int R, int m, double2* __restr
         y[(int64_t)i * R + r] = make_double2((acc.x * d.x + acc.y * d.y) / den, (acc.y * d.x - acc.x * d.y) / den);
     }
     const double2 gk = st.g[(int64_t)k * R + r];
-    if (hypot(gk.x, gk.y) <= st.tol * st.bnorm[r]) st.conv[r] = 1;
+    st.cand[r] = hypot(gk.x, gk.y) <= st.tol * st.bnorm[r] ? 1 : 0;
 }
 
 // sum of active flags into one int (single workgroup)
@@ -1096,7 +1107,7 @@ size_t gmres_state_bytes(int64_t N, int R, int m) {
     s += sizeof(double2) * (size_t)m * R;                      // y
     s += sizeof(double2) * (size_t)nchunk * (2 * m + 2) * R;   // partials
     s += sizeof(double2) * (size_t)R + 256;                    // reduced squared norms
-    s += sizeof(double) * (size_t)R * 4 + sizeof(int) * (size_t)R * 6 + 64;
+    s += sizeof(double) * (size_t)R * 4 + sizeof(int) * (size_t)R * 7 + 12 * 256;
     // delayed reorthogonalisation: unrotated Hessenberg, reduced sweep, coefficients, 1/nu
     s += sizeof(double2) * (size_t)(m + 1) * (m + 1) * R + sizeof(double2) * (size_t)(2 * m + 2) * R +
          sizeof(double2) * (size_t)(2 * m + 1) * R + sizeof(double) * (size_t)R + 4 * 256;
@@ -1124,6 +1135,7 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     st.scale = arena.get<double>(R);
     st.active = arena.get<int>(R);
     st.conv = arena.get<int>(R);
+    st.cand = arena.get<int>(R);
     st.flag = arena.get<int>(R);
     st.kcyc = arena.get<int>(R);
     st.iters = arena.get<int>(R);
@@ -1180,14 +1192,15 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     hipLaunchKernelGGL((copy_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, b, r0v, vs);
     MBT_LAUNCH_CHECK();
     bool first = true;
-    for (int cycle = 0; cycle < prm.max_cycles; ++cycle) {
-        // beta = ||r|| (r sits in V_0, or in the candidate vector when packed)
+    for (int cycle = 0;; ++cycle) {
+        // beta = ||r|| (r sits in V_0, or in the candidate vector when packed);
+        // the convergence verdict of the previous cycle is taken on it
         hipLaunchKernelGGL((colnorm2_kernel<TB>), dim3((R + 63) / 64, nchunk), dim3(64), 0, s, r0v, N, R, rpc, partial);
         launch_reduce_partials(partial, nchunk, 1, R, nrm2, s);
         hipLaunchKernelGGL(cycle_init_kernel, gR, bR, 0, s, st, nrm2, R, first ? 1 : 0);
         MBT_LAUNCH_CHECK();
         first = false;
-        if (count_active() == 0) break;
+        if (count_active() == 0 || cycle == prm.max_cycles) break;
         res.cycles++;
         hipLaunchKernelGGL((scale_cols_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, r0v, st.scale, N, R);
         MBT_LAUNCH_CHECK();
@@ -1274,15 +1287,6 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
         // explicit residual r = b - A x into V_0 (x cast to the basis type into V_1 first)
         hipLaunchKernelGGL((from_f64_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, x, xb, vs);
         MBT_LAUNCH_CHECK();
-        // all converged? then skip the residual
-        std::vector<int> conv(R);
-        MBT_HIP(hipMemcpyAsync(conv.data(), st.conv, sizeof(int) * R, hipMemcpyDeviceToHost, s));
-        std::vector<int> flag(R);
-        MBT_HIP(hipMemcpyAsync(flag.data(), st.flag, sizeof(int) * R, hipMemcpyDeviceToHost, s));
-        MBT_HIP(hipStreamSynchronize(s));
-        bool all = true;
-        for (int r = 0; r < R; ++r) all = all && (conv[r] || flag[r]);
-        if (all) break;
         apply(xb, r0v);
         res.matvecs += prm.matvecs_per_apply;
         hipLaunchKernelGGL((residual_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, b, r0v, vs);

@@ -138,21 +138,42 @@ def test_preconditioner_blocks_and_apply(ctx, make_array, shape):
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-11
 
 
-def _iteration_parity(gpu_iters, ref):
-    """Per-RHS Arnoldi-step counts must agree exactly, with two exceptions that
-    depend on rounding rather than on the algorithm: a difference of one at a
-    tie (the oracle's residual within 1e-8 of the threshold, relatively), and,
-    after a near-invariant Krylov subspace (an Arnoldi step whose norm ratio
-    ||w_after|| / ||w_before|| falls below 1e-2), a difference of at most three
-    (the basis after such a step is dominated by the operator's rounding)."""
+def _tie(ref, k):
+    """The oracle's least-squares residual after step k lies within 1e-8
+    (relatively) of the threshold tol * ||b||."""
+    thr = 1e-10 * (ref.restart_residuals[0] if ref.restart_residuals else 1.0)
+    return 1 <= k <= len(ref.history) and abs(ref.history[k - 1] / thr - 1.0) < 1e-8
+
+
+def _iteration_parity(gpu_iters, ref, ref_ext=None):
+    """Per-RHS Arnoldi-step counts agree exactly with the FP64 oracle; a
+    difference of one is allowed only at a tie (the oracle's residual at the
+    earlier of the two steps within 1e-8 of the threshold).  Where the count
+    depends on the arithmetic itself (the squared conditioning of the normal
+    equations), ref_ext is the oracle run in extended precision, which stands in
+    for exact arithmetic: the GPU's count must then lie between the FP64 and the
+    extended-precision counts (ties allowed at either end)."""
     if gpu_iters == ref.iters:
         return True
-    d = abs(gpu_iters - ref.iters)
-    k = min(gpu_iters, ref.iters)
-    thr = 1e-10 * (ref.restart_residuals[0] if ref.restart_residuals else 1.0)
-    if d == 1 and abs(ref.history[k - 1] / thr - 1.0) < 1e-8:
+    refs = [ref] + ([ref_ext] if ref_ext is not None else [])
+    lo = min(r.iters for r in refs)
+    hi = max(r.iters for r in refs)
+    if lo <= gpu_iters <= hi:
+        _say("count %d between the FP64 (%d) and extended-precision (%d) oracles" % (
+            gpu_iters, ref.iters, ref_ext.iters))
         return True
-    return d <= 3 and min(ref.arnoldi_ratio[:k]) < 1e-2
+    for r in refs:
+        if abs(gpu_iters - r.iters) == 1 and _tie(r, min(gpu_iters, r.iters)):
+            _say("tie at step %d" % min(gpu_iters, r.iters))
+            return True
+    k = min(gpu_iters, ref.iters)
+    lo_i = max(0, k - 4)
+    thr = 1e-10 * (ref.restart_residuals[0] if ref.restart_residuals else 1.0)
+    _say("step-count mismatch: gpu %d oracle %d%s; oracle |g|/thr around it %s; Arnoldi ratios %s" % (
+        gpu_iters, ref.iters, "" if ref_ext is None else " (extended %d)" % ref_ext.iters,
+        ["%.3e" % (h / thr) for h in ref.history[lo_i:k + 3]],
+        ["%.1e" % a for a in ref.arnoldi_ratio[lo_i:k + 3]]))
+    return False
 
 
 @pytest.mark.parametrize("pc", ["element_block", "normal_eq"])
@@ -168,39 +189,52 @@ def test_gmres_iteration_parity_and_admittance_cfg_5x5(ctx, make_array, cfg1, cf
     Y, iters, st = mbt.mbt_port_admittance(ctx, a, 1.0, None, opts)
     sysm = og.PreconditionedSystem(cfg1_oracle.Z, lat, dip, pc)
     _, res = og.gmres_all(sysm, mom.excitation(lat, dip), restart=50, tol=1e-10, orth=orth)
-    mism = [(j, int(iters[j]), res[j].iters) for j in range(len(res)) if not _iteration_parity(int(iters[j]), res[j])]
+    ext = [None] * len(res)
+    if pc == "normal_eq":
+        sx = og.PreconditionedSystem(cfg1_oracle.Z, lat, dip, pc, extended=True)
+        _, ext = og.gmres_all(sx, mom.excitation(lat, dip), restart=50, tol=1e-10, orth=orth)
+    _say("gpu     ", [int(v) for v in iters])
+    _say("oracle  ", [r.iters for r in res])
+    if pc == "normal_eq":
+        _say("extended", [r.iters for r in ext])
+    mism = [(j, int(iters[j]), res[j].iters) for j in range(len(res))
+            if not _iteration_parity(int(iters[j]), res[j], ext[j])]
     assert not mism, mism
     err = np.linalg.norm(Y - cfg1_oracle.Yp) / np.linalg.norm(cfg1_oracle.Yp)
     assert err <= 1e-9, err
     assert st["nconverged"] == 25
 
 
-@pytest.mark.parametrize("pc", ["element_block", "normal_eq"])
-def test_gmres_through_restarts(ctx, make_array, pc):
-    """GMRES(8) on a 3x4 array of 7-basis dipoles (unequal spacings), each cycle
-    restarted from the explicit residual.  With P_K (7 to 13 cycles per RHS) the
-    per-RHS step counts equal the oracle's delayed-reorthogonalisation GMRES.
-    With P_A (20 to 48 cycles on the squared-conditioned normal equations) the
-    count where a slow RHS crosses the tolerance is set by rounding: the
-    oracle's own classical and delayed Gram-Schmidt variants disagree by up to
-    nine steps on the middle column of the array, so there only convergence and
-    the admittance are compared."""
+@pytest.mark.parametrize("pc,restart", [("element_block", 8), ("normal_eq", 12)])
+def test_gmres_through_restarts(ctx, make_array, pc, restart):
+    """Restarted GMRES on a 3x4 array of 7-basis dipoles (unequal spacings),
+    each cycle restarted from the explicit residual; the per-RHS step counts
+    equal the oracle's delayed-reorthogonalisation GMRES.  P_K: GMRES(8), 7 to
+    13 cycles per RHS.  P_A: GMRES(12), up to 16 cycles on the squared-
+    conditioned normal equations; at this restart length the oracle's classical
+    and delayed Gram-Schmidt variants agree step for step (at m = 8 or 10 they
+    differ by up to seven steps, so rounding decides there)."""
     from paper_2608_17844_amd import mbt
     lat, dip = W.Lattice(3, 4, 0.45, 0.6), W.Dipole(0.5, 0.005, 7)
-    _say("gmres through restarts", pc)
+    _say("gmres through restarts", pc, restart)
     Z = mom.fill_dense(lat, dip, 1.0)
     a = make_array(lat, dip)
     code = mbt.MBT_PC_ELEMENT_BLOCK if pc == "element_block" else mbt.MBT_PC_NORMAL_EQ
-    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=code, restart=8, tol=1e-10)
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=code, restart=restart, tol=1e-10)
     Y, iters, st = mbt.mbt_port_admittance(ctx, a, 1.0, None, opts)
-    if pc == "element_block":
-        sysm = og.PreconditionedSystem(Z, lat, dip, pc)
-        _, res = og.gmres_all(sysm, mom.excitation(lat, dip), restart=8, tol=1e-10, orth="dcgs2")
-        _say("gpu", list(int(v) for v in iters), "oracle", [r.iters for r in res])
-        assert min(len(r.restart_residuals) for r in res) >= 7
-        mism = [(j, int(iters[j]), res[j].iters) for j in range(len(res))
-                if not _iteration_parity(int(iters[j]), res[j])]
-        assert not mism, mism
+    sysm = og.PreconditionedSystem(Z, lat, dip, pc)
+    _, res = og.gmres_all(sysm, mom.excitation(lat, dip), restart=restart, tol=1e-10, orth="dcgs2")
+    ext = [None] * len(res)
+    if pc == "normal_eq":
+        sx = og.PreconditionedSystem(Z, lat, dip, pc, extended=True)
+        _, ext = og.gmres_all(sx, mom.excitation(lat, dip), restart=restart, tol=1e-10, orth="dcgs2")
+    _say("gpu", list(int(v) for v in iters), "oracle", [r.iters for r in res])
+    if pc == "normal_eq":
+        _say("extended", [r.iters for r in ext])
+    assert max(len(r.restart_residuals) for r in res) >= 7
+    mism = [(j, int(iters[j]), res[j].iters) for j in range(len(res))
+            if not _iteration_parity(int(iters[j]), res[j], ext[j])]
+    assert not mism, mism
     I = mom.solve_lu(Z, mom.excitation(lat, dip))
     Yref = mom.port_admittance(I, lat, dip)
     assert np.linalg.norm(Y - Yref) / np.linalg.norm(Yref) <= 1e-8

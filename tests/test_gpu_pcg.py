@@ -31,11 +31,54 @@ def _opts(mbt, prec, **kw):
     return mbt.mbt_default_opts(prec=prec, pc=mbt.MBT_PC_NORMAL_EQ, flags=mbt.MBT_FLAG_PCG, **kw)
 
 
+def _pcg_tie(r, k, tol):
+    return 1 <= k <= len(r.relres) and abs(r.relres[k - 1] / tol - 1.0) < 1e-8
+
+
+def _pcg_counts_ok(gpu, ref, ref_ext, tol):
+    """Exact agreement with the FP64 oracle, or +-1 at a tie; where the FP64
+    and extended-precision oracles disagree (rounding decides when CG on the
+    normal equations crosses the tolerance), the GPU's count lies between them."""
+    if gpu == ref.iters:
+        return True
+    lo, hi = sorted((ref.iters, ref_ext.iters))
+    if lo <= gpu <= hi:
+        return True
+    return any(abs(gpu - r.iters) == 1 and _pcg_tie(r, min(gpu, r.iters), tol) for r in (ref, ref_ext))
+
+
+def test_pcg_iteration_parity_at_the_paper_tolerance(ctx, cfg1, cfg1_oracle):
+    """At the paper's iterative tolerance 1e-3 (Sec. IV-A) CG stops before
+    rounding takes over: the FP64 and extended-precision oracles agree, and the
+    GPU's per-RHS counts equal theirs (+-1 at a tie only)."""
+    from paper_2608_17844_amd import mbt
+    lat, dip = cfg1.lattice, cfg1.dipole
+    a = mbt.mbt_array_create_dipole(ctx, dip, lat)
+    try:
+        _, iters, st = mbt.mbt_port_admittance(ctx, a, 1.0, None, _opts(mbt, mbt.MBT_FP64, tol=1e-3))
+    finally:
+        mbt.mbt_array_destroy(a)
+    V = mom.excitation(lat, dip)
+    _, res = og.pcg_all(cfg1_oracle.Z, lat, dip, V, tol=1e-3)
+    _, ext = og.pcg_all(cfg1_oracle.Z, lat, dip, V, tol=1e-3, extended=True)
+    _say("pcg tol 1e-3 gpu      %s" % iters.tolist())
+    _say("pcg tol 1e-3 oracle   %s" % [r.iters for r in res])
+    _say("pcg tol 1e-3 extended %s" % [r.iters for r in ext])
+    assert [r.iters for r in res] == [r.iters for r in ext]
+    bad = [(j, int(iters[j]), r.iters) for j, r in enumerate(res)
+           if not (int(iters[j]) == r.iters or (abs(int(iters[j]) - r.iters) == 1
+                                                 and _pcg_tie(r, min(int(iters[j]), r.iters), 1e-3)))]
+    assert not bad, bad
+    assert st["nconverged"] == 25
+
+
 def test_pcg_iteration_parity_and_admittance_cfg_5x5(ctx, cfg1, cfg1_oracle):
-    """Every RHS stops within two iterations of the oracle's PCG.  Conjugate
-    gradients on the normal equations (condition number squared) is sensitive
-    to rounding order: the oracle itself moves by one iteration on many RHS when
-    Z^H Z is applied as one matrix instead of Z^H (Z v)."""
+    """At tol 1e-10 CG on the normal equations runs into the regime where
+    rounding sets the step that crosses the tolerance: the FP64 oracle (dense
+    BLAS products, whose sums of large cancelling EFIE terms round worst) and
+    the same recurrence in extended precision (standing in for exact
+    arithmetic) differ by up to two steps.  The GPU's FP64 count must lie
+    between the two on every RHS; its admittance matches the LU oracle."""
     from paper_2608_17844_amd import mbt
     lat, dip = cfg1.lattice, cfg1.dipole
     a = mbt.mbt_array_create_dipole(ctx, dip, lat)
@@ -43,16 +86,15 @@ def test_pcg_iteration_parity_and_admittance_cfg_5x5(ctx, cfg1, cfg1_oracle):
         Y, iters, st = mbt.mbt_port_admittance(ctx, a, 1.0, None, _opts(mbt, mbt.MBT_FP64, tol=1e-10))
     finally:
         mbt.mbt_array_destroy(a)
-    _, res = og.pcg_all(cfg1_oracle.Z, lat, dip, mom.excitation(lat, dip), tol=1e-10)
-    ref_it = np.array([r.iters for r in res])
-    _say("pcg iterations gpu %s" % iters.tolist())
-    _say("pcg iterations oracle %s" % ref_it.tolist())
-    bad = [(j, int(iters[j]), r.iters) for j, r in enumerate(res) if abs(int(iters[j]) - r.iters) > 2]
+    V = mom.excitation(lat, dip)
+    _, res = og.pcg_all(cfg1_oracle.Z, lat, dip, V, tol=1e-10)
+    _, ext = og.pcg_all(cfg1_oracle.Z, lat, dip, V, tol=1e-10, extended=True)
+    _say("pcg iterations gpu      %s" % iters.tolist())
+    _say("pcg iterations oracle   %s" % [r.iters for r in res])
+    _say("pcg iterations extended %s" % [r.iters for r in ext])
+    bad = [(j, int(iters[j]), r.iters, x.iters) for j, (r, x) in enumerate(zip(res, ext))
+           if not _pcg_counts_ok(int(iters[j]), r, x, 1e-10)]
     assert not bad, bad
-    # where the GPU stopped, the oracle's split residual was already within two decades of tol
-    for j, r in enumerate(res):
-        k = min(int(iters[j]), len(r.relres))
-        assert r.relres[k - 1] <= 1e-8, (j, k, r.relres[k - 1])
     err = np.linalg.norm(Y - cfg1_oracle.Yp) / np.linalg.norm(cfg1_oracle.Yp)
     _say("pcg fp64 |dY|/|Y| %.2e" % err)
     assert err <= 1e-8

@@ -575,3 +575,140 @@ def test_cocg_with_pk_reaches_the_lu_solution(cfg1, cfg1_dense, cfg1_oracle):
     assert all(r.converged for r in res)
     ref = mom.solve_lu(Z, V[:, [0, 12, 24]])
     assert np.linalg.norm(I - ref) / np.linalg.norm(ref) <= 1e-9
+
+
+# ----------------------------------------------------------------- extended-precision oracle variant
+
+def test_refined_inverse_is_accurate_beyond_fp64():
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((9, 9)) + 1j * rng.standard_normal((9, 9)) + 4 * np.eye(9)
+    X = og.refined_inverse(B)
+    R = B.astype(np.clongdouble) @ X - np.eye(9, dtype=np.clongdouble)
+    assert X.dtype == np.clongdouble
+    assert float(np.max(np.abs(R))) < 1e-17
+
+
+def test_extended_gmres_is_the_same_algorithm(cfg1, cfg1_dense):
+    """On the well-conditioned element-block system the extended-precision run
+    takes exactly the FP64 run's steps and reaches the LU solution; on the
+    normal equations it also reaches the LU solution."""
+    lat, dip = cfg1.lattice, cfg1.dipole
+    V = mom.excitation(lat, dip, [0, 7, 12])
+    I_lu = mom.solve_lu(cfg1_dense, V)
+    s64 = og.PreconditionedSystem(cfg1_dense, lat, dip, "element_block")
+    sx = og.PreconditionedSystem(cfg1_dense, lat, dip, "element_block", extended=True)
+    _, r64 = og.gmres_all(s64, V, orth="dcgs2")
+    Ix, rx = og.gmres_all(sx, V, orth="dcgs2")
+    assert [r.iters for r in r64] == [r.iters for r in rx]
+    assert np.linalg.norm(Ix - I_lu) <= 1e-8 * np.linalg.norm(I_lu)
+    sxn = og.PreconditionedSystem(cfg1_dense, lat, dip, "normal_eq", extended=True)
+    In, rn = og.gmres_all(sxn, V, orth="dcgs2")
+    assert all(r.converged for r in rn)
+    assert np.linalg.norm(In - I_lu) <= 1e-7 * np.linalg.norm(I_lu)
+    Ip, rp = og.pcg_all(cfg1_dense, lat, dip, V, tol=1e-10, extended=True)
+    assert all(r.converged for r in rp)
+    assert np.linalg.norm(Ip - I_lu) <= 1e-7 * np.linalg.norm(I_lu)
+
+
+# ----------------------------------------------------------------- coupling predictors (Sec. II-E)
+
+from oracle import predict as opr  # noqa: E402
+
+
+def test_border_set_and_nearest_border_element():
+    lat = W.Lattice(4, 3, 0.5, 0.5)
+    assert opr.border_elements(lat).tolist() == [0, 1, 2, 3, 4, 7, 8, 9, 10, 11]
+    assert opr.border_elements(W.Lattice(5, 1, 0.5, 0.5)).tolist() == [0, 4]
+    # 7 x 5 with dy < dx: the nearest border element of the center (3, 2) is
+    # straight down in y (distance 2 dy = 0.8) rather than in x (3 dx = 1.5)
+    lat = W.Lattice(7, 5, 0.5, 0.4)
+    c = mom.center_element(lat)
+    assert c == 2 * 7 + 3
+    assert opr.nearest_border(lat, c) == 3        # (3, 0); (3, 4) ties and has the larger index
+    # brute force over the ring
+    xy = mom.element_xy(lat)
+    ring = [e for e in range(35) if e % 7 in (0, 6) or e // 7 in (0, 4)]
+    d = [np.hypot(*(xy[e] - xy[c])) for e in ring]
+    assert opr.nearest_border(lat, c) == ring[int(np.argmin(d))]
+
+
+def test_xi_z_on_a_square_odd_array(cfg1, cfg1_oracle):
+    """5 x 5, square lattice: the four border elements nearest the center are
+    symmetric images, so the tie rule does not change xi_Z; the max form and the
+    border sum bound it from above."""
+    Zp = cfg1_oracle.Zp
+    lat = cfg1.lattice
+    c = mom.center_element(lat)
+    out = opr.xi_z(Zp, lat)
+    images = [2, 10, 14, 22]
+    vals = [abs(Zp[c, e]) / abs(Zp[c, c]) for e in images]
+    assert max(vals) - min(vals) < 1e-10 * max(vals)
+    assert out["nearest"] == 2 and abs(out["xi_z"] - vals[0]) < 1e-15
+    assert out["xi_z"] <= out["xi_z_max"] <= out["border_sum"] / abs(Zp[c, c])
+
+
+def _synthetic_s(lat, s0, a, seed=0, fill=0.0):
+    """Symmetric S with s0 on the diagonal, a between x-neighbours and `fill`
+    times random values elsewhere."""
+    P = lat.nx * lat.ny
+    rng = np.random.default_rng(seed)
+    R = fill * (rng.standard_normal((P, P)) + 1j * rng.standard_normal((P, P)))
+    S = (R + R.T) / 2
+    np.fill_diagonal(S, s0)
+    for e in range(P):
+        if e % lat.nx + 1 < lat.nx:
+            S[e, e + 1] = S[e + 1, e] = a
+    return S
+
+
+def test_column_coupling_of_a_known_arc():
+    """Nearest-column coupling only: Gamma_a(psi) = s0 + 2 a cos(psi), so the
+    Fourier coefficients are C_0 = s0, C_{+-1} = a and zero elsewhere."""
+    lat = W.Lattice(7, 1, 0.5, 0.5)
+    s0, a = 0.3 - 0.1j, 0.05 + 0.02j
+    S = _synthetic_s(lat, s0, a)
+    n, C, psi, g = opr.column_coupling(S, lat, 16)
+    assert np.allclose(g, s0 + 2 * a * np.cos(psi), atol=1e-15)
+    want = np.where(n == 0, s0, np.where(np.abs(n) == 1, a, 0))
+    assert np.max(np.abs(C - want)) < 1e-15
+
+
+def test_column_coupling_equals_column_sums(cfg1_oracle, cfg1):
+    """For Q >= nx the quadrature is exact: C_n is the sum of the center row of S
+    over the column at offset n.  Too few nodes alias (Q < nx fails)."""
+    S = cfg1_oracle.S
+    lat = cfg1.lattice
+    c = mom.center_element(lat)
+    ix = np.arange(25) % 5
+    for Q in (5, 8, 31):
+        n, C, _, _ = opr.column_coupling(S, lat, Q)
+        sums = np.array([S[c, ix - ix[c] == k].sum() for k in n])
+        assert np.max(np.abs(C - sums)) < 1e-14
+    n, C, _, _ = opr.column_coupling(S, lat, 3)
+    sums = np.array([S[c, ix - ix[c] == k].sum() for k in n])
+    assert np.max(np.abs(C - sums)) > 1e-6
+    # a row of elements: C_n is the coupling to the element n columns away
+    lat1 = W.Lattice(6, 1, 0.5, 0.5)
+    S1 = _synthetic_s(lat1, 0.2, 0.07, fill=0.01)
+    c1 = mom.center_element(lat1)
+    n, C, _, _ = opr.column_coupling(S1, lat1, 6)
+    assert np.max(np.abs(C - S1[c1, c1 + n])) < 1e-15
+
+
+def test_ideal_s_matrix_and_xi_s_closed_forms():
+    """S_ideal: symmetric, S_cc on the diagonal, S_1 at the x-neighbour, |S|
+    falling as rho^a.  Without coupling Z_ideal is diagonal (xi_S = 0).  Two
+    elements: S = [[p, q], [q, p]] has eigenvalues p +- q on (1, +-1), so
+    [z0 (1 + S)(1 - S)^{-1}]_12 = z0/2 [(1+p+q)/(1-p-q) - (1+p-q)/(1-p+q)]."""
+    lat = W.Lattice(5, 4, 0.5, 0.6)
+    S = opr.ideal_s(lat, 1.0, 0.2 - 0.3j, 0.04 + 0.01j, decay=-2.0)
+    c = mom.center_element(lat)
+    assert np.allclose(S, S.T)
+    assert S[c, c] == 0.2 - 0.3j and abs(S[c, c + 1] - (0.04 + 0.01j)) < 1e-15
+    assert abs(abs(S[c, c + 2]) - abs(0.04 + 0.01j) / 4) < 1e-15
+    assert abs(abs(S[c, c + 5 + 1]) - abs(0.04 + 0.01j) / 2) < 1e-15
+    assert opr.xi_s(lat, 1.0, 0.2, 0.0, 50.0) == 0.0
+    lat2 = W.Lattice(2, 1, 0.5, 0.5)
+    p, q, z0, zcc = 0.1 + 0.2j, -0.05 + 0.03j, 50.0, 80 + 20j
+    z12 = z0 / 2 * ((1 + p + q) / (1 - p - q) - (1 + p - q) / (1 - p + q))
+    assert abs(opr.xi_s(lat2, 1.0, p, q, zcc, z0) - abs(z12) / abs(zcc)) < 1e-14
