@@ -2,7 +2,7 @@
  * mbt.h -- C ABI of the MI355X multilevel-block-Toeplitz (MBT) finite-array
  * Method-of-Moments solver.
  *
- * Problem (paper Sec. II-C, eq. (eqProb)): Z I = V for a regular nx x ny
+ * Problem (paper Sec. II-D, eq. (eqProb)): Z I = V for a regular nx x ny
  * lattice of identical elements with M bases each, for every port excitation
  * at once (one feed per element, F = 1).  Z is multilevel block-Toeplitz
  * (Sec. II-A): the M x M block between two elements depends only on their
@@ -12,7 +12,7 @@
  * admittance / open-circuit port impedance (eq. (passZ)), the active
  * impedance (eqs. (actZ), (actZmat)) and active reflection coefficient
  * (eq. (ARC)) of the center element, and the wave-excited reflection
- * coefficient from the phased S-sum (Sec. II-D with eq. (S2Z)).
+ * coefficient from the phased S-sum (Sec. II-E with eq. (S2Z)).
  *
  * Element: a z-directed thin-wire dipole (length, radius in wavelengths at the
  * reference frequency f0; nbases odd rooftops; port at the center rooftop),
@@ -69,7 +69,8 @@ typedef enum { MBT_FP64 = 0, MBT_FP32 = 1, MBT_BF16 = 2, MBT_FP16 = 3 } mbt_prec
 
 /* Preconditioning strategy.
  * MBT_PC_NORMAL_EQ:     GMRES on P^{-1} Z^H Z I = P^{-1} Z^H V, P the block
- *                       diagonal of Z^H Z (Sec. II-B, eqs. (precondA), (precond)).
+ *                       diagonal of Z^H Z (Sec. II-B eq. (precondTBBT); built as in
+ *                       Sec. III-A, eqs. (precondA), (precond)).
  * MBT_PC_ELEMENT_BLOCK: GMRES on P_K^{-1} Z I = P_K^{-1} V, P_K the element
  *                       self blocks of Z (the older strategy of Table I). */
 typedef enum { MBT_PC_NORMAL_EQ = 0, MBT_PC_ELEMENT_BLOCK = 1 } mbt_pc;
@@ -175,7 +176,8 @@ mbt_status mbt_array_info(const mbt_array* arr, int64_t* nunknowns, int32_t* npo
 /* Device-memory estimate (bytes) of one batched solve of `nrhs` RHS. */
 size_t mbt_footprint(const mbt_array* arr, int32_t nrhs, const mbt_solve_opts* opts);
 
-/* Port admittance columns: unit delta-gap voltage at each port in `ports`
+/* Port admittance columns (Sec. II-D eq. (eqProb) with one unit delta-gap
+ * excitation per column, F = 1): unit voltage at each port in `ports`
  * (ports == NULL and nports == -1: all P ports, in order), every other port
  * shorted.  Y (P x nports, column-major, complex) receives the port-basis
  * currents: Y[i + P*j] = I(port i) for excitation ports[j].  iters (nports, may
@@ -193,22 +195,34 @@ mbt_status mbt_port_admittance_dev(mbt_ctx* ctx, const mbt_array* arr, double fr
                                    const int32_t* ports, int32_t nports, const mbt_solve_opts* opts,
                                    void* Y_dev, void* stream, int32_t* iters, mbt_stats* stats);
 
-/* Full open-circuit port impedance Z_p = Y_p^{-1} (P x P complex). */
+/* Full open-circuit port impedance (Sec. II-E eq. (passZ)): Z_p = Y_p^{-1}
+ * (P x P complex, column-major), the inverse of the short-circuit admittance
+ * that delta-gap excitation gives, on the device in FP64.  Errors as for
+ * mbt_port_admittance; MBT_EDEVICE if Y_p is singular. */
 mbt_status mbt_port_impedance(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio,
                               const mbt_solve_opts* opts, double* Zp, mbt_stats* stats);
 
 /* End to end for one frequency: geometry, lattice, frequency and all port
- * excitations in; Z_p (P x P, may be NULL), and for each of the nscan
- * directions (theta, phi radians) the center-element active impedance Za,
- * ARC Gamma = (Za - z0)/(Za + z0) and the wave-excited Gamma_wave (may be
- * NULL) out.  Everything after the solve (Y_p^{-1}, S, scans) runs on the GPU
- * in FP64. */
+ * excitations in (eq. (eqProb)); Z_p (eq. (passZ); P x P, may be NULL), and for
+ * each of the nscan directions (theta, phi radians) the center-element active
+ * impedance Za (eqs. (actZ), (actZmat)), ARC Gamma = (Za - z0)/(Za + z0)
+ * (eq. (ARC)) and the wave-excited Gamma_wave, the phased S-sum of Sec. II-E
+ * with S from eq. (S2Z) (may be NULL), out.  The port currents are phased to
+ * steer the main beam at (theta, phi): I_e = exp(-j k (x_e u + y_e v)),
+ * u = sin(theta) cos(phi), v = sin(theta) sin(phi), for the exp(-jkR) kernel of
+ * the fill.  Everything after the solve (Y_p^{-1}, S, scans) runs on the GPU in
+ * FP64.  Errors as for mbt_port_admittance; MBT_EINVAL for nscan < 0 or
+ * missing outputs, or scans requested of a block-defined array. */
 mbt_status mbt_solve(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, const mbt_solve_opts* opts,
                      const double* theta, const double* phi, int32_t nscan, double z0, double* Zp,
                      double* Za, double* Gamma, double* Gamma_wave, mbt_stats* stats);
 
-/* Scan quantities from a given Z_p (host, P x P): Za, Gamma, Gamma_wave as in
- * mbt_solve; center < 0 selects (nx/2, ny/2).  Computed on the GPU. */
+/* Scan quantities from a given Z_p (host, P x P, column-major): Za
+ * (eqs. (actZ), (actZmat)), Gamma (eq. (ARC)) and Gamma_wave (Sec. II-E, S from
+ * eq. (S2Z); may be NULL) as in mbt_solve, for the element `center` (< 0
+ * selects (nx/2, ny/2)).  Computed on the GPU in FP64.  The array supplies the
+ * lattice positions (dipole arrays only).  Errors: MBT_EINVAL (NULL argument,
+ * nscan < 1, center out of range, block-defined array), MBT_EDEVICE. */
 mbt_status mbt_active(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, const double* Zp,
                       int32_t center, const double* theta, const double* phi, int32_t nscan, double z0,
                       double* Za, double* Gamma, double* Gamma_wave);

@@ -5,7 +5,7 @@
  * symmetry.  Only tests, the smoke check and the CPU-baseline leg of the
  * benchmark may load this file's library; the GPU product path never does.
  *
- * Method-of-Moments matrix Z of the linear system Z I = V (paper, Sec. II-C,
+ * Method-of-Moments matrix Z of the linear system Z I = V (paper, Sec. II-D,
  * eq. (eqProb)).  The paper meshes its elements with RWG functions and gives
  * no fill formulas, so the element here is the thin-wire dipole of the
  * benchmark workloads, filled as follows (one reading, fixed once):
