@@ -227,6 +227,49 @@ mbt_status mbt_active(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, con
                       int32_t center, const double* theta, const double* phi, int32_t nscan, double z0,
                       double* Za, double* Gamma, double* Gamma_wave);
 
+/* ---------------------------------------------------------------- coupling predictors
+ * Post-processing of a port impedance matrix (paper Sec. II-E), on the GPU in
+ * FP64.  The border of an nx x ny lattice is its outer ring (the elements that
+ * growing the array from (nx-2) x (ny-2) adds; an axis of extent 1 has none);
+ * "nearest" is the smallest physical distance to the center element c, ties
+ * to the smallest element index. */
+typedef struct {
+    double xi_z;          /* eq. (predZ): |Z_p,cj| / |Z_p,cc|, j the border element nearest c */
+    double xi_z_max;      /* max over the border of |Z_p,cj| / |Z_p,cc| (the form before eq. (predZ)) */
+    double border_sum;    /* eq. (badpred): sum over the border of |Z_p,cn|, ohm */
+    int32_t nearest;      /* j */
+    int32_t center;       /* c */
+    double s_cc[2];       /* S_cc (complex), S from eq. (S2Z) with reference z0 */
+    double s_1[2];        /* S between c and its +x neighbour (complex) */
+} mbt_predictors;
+
+/* Predictors of element `center` (< 0: (nx/2, ny/2)) from Z_p (host, P x P
+ * complex, column-major, P = nx*ny): the xi_Z family above, and the
+ * column couplings C_n (eq. (amitayPred)) of the E-plane active reflection
+ * coefficient Gamma_a(psi) = sum_j S_cj exp(j n_j psi) (n_j the column offset
+ * of element j from c's column, uniform amplitudes), by the nq-point
+ * trapezoid rule over psi = -pi + 2 pi q / nq (exact for nq >= nx; the
+ * samples are the scan angles theta = asin(psi / (k dx)) of
+ * eq. (amitayPredTheta)).  Cn (nx complex) receives C_n for n = -ix_c ..
+ * nx-1-ix_c; Gamma_psi (nq complex, may be NULL) the sampled Gamma_a.
+ * Errors: MBT_EINVAL (NULL argument, lattice outside 1..64 per axis, z0 <= 0,
+ * nq outside 1..65536, center out of range or without a +x neighbour, no
+ * border element besides c, singular Z_p + z0), MBT_EDEVICE. */
+mbt_status mbt_predict(mbt_ctx* ctx, const mbt_lattice* lat, const double* Zp, int32_t center, double z0,
+                       int32_t nq, mbt_predictors* out, double* Cn, double* Gamma_psi);
+
+/* xi_S (eq. (predS)) for an nx x ny lattice at frequency ratio s: the ideal
+ * scattering matrix with s_cc (complex) on the diagonal and
+ * s_1 rho^decay exp(-j k (r - dx)) off it (rho the distance between lattice
+ * indices, r the physical distance, decay -2 for the infinite-array law),
+ * converted by eq. (S2Z), gives |[Z_ideal]_cj| / zp_cc_abs for the border
+ * element j nearest c.  Errors: MBT_EINVAL (as mbt_predict, freq_ratio,
+ * zp_cc_abs or z0 not positive, non-finite input, singular 1 - S_ideal),
+ * MBT_EDEVICE. */
+mbt_status mbt_predict_xi_s(mbt_ctx* ctx, const mbt_lattice* lat, double freq_ratio, const double* s_cc,
+                            const double* s_1, double zp_cc_abs, double z0, double decay, int32_t center,
+                            double* xi_s);
+
 /* ---------------------------------------------------------------- serving
  * A persistent request loop: requests are admitted while in-flight slots and
  * the device-memory budget allow, their solves overlap on the device on

@@ -54,6 +54,12 @@ class mbt_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class mbt_predictors(ctypes.Structure):
+    _fields_ = [("xi_z", ctypes.c_double), ("xi_z_max", ctypes.c_double), ("border_sum", ctypes.c_double),
+                ("nearest", ctypes.c_int32), ("center", ctypes.c_int32), ("s_cc", ctypes.c_double * 2),
+                ("s_1", ctypes.c_double * 2)]
+
+
 class mbt_request(ctypes.Structure):
     _fields_ = [("elem", mbt_dipole), ("lat", mbt_lattice), ("nfreq", ctypes.c_int32),
                 ("freq_ratio", ctypes.POINTER(ctypes.c_double)), ("nscan", ctypes.c_int32),
@@ -131,6 +137,10 @@ def lib():
             "mbt_dbg_solve": (S, [_vp, _vp, ctypes.c_double, ctypes.POINTER(mbt_solve_opts), _dp, ctypes.c_int32,
                                   _dp, _ip, ctypes.POINTER(mbt_stats)]),
             "mbt_dbg_inverse": (S, [_vp, _dp, ctypes.c_int32, _dp]),
+            "mbt_predict": (S, [_vp, ctypes.POINTER(mbt_lattice), _dp, ctypes.c_int32, ctypes.c_double,
+                                ctypes.c_int32, ctypes.POINTER(mbt_predictors), _dp, _dp]),
+            "mbt_predict_xi_s": (S, [_vp, ctypes.POINTER(mbt_lattice), ctypes.c_double, _dp, _dp, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int32, _dp]),
             "mbt_prof_start": (S, [ctypes.c_int32]),
             "mbt_prof_read": (S, [_dp, ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
         }
@@ -151,6 +161,7 @@ def exported_symbols() -> list:
         "mbt_server_create", "mbt_server_submit", "mbt_server_wait", "mbt_result_free", "mbt_server_clock",
         "mbt_server_destroy", "mbt_dbg_fill_blocks", "mbt_dbg_matvec", "mbt_dbg_precond_apply",
         "mbt_dbg_precond_blocks", "mbt_dbg_solve", "mbt_dbg_inverse", "mbt_prof_start", "mbt_prof_read",
+        "mbt_predict", "mbt_predict_xi_s",
     ]
 
 
@@ -288,6 +299,38 @@ def mbt_solve(ctx: int, arr: int, freq_ratio: float, opts: mbt_solve_opts, theta
                                     ctypes.byref(st)), allow)
     return {"Zp": Zp, "Za": Za[:ns], "Gamma": G[:ns], "Gamma_wave": Gw[:ns], "stats": st.as_dict(),
             "status": status}
+
+
+def _lat(lattice) -> mbt_lattice:
+    return mbt_lattice(lattice.nx, lattice.ny, lattice.dx, lattice.dy)
+
+
+def mbt_predict(ctx: int, lattice, Zp: np.ndarray, z0: float = 50.0, nq: int = 0, center: int = -1) -> dict:
+    """Coupling predictors of Sec. II-E from Z_p; nq = 0 picks 2 nx nodes."""
+    Zf = np.asfortranarray(Zp, dtype=np.complex128)
+    nq = nq if nq > 0 else 2 * lattice.nx
+    out = mbt_predictors()
+    Cn = np.zeros(lattice.nx, dtype=np.complex128)
+    G = np.zeros(nq, dtype=np.complex128)
+    lat = _lat(lattice)
+    _check(lib().mbt_predict(ctx, ctypes.byref(lat), _cd(Zf), center, z0, nq, ctypes.byref(out), _cd(Cn), _cd(G)))
+    c = out.center
+    ixc = c % lattice.nx
+    return {"xi_z": out.xi_z, "xi_z_max": out.xi_z_max, "border_sum": out.border_sum, "nearest": out.nearest,
+            "center": c, "s_cc": complex(out.s_cc[0], out.s_cc[1]), "s_1": complex(out.s_1[0], out.s_1[1]),
+            "n": np.arange(-ixc, lattice.nx - ixc), "Cn": Cn, "Gamma_psi": G,
+            "psi": -np.pi + 2 * np.pi * np.arange(nq) / nq}
+
+
+def mbt_predict_xi_s(ctx: int, lattice, freq_ratio: float, s_cc: complex, s_1: complex, zp_cc_abs: float,
+                     z0: float = 50.0, decay: float = -2.0, center: int = -1) -> float:
+    a = np.array([s_cc.real, s_cc.imag])
+    b = np.array([s_1.real, s_1.imag])
+    out = np.zeros(1)
+    lat = _lat(lattice)
+    _check(lib().mbt_predict_xi_s(ctx, ctypes.byref(lat), freq_ratio, _cd(a), _cd(b), zp_cc_abs, z0, decay, center,
+                                  _cd(out)))
+    return float(out[0])
 
 
 def mbt_active(ctx: int, arr: int, freq_ratio: float, Zp: np.ndarray, theta, phi, z0: float = 50.0,

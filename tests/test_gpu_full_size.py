@@ -113,10 +113,10 @@ def test_mixed_path_full_size_in_bench_configuration(setup):
 
 
 def test_fp64_cocg_full_size(setup):
-    """COCG with P_K (FP64, ||r|| <= 1e-9 ||V||): Z_p entries and the center ARC
+    """COCG with P_K (FP64, ||r|| <= 5e-10 ||V||): Z_p entries and the center ARC
     within 1e-6 relative of the oracle."""
     mbt, ctx, arr, w, ref = setup
-    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK, tol=1e-9, flags=mbt.MBT_FLAG_COCG)
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK, tol=5e-10, flags=mbt.MBT_FLAG_COCG)
     out = mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
     e = _errors(out, ref)
     _say({k: "%.2e" % v for k, v in e.items()}, out["stats"]["iters_max"])
@@ -166,11 +166,13 @@ def test_pcg_fp64_full_size(setup):
 
 
 def test_pcg_mixed_full_size(setup):
-    """FP32 PCG inner solves with FP64 refinement: 1e-6 on Z_p and the ARC."""
+    """FP32 PCG inner solves with FP64 refinement to 2e-9 (the normal equations
+    make the residual a weaker bound on the port currents: at 1e-8 the smallest
+    Z_p entries of the checked rows miss 1e-6): 1e-6 on Z_p and the ARC."""
     mbt, ctx, arr, w, ref = setup
     opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_NORMAL_EQ, restart=50, max_cycles=200,
-                                refine_tol=1e-8, inner_tol=1e-3, refine_max=4, flags=mbt.MBT_FLAG_PCG)
-    _say("32x32 mixed PCG, inner 1e-3, refine 1e-8")
+                                refine_tol=2e-9, inner_tol=1e-3, refine_max=4, flags=mbt.MBT_FLAG_PCG)
+    _say("32x32 mixed PCG, inner 1e-3, refine 2e-9")
     out = mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
     e = _errors(out, ref)
     _say({k: "%.2e" % v for k, v in e.items()}, out["stats"]["outer_steps"], out["stats"]["iters_max"])
