@@ -227,6 +227,25 @@ mbt_status mbt_active(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, con
                       int32_t center, const double* theta, const double* phi, int32_t nscan, double z0,
                       double* Za, double* Gamma, double* Gamma_wave);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mbt_active on
+ * device buffers, with no hipMalloc, hipFree or other device allocation.
+ * Zp_dev (P x P complex, column-major), theta_dev and phi_dev (nscan doubles)
+ * and the outputs Za_dev, Gamma_dev, Gamma_wave_dev (nscan complex each;
+ * Gamma_wave_dev may be NULL) are device pointers owned by the caller; the work
+ * is ordered on `stream` (NULL: the context stream) and the call returns when
+ * it is done.  The S matrix behind Gamma_wave is formed in a device scratch
+ * array of MBT_NOALLOC_SCRATCH_BYTES that the library holds on each GPU until
+ * the process ends (set up by mbt_ctx_create): at most 1024 ports when
+ * Gamma_wave_dev is given, MBT_EINVAL beyond that.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (two contexts on the same
+ * device, or threads) race on it and must be serialised by the caller.  Same
+ * results as mbt_active.  Errors as mbt_active. */
+#define MBT_NOALLOC_SCRATCH_BYTES (33u * 1024u * 1024u)
+mbt_status mbt_active_dev_noalloc(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, const void* Zp_dev,
+                                  int32_t center, const double* theta_dev, const double* phi_dev, int32_t nscan,
+                                  double z0, void* Za_dev, void* Gamma_dev, void* Gamma_wave_dev, void* stream);
+
 /* ---------------------------------------------------------------- coupling predictors
  * Post-processing of a port impedance matrix (paper Sec. II-E), on the GPU in
  * FP64.  The border of an nx x ny lattice is its outer ring (the elements that

@@ -336,6 +336,29 @@ __global__ void permute_cols_kernel(const double2* __restrict__ in, double2* __r
     out[t] = in[(int64_t)i * n + src[j]];
 }
 
+// The row interchanges of the elimination become column interchanges of the
+// inverse, last first; one thread (n <= 1024 swaps).  An out-of-range pivot
+// marks the matrix singular.
+__global__ void perm_from_pivots_kernel(const int* __restrict__ piv, int* __restrict__ src, int n,
+                                        int* __restrict__ flag) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int j = 0; j < n; ++j) src[j] = j;
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = piv[k];
+        if (p < 0 || p >= n) {
+            *flag = 1;
+            return;
+        }
+        const int t = src[k];
+        src[k] = src[p];
+        src[p] = t;
+    }
+}
+
+__global__ void clear_flag_kernel(int* flag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0;
+}
+
 __global__ void add_diag_kernel(const double2* __restrict__ in, double2* __restrict__ out, int n, double z) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * n) return;
@@ -453,6 +476,52 @@ void gj_inverse(double2* A, double2* out, int n, double2* colbuf, int* piv, int*
     hipLaunchKernelGGL(permute_cols_kernel, dim3(g1((int64_t)n * n)), dim3(256), 0, s, A, out, n, piv);
     MBT_LAUNCH_CHECK();
     MBT_HIP(hipStreamSynchronize(s));
+}
+
+// The elimination of gj_inverse with the column permutation formed on the
+// device: no host buffers, one 4-byte readback of the singularity flag into
+// pinned host memory.
+static void gj_inverse_dev_perm(double2* A, double2* out, int n, double2* colbuf, int* piv, int* src, int* flag,
+                                int* host_flag, hipStream_t s) {
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(64), 0, s, flag);
+    const int nb = kMaxPan;
+    if (n >= kBlockedMinN && n <= kPanT) {
+        double2* L = out;
+        double2* RK = out + (size_t)nb * n;
+        const dim3 ug(g1(n), (unsigned)((n + kUpdRows - 1) / kUpdRows));
+        for (int k0 = 0; k0 < n; k0 += nb) {
+            switch (std::min(nb, n - k0)) {
+            case 8: launch_panel<8>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 7: launch_panel<7>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 6: launch_panel<6>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 5: launch_panel<5>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 4: launch_panel<4>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 3: launch_panel<3>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            case 2: launch_panel<2>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            default: launch_panel<1>(A, n, k0, L, piv, flag, RK, ug, s); break;
+            }
+        }
+    } else {
+        for (int k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(gj_pivot_kernel, dim3(1), dim3(kPivT), 0, s, A, n, k, colbuf, piv, flag);
+            hipLaunchKernelGGL(gj_elim_kernel, dim3(g1((int64_t)n * n)), dim3(256), 0, s, A, n, k, colbuf);
+        }
+    }
+    hipLaunchKernelGGL(perm_from_pivots_kernel, dim3(1), dim3(64), 0, s, piv, src, n, flag);
+    hipLaunchKernelGGL(permute_cols_kernel, dim3(g1((int64_t)n * n)), dim3(256), 0, s, A, out, n, src);
+    MBT_LAUNCH_CHECK();
+    MBT_HIP(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    MBT_HIP(hipStreamSynchronize(s));
+    if (*host_flag) throw Error(-1, "port matrix is singular");
+}
+
+void s_matrix_dev_perm(const double2* Zp, double2* S, double2* work, int n, double z0, double2* colbuf, int* piv,
+                       int* src, int* flag, int* host_flag, hipStream_t s) {
+    hipLaunchKernelGGL(add_diag_kernel, dim3(g1((int64_t)n * n)), dim3(256), 0, s, Zp, work, n, z0);
+    MBT_LAUNCH_CHECK();
+    gj_inverse_dev_perm(work, S, n, colbuf, piv, src, flag, host_flag, s);   // S holds (Zp + z0)^{-1}
+    hipLaunchKernelGGL(s_from_inv_kernel, dim3(g1((int64_t)n * n)), dim3(256), 0, s, S, S, n, z0);
+    MBT_LAUNCH_CHECK();
 }
 
 void s_matrix(const double2* Zp, double2* S, double2* work, int n, double z0, double2* colbuf, int* piv, int* flag,

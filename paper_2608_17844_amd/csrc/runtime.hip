@@ -40,6 +40,43 @@ void mbt::set_last_error(const std::string& m) { g_err = m; }
     catch (const std::exception& e) { return set_err(MBT_EDEVICE, e.what()); }     \
     return MBT_OK;
 
+// ------------------------------------------------------------------ allocation-free entry point
+// Device scratch of mbt_active_dev_noalloc: the S-matrix work (Z_p + z0, its
+// inverse, the pivot search column and pivot arrays) for up to 1024 ports.
+// Each GPU the library runs on holds one copy until the process ends; host code
+// refers to it only through the per-device address taken at context creation
+// (the array's name is a host-side stand-in, not a device address).
+static __device__ __align__(256) char scratch[MBT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// With device `dev` current: record the address of its copy of the scratch array.
+void noalloc_scratch_setup(int dev) {
+    MBT_REQUIRE(dev < kMaxDevices, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void* p = nullptr;
+    MBT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    MBT_REQUIRE(p != nullptr, "no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+}
+
+char* noalloc_scratch(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+}
+
+// bytes of scratch the S-matrix work of P ports takes (256-byte aligned pieces)
+size_t noalloc_need(int P) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return 2 * al(sizeof(double2) * (size_t)P * P) + al(sizeof(double2) * (size_t)P) + 2 * al(sizeof(int) * (size_t)P) +
+           al(sizeof(int));
+}
+}  // namespace
+
 namespace mbt {
 
 // ------------------------------------------------------------------ workers
@@ -244,9 +281,9 @@ static std::shared_ptr<OpData> build_op(const mbt_array* arr, double s, Worker& 
     }
     op->Chat.alloc(sizeof(double2) * g.bins() * MM);
     {
-        DBuf scratch;
-        scratch.alloc(sizeof(double2) * ((int64_t)g.noy * g.Px * MM + g.Px + g.Py));
-        embed_blocks_fft(g, op->T.as<double2>(), op->Chat.as<double2>(), 1.0 / (double)g.bins(), scratch.as<double2>(),
+        DBuf embed_work;
+        embed_work.alloc(sizeof(double2) * ((int64_t)g.noy * g.Px * MM + g.Px + g.Py));
+        embed_blocks_fft(g, op->T.as<double2>(), op->Chat.as<double2>(), 1.0 / (double)g.bins(), embed_work.as<double2>(),
                          wk.stream);
         MBT_HIP(hipStreamSynchronize(wk.stream));
     }
@@ -909,6 +946,7 @@ mbt_status mbt_ctx_create(int32_t dev, size_t budget, mbt_ctx** out) {
     MBT_HIP(hipGetDeviceCount(&n));
     MBT_REQUIRE(dev >= 0 && dev < n, "no such HIP device");
     MBT_HIP(hipSetDevice(dev));
+    noalloc_scratch_setup(dev);
     std::unique_ptr<mbt_ctx> c(new mbt_ctx());
     c->device = dev;
     size_t freeb = 0, totalb = 0;
@@ -1055,6 +1093,50 @@ mbt_status mbt_solve(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_sol
     API_BEGIN
     MBT_REQUIRE(ctx && arr && opts, "NULL argument");
     return solve_impl(ctx, arr, s, opts, theta, phi, nscan, z0, Zp, Za, Gamma, Gamma_wave, st);
+    API_END
+}
+
+mbt_status mbt_active_dev_noalloc(mbt_ctx* ctx, const mbt_array* arr, double s, const void* Zp_dev, int32_t center,
+                                  const double* theta_dev, const double* phi_dev, int32_t nscan, double z0,
+                                  void* Za_dev, void* Gamma_dev, void* Gamma_wave_dev, void* stream) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && Zp_dev && theta_dev && phi_dev && Za_dev && Gamma_dev, "NULL argument");
+    MBT_REQUIRE(nscan >= 1, "nscan must be >= 1");
+    MBT_REQUIRE(s > 0 && z0 > 0 && std::isfinite(s) && std::isfinite(z0), "freq_ratio and z0 must be positive");
+    MBT_REQUIRE(!arr->blocks, "scan quantities need element positions: dipole arrays only");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    const Geom& g = arr->g;
+    const int P = g.P;
+    const int c = center < 0 ? (g.ny / 2) * g.nx + g.nx / 2 : center;
+    MBT_REQUIRE(c < P, "center out of range");
+    hipStream_t str = stream ? static_cast<hipStream_t>(stream) : ctx->main->stream;
+    const double2* Zp = static_cast<const double2*>(Zp_dev);
+    double2* S = nullptr;
+    if (Gamma_wave_dev) {
+        const size_t need = noalloc_need(P);
+        MBT_REQUIRE(need <= (size_t)MBT_NOALLOC_SCRATCH_BYTES,
+                    "the wave-excited ARC of " + std::to_string(P) + " ports needs " + std::to_string(need) +
+                        " bytes of device scratch; the allocation-free entry point has " +
+                        std::to_string((size_t)MBT_NOALLOC_SCRATCH_BYTES) + " (at most 1024 ports)");
+        char* base = noalloc_scratch(ctx->device);
+        MBT_REQUIRE(base != nullptr, "device scratch not set up (no context created on this device)");
+        auto take = [&](size_t b) {
+            char* p = base;
+            base += (b + 255) & ~(size_t)255;
+            return p;
+        };
+        double2* work = reinterpret_cast<double2*>(take(sizeof(double2) * (size_t)P * P));
+        S = reinterpret_cast<double2*>(take(sizeof(double2) * (size_t)P * P));
+        double2* colbuf = reinterpret_cast<double2*>(take(sizeof(double2) * (size_t)P));
+        int* piv = reinterpret_cast<int*>(take(sizeof(int) * (size_t)P));
+        int* src = reinterpret_cast<int*>(take(sizeof(int) * (size_t)P));
+        int* flag = reinterpret_cast<int*>(take(sizeof(int)));
+        s_matrix_dev_perm(Zp, S, work, P, z0, colbuf, piv, src, flag, ctx->main->host_count, str);
+    }
+    scans(g, 2.0 * M_PI * s, Zp, S, c, theta_dev, phi_dev, nscan, z0, static_cast<double2*>(Za_dev),
+          static_cast<double2*>(Gamma_dev), Gamma_wave_dev ? static_cast<double2*>(Gamma_wave_dev) : nullptr, str);
+    MBT_HIP(hipStreamSynchronize(str));
     API_END
 }
 

@@ -137,6 +137,8 @@ def lib():
             "mbt_dbg_solve": (S, [_vp, _vp, ctypes.c_double, ctypes.POINTER(mbt_solve_opts), _dp, ctypes.c_int32,
                                   _dp, _ip, ctypes.POINTER(mbt_stats)]),
             "mbt_dbg_inverse": (S, [_vp, _dp, ctypes.c_int32, _dp]),
+            "mbt_active_dev_noalloc": (S, [_vp, _vp, ctypes.c_double, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32,
+                                           ctypes.c_double, _vp, _vp, _vp, _vp]),
             "mbt_predict": (S, [_vp, ctypes.POINTER(mbt_lattice), _dp, ctypes.c_int32, ctypes.c_double,
                                 ctypes.c_int32, ctypes.POINTER(mbt_predictors), _dp, _dp]),
             "mbt_predict_xi_s": (S, [_vp, ctypes.POINTER(mbt_lattice), ctypes.c_double, _dp, _dp, ctypes.c_double,
@@ -161,7 +163,7 @@ def exported_symbols() -> list:
         "mbt_server_create", "mbt_server_submit", "mbt_server_wait", "mbt_result_free", "mbt_server_clock",
         "mbt_server_destroy", "mbt_dbg_fill_blocks", "mbt_dbg_matvec", "mbt_dbg_precond_apply",
         "mbt_dbg_precond_blocks", "mbt_dbg_solve", "mbt_dbg_inverse", "mbt_prof_start", "mbt_prof_read",
-        "mbt_predict", "mbt_predict_xi_s",
+        "mbt_predict", "mbt_predict_xi_s", "mbt_active_dev_noalloc",
     ]
 
 
@@ -299,6 +301,15 @@ def mbt_solve(ctx: int, arr: int, freq_ratio: float, opts: mbt_solve_opts, theta
                                     ctypes.byref(st)), allow)
     return {"Zp": Zp, "Za": Za[:ns], "Gamma": G[:ns], "Gamma_wave": Gw[:ns], "stats": st.as_dict(),
             "status": status}
+
+
+def mbt_active_dev_noalloc(ctx: int, arr: int, freq_ratio: float, Zp_ptr: int, theta_ptr: int, phi_ptr: int,
+                           nscan: int, z0: float, Za_ptr: int, Gamma_ptr: int, Gamma_wave_ptr: Optional[int],
+                           stream: Optional[int] = None, center: int = -1) -> None:
+    """mbt_active on caller-owned device buffers (integer device addresses, e.g.
+    torch tensors' data_ptr()) with no device allocation."""
+    _check(lib().mbt_active_dev_noalloc(ctx, arr, freq_ratio, Zp_ptr, center, theta_ptr, phi_ptr, nscan, z0, Za_ptr,
+                                        Gamma_ptr, Gamma_wave_ptr, stream))
 
 
 def _lat(lattice) -> mbt_lattice:
