@@ -544,6 +544,72 @@ def sweep(args):
             "n_gpus": 1, "results": out}
 
 
+def predict(args):
+    """Array-size sweep of the coupling predictors (Sec. II-E) on N x N dipole
+    arrays (odd N, so the center element is unique): the center element's
+    active impedance at broadside and with the beam 30 degrees off broadside in
+    the E-plane, its deviation xi(N) from the mean over the three largest
+    arrays, xi_Z(N) of each array's own Z_p, xi_S(N) from the largest array's
+    S_cc and S_1 (decay -2 and -2.4), and the decay of |C_n| of the largest
+    array.  FP64 solves; all predictors computed on the GPU."""
+    from paper_2608_17844_amd import mbt
+    from paper_2608_17844_amd import workloads as W
+    s = args.predict_freq
+    dip = W.Dipole(0.5, 0.005, 15)
+    sizes = list(range(3, args.predict + 1, 2))
+    th = np.array([0.0, np.deg2rad(30.0)])
+    ph = np.array([0.0, 0.0])
+    ctx = mbt.mbt_ctx_create(0)
+    rows = []
+    t0 = time.perf_counter()
+    try:
+        opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK, tol=1e-10)
+        for n in sizes:
+            lat = W.Lattice(n, n, 0.5, 0.5)
+            arr = mbt.mbt_array_create_dipole(ctx, dip, lat)
+            try:
+                out = mbt.mbt_solve(ctx, arr, s, opts, th, ph, 50.0)
+            finally:
+                mbt.mbt_array_destroy(arr)
+            pr = mbt.mbt_predict(ctx, lat, out["Zp"], z0=50.0, nq=2 * n)
+            c = pr["center"]
+            rows.append({"n": n, "electrical_size": n * 0.5 * s, "za_broadside": out["Za"][0], "za_30": out["Za"][1],
+                         "zp_cc": out["Zp"][c, c], "xi_z": pr["xi_z"], "xi_z_max": pr["xi_z_max"],
+                         "border_sum": pr["border_sum"], "pred": pr, "Zp_row": out["Zp"][c, :]})
+            log("predict: %dx%d  Za(0) %s  Za(30) %s  xi_Z %.3e" % (n, n, out["Za"][0], out["Za"][1], pr["xi_z"]))
+        big = rows[-1]
+        ref0 = np.mean([r["za_broadside"] for r in rows[-3:]])
+        ref30 = np.mean([r["za_30"] for r in rows[-3:]])
+        for r in rows:
+            lat = W.Lattice(r["n"], r["n"], 0.5, 0.5)
+            r["xi_broadside"] = abs(r["za_broadside"] / ref0 - 1)
+            r["xi_30"] = abs(r["za_30"] / ref30 - 1)
+            r["xi_s_2"] = mbt.mbt_predict_xi_s(ctx, lat, s, big["pred"]["s_cc"], big["pred"]["s_1"], abs(r["zp_cc"]),
+                                               50.0, -2.0)
+            r["xi_s_24"] = mbt.mbt_predict_xi_s(ctx, lat, s, big["pred"]["s_cc"], big["pred"]["s_1"],
+                                                abs(r["zp_cc"]), 50.0, -2.4)
+    finally:
+        mbt.mbt_ctx_destroy(ctx)
+    pr = big["pred"]
+    n = pr["n"]
+    pos = n > 0
+    Cn = np.abs(pr["Cn"][pos])
+    nmax = big["n"]
+    fit = lambda k, v: float(np.polyfit(np.log(k), np.log(v), 1)[0])
+    kk = n[pos]
+    sel = kk >= 3
+    out = {"metric": "coupling predictors over an array-size sweep (Sec. II-E)", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "dipole_NxN_m15_sweep", "sizes": sizes, "freq_ratio": s, "spacing_wavelengths":
+                      0.5 * s, "scan": ["broadside", "30 deg E-plane"], "z0": 50.0},
+           "seconds": time.perf_counter() - t0,
+           "rows": [{k: (v if not isinstance(v, complex) else [v.real, v.imag]) for k, v in r.items()
+                     if k not in ("pred", "Zp_row")} for r in rows],
+           "largest": {"n": nmax, "C_n_abs": Cn.tolist(), "n_values": kk.tolist(),
+                       "C_n_slope_n_ge_3": fit(kk[sel], Cn[sel]) if sel.sum() >= 2 else None,
+                       "s_cc": [pr["s_cc"].real, pr["s_cc"].imag], "s_1": [pr["s_1"].real, pr["s_1"].imag]}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -577,6 +643,10 @@ def main():
                     help="time one GPU's share of the ports (this many RHS, admittance only) instead")
     ap.add_argument("--blocks", type=int, default=0,
                     help="run the 64x64x96 synthetic-block shape with this many operators (1..5) instead")
+    ap.add_argument("--predict", type=int, default=0,
+                    help="run the coupling-predictor sweep over N x N arrays up to this N (odd) instead")
+    ap.add_argument("--predict-freq", type=float, default=1.1,
+                    help="frequency ratio of the predictor sweep (1.1: spacing 0.55 wavelengths)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy kernel three times (a known-size reference "
                          "for hardware traffic counters)")
@@ -604,6 +674,8 @@ def main():
         result = small(args)
     elif args.blocks > 0:
         result = blocks_shape(args)
+    elif args.predict > 0:
+        result = predict(args)
     else:
         result = headline(args)
     print(json.dumps(result), flush=True)

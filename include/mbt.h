@@ -163,8 +163,8 @@ mbt_status mbt_array_create_dipole(mbt_ctx* ctx, const mbt_dipole* elem, const m
  * basis p of an element to basis q of the element -d = (-dx, -dy) away, i.e.
  * Z[t][s] = T[t - s]; copied at the call.  The operator does not depend on
  * freq_ratio.  Port j is basis (M-1)/2 of element j.  Limits: nbases 1..128,
- * nx, ny 1..64; more than 32 bases: element-block preconditioner, FP64 or FP32
- * products, no scans.  Errors: MBT_EINVAL (sizes, non-finite values). */
+ * nx, ny 1..64; more than 32 bases: FP64 or FP32 products; no scans (no element
+ * positions).  Errors: MBT_EINVAL (sizes, non-finite values). */
 mbt_status mbt_array_create_blocks(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t nbases, const double* T,
                                    mbt_array** out);
 void mbt_array_destroy(mbt_array* arr);

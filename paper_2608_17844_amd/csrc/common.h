@@ -195,6 +195,9 @@ void window_sum(const Geom& g, const double2* G, double2* Pblk, hipStream_t s); 
 // info[b] != 0 flags a non-positive pivot / singular block.
 void batched_inverse(const double2* A, double2* Ainv, int M, int64_t nbatch, bool hpd, int* info,
                      hipStream_t s);
+// Hermitian positive definite blocks up to kMaxBlockM bases; A is overwritten (used as the factor's storage
+// when M > 32).
+void batched_inverse_hpd_inplace(double2* A, double2* Ainv, int M, int64_t nbatch, int* info, hipStream_t s);
 
 // elementwise / conversion helpers (vec.hip)
 template <typename TS, typename TD>

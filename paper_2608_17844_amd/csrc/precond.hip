@@ -124,6 +124,71 @@ __global__ __launch_bounds__(256) void inv_hpd_kernel(const double2* __restrict_
     if (tid == 0 && info) info[b] = bad;
 }
 
+// Larger blocks (32 < M <= 128; one M x M complex block no longer fits the LDS
+// next to its factor): one workgroup per block factorises its block in place in
+// global memory (A is overwritten with L), then each thread forms one column of
+// A^{-1} by the forward substitution L y = e_c and the back substitution
+// L^H x = y.  The workgroup's waves share one CU, so its global stores are
+// visible to its other waves after each barrier.
+__global__ __launch_bounds__(256) void inv_hpd_global_kernel(double2* __restrict__ A, double2* __restrict__ Ainv,
+                                                             int M, int* __restrict__ info) {
+    __shared__ int bad;
+    const int64_t b = blockIdx.x;
+    double2* L = A + b * (int64_t)M * M;
+    double2* Ob = Ainv + b * (int64_t)M * M;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < M; ++j) {
+        if (tid == 0) {
+            const double djj = L[j * M + j].x;
+            if (!(djj > 0.0)) bad = 1;
+            L[j * M + j] = make_double2(sqrt(djj > 0.0 ? djj : 1.0), 0.0);
+        }
+        __syncthreads();
+        const double dinv = 1.0 / L[j * M + j].x;
+        for (int i = j + 1 + tid; i < M; i += nt) L[i * M + j] = make_double2(L[i * M + j].x * dinv, L[i * M + j].y * dinv);
+        __syncthreads();
+        const int rem = M - j - 1;
+        for (int t = tid; t < rem * rem; t += nt) {
+            const int i = j + 1 + t / rem, k = j + 1 + t % rem;
+            if (k <= i) {
+                const double2 a = L[i * M + j], c = L[k * M + j];
+                double2 v = L[i * M + k];
+                v.x -= a.x * c.x + a.y * c.y;
+                v.y -= a.y * c.x - a.x * c.y;
+                L[i * M + k] = v;
+            }
+        }
+        __syncthreads();
+    }
+    for (int c = tid; c < M; c += nt) {
+        // L y = e_c (y_i = 0 for i < c), y kept in column c of the output
+        for (int i = 0; i < M; ++i) {
+            double sr = (i == c) ? 1.0 : 0.0, si = 0.0;
+            for (int k = c; k < i; ++k) {
+                const double2 l = L[i * M + k], y = Ob[k * M + c];
+                sr -= l.x * y.x - l.y * y.y;
+                si -= l.x * y.y + l.y * y.x;
+            }
+            const double dinv = 1.0 / L[i * M + i].x;
+            Ob[i * M + c] = (i < c) ? make_double2(0, 0) : make_double2(sr * dinv, si * dinv);
+        }
+        // L^H x = y, x over y in place (row i of L^H is the conjugated column i of L)
+        for (int i = M - 1; i >= 0; --i) {
+            double2 acc = Ob[i * M + c];
+            for (int k = i + 1; k < M; ++k) {
+                const double2 l = L[k * M + i], x = Ob[k * M + c];
+                acc.x -= l.x * x.x + l.y * x.y;
+                acc.y -= l.x * x.y - l.y * x.x;
+            }
+            const double dinv = 1.0 / L[i * M + i].x;
+            Ob[i * M + c] = make_double2(acc.x * dinv, acc.y * dinv);
+        }
+    }
+    if (tid == 0 && info) info[b] = bad;
+}
+
 // One workgroup per block: Gauss-Jordan inversion with partial pivoting (the
 // LU factorisation and both triangular solves in one sweep).
 __global__ __launch_bounds__(256) void inv_lu_kernel(const double2* __restrict__ A, double2* __restrict__ Ainv, int M,
@@ -203,6 +268,16 @@ void gram_blocks(const Geom& g, const double2* T, double2* G, hipStream_t s) {
 
 void window_sum(const Geom& g, const double2* G, double2* Pb, hipStream_t s) {
     hipLaunchKernelGGL(window_kernel, dim3(2048), dim3(256), 0, s, G, Pb, g.nx, g.ny, g.M);
+    MBT_LAUNCH_CHECK();
+}
+
+void batched_inverse_hpd_inplace(double2* A, double2* Ainv, int M, int64_t nbatch, int* info, hipStream_t s) {
+    MBT_REQUIRE(M >= 1 && M <= kMaxBlockM, "batched_inverse_hpd_inplace: block size out of range");
+    if (nbatch <= 0) return;
+    if (M <= kMaxInvM)
+        hipLaunchKernelGGL(inv_hpd_kernel, dim3((unsigned)nbatch), dim3(256), 0, s, A, Ainv, M, info);
+    else
+        hipLaunchKernelGGL(inv_hpd_global_kernel, dim3((unsigned)nbatch), dim3(256), 0, s, A, Ainv, M, info);
     MBT_LAUNCH_CHECK();
 }
 

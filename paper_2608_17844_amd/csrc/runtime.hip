@@ -200,7 +200,6 @@ static std::string op_key(const mbt_array* arr, double s) {
 
 static void build_pa(OpData& op, Worker& wk) {
     const Geom& g = op.g;
-    MBT_REQUIRE(g.M <= 32, "the normal-equation preconditioner supports at most 32 bases per element");
     const int64_t MM = (int64_t)g.M * g.M;
     DBuf G, Pb, info;
     G.alloc(sizeof(double2) * g.noff() * MM);
@@ -209,7 +208,7 @@ static void build_pa(OpData& op, Worker& wk) {
     gram_blocks(g, op.T.as<double2>(), G.as<double2>(), wk.stream);
     window_sum(g, G.as<double2>(), Pb.as<double2>(), wk.stream);
     op.PaInv.alloc(sizeof(double2) * g.P * MM);
-    batched_inverse(Pb.as<double2>(), op.PaInv.as<double2>(), g.M, g.P, true, info.as<int>(), wk.stream);
+    batched_inverse_hpd_inplace(Pb.as<double2>(), op.PaInv.as<double2>(), g.M, g.P, info.as<int>(), wk.stream);
     std::vector<int> hi(g.P);
     MBT_HIP(hipMemcpyAsync(hi.data(), info.p, sizeof(int) * g.P, hipMemcpyDeviceToHost, wk.stream));
     MBT_HIP(hipStreamSynchronize(wk.stream));
