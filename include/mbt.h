@@ -167,9 +167,24 @@ mbt_status mbt_array_create_dipole(mbt_ctx* ctx, const mbt_dipole* elem, const m
  * positions).  Errors: MBT_EINVAL (sizes, non-finite values). */
 mbt_status mbt_array_create_blocks(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t nbases, const double* T,
                                    mbt_array** out);
+/* Array whose impedance matrix has a margin besides its elements (Sec. II-A
+ * eq. (Zblock)): Z = [[Z_A, Z_B^T], [Z_B, Z_C]], Z_A the block-Toeplitz element
+ * interaction given by its unique blocks T as in mbt_array_create_blocks, and
+ * nmargin further unknowns (after the nx*ny*nbases element unknowns) with the
+ * element-margin coupling ZB (nmargin x nx*ny*nbases complex, row-major) and the
+ * margin's own interaction ZC (nmargin x nmargin, row-major); all copied at the
+ * call.  Ports are the element ports; the margin carries no excitation.  The
+ * normal-equation strategy solves Z^H Z I = Z^H V (eq. (Z2)) with
+ * P = blkdiag(P_A, P_C), P_A from the diagonal blocks of Z_A^H Z_A and
+ * P_C = Z_B^* Z_B^T + Z_C^H Z_C (Sec. III-A, eq. (precond)); the element-block
+ * strategy uses blkdiag(T[0], ..., T[0], Z_C).  Limits as
+ * mbt_array_create_blocks, nmargin 1..2048, FP64 or FP32 products.  Errors:
+ * MBT_EINVAL (sizes, non-finite values). */
+mbt_status mbt_array_create_margin(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t nbases, const double* T,
+                                   int32_t nmargin, const double* ZB, const double* ZC, mbt_array** out);
 void mbt_array_destroy(mbt_array* arr);
 
-/* Sizes: unknowns N = nx*ny*M, ports P = nx*ny, FFT grid (gx, gy) >= (2nx-1, 2ny-1). */
+/* Sizes: unknowns N = nx*ny*M (+ nmargin), ports P = nx*ny, FFT grid (gx, gy) >= (2nx-1, 2ny-1). */
 mbt_status mbt_array_info(const mbt_array* arr, int64_t* nunknowns, int32_t* nports, int32_t* gx,
                           int32_t* gy);
 

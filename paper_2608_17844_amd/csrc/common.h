@@ -144,6 +144,8 @@ struct Geom {
     int Px = 0, Py = 0;            // FFT grid 2*Lx x 2*Ly >= (2nx-1) x (2ny-1)
     int nox = 0, noy = 0;          // offsets per axis 2nx-1, 2ny-1
     int pc = 0;                    // port basis (M-1)/2
+    int Nc = 0;                    // margin unknowns after the P*M element unknowns (N = P*M + Nc)
+    int64_t NA() const { return (int64_t)P * M; }
     int64_t bins() const { return (int64_t)Px * Py; }
     int64_t noff() const { return (int64_t)nox * noy; }
 };
@@ -198,6 +200,15 @@ void batched_inverse(const double2* A, double2* Ainv, int M, int64_t nbatch, boo
 // Hermitian positive definite blocks up to kMaxBlockM bases; A is overwritten (used as the factor's storage
 // when M > 32).
 void batched_inverse_hpd_inplace(double2* A, double2* Ainv, int M, int64_t nbatch, int* info, hipStream_t s);
+
+// margin.hip: Y[m][r] (+)= sum_k op(A)(m, k) X[k * sxk + r * sxr], op(A)(m, k) = A[m*sm + k*sk] (conjugated
+// if conjA), for m < Mrows, r < R; Y rows of stride ldy.  A long K is split over workgroups whose partial
+// tiles go to `partial` (margin_ksplit(K) * Mrows * R values) and are summed in a fixed order.
+template <typename T>
+void margin_gemm(const cplx<T>* A, int64_t sm, int64_t sk, bool conjA, const cplx<T>* X, int64_t sxk, int64_t sxr,
+                 cplx<T>* Y, int64_t ldy, int Mrows, int64_t K, int R, bool accumulate, cplx<T>* partial,
+                 hipStream_t s);
+int margin_ksplit(int64_t K);
 
 // elementwise / conversion helpers (vec.hip)
 template <typename TS, typename TD>

@@ -53,10 +53,15 @@ struct OpData {
     DBuf ChatK32;
     DBuf Chat16[2];                            // 16-bit spectra (bfloat16, binary16) for the 16-bit products,
     double scale16[2] = {1.0, 1.0};            // stored as scale16 * C^ (a power of two)
+    // margin blocks (Nc > 0): Z_B (Nc x P*M) and Z_C (Nc x Nc) row-major, the margin's preconditioner
+    // blocks P_C^{-1} (normal equations) and Z_C^{-1} (element blocks), and their FP32 copies
+    DBuf ZB, ZC, PcInv, ZcInv, ZB32, ZC32, PcInv32, ZcInv32;
     bool has_pa = false, has32 = false;
     size_t bytes() const {
         return T.bytes + Chat.bytes + ChatK.bytes + tw.bytes + PkInv.bytes + PaInv.bytes + Chat32.bytes +
-               ChatK32.bytes + tw32.bytes + PkInv32.bytes + PaInv32.bytes + Chat16[0].bytes + Chat16[1].bytes;
+               ChatK32.bytes + tw32.bytes + PkInv32.bytes + PaInv32.bytes + Chat16[0].bytes + Chat16[1].bytes +
+               ZB.bytes + ZC.bytes + PcInv.bytes + ZcInv.bytes + ZB32.bytes + ZC32.bytes + PcInv32.bytes +
+               ZcInv32.bytes;
     }
 };
 
@@ -95,6 +100,8 @@ struct mbt_array {
     // arrays defined by caller-supplied unique blocks (no element fill): host copy
     // of T[dy][dx][p][q] and an identity for the operator cache
     std::shared_ptr<const std::vector<double2>> blocks;
+    // partitioned operators: margin blocks Z_B (Nc x P*M) and Z_C (Nc x Nc), row-major host copies
+    std::shared_ptr<const std::vector<double2>> zb, zc;
     uint64_t uid = 0;
 };
 

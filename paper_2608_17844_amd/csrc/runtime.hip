@@ -213,6 +213,25 @@ static void build_pa(OpData& op, Worker& wk) {
     MBT_HIP(hipMemcpyAsync(hi.data(), info.p, sizeof(int) * g.P, hipMemcpyDeviceToHost, wk.stream));
     MBT_HIP(hipStreamSynchronize(wk.stream));
     for (int v : hi) MBT_REQUIRE(v == 0, "normal-equation preconditioner block is not positive definite");
+    if (g.Nc > 0) {
+        // P_C = Z_B^* Z_B^T + Z_C^H Z_C (eq. (precond)), then its inverse
+        const int nc = g.Nc;
+        const int64_t NA = g.NA();
+        DBuf Pc, part, work;
+        Pc.alloc(sizeof(double2) * (size_t)nc * nc);
+        part.alloc(sizeof(double2) * (size_t)margin_ksplit(NA) * nc * nc);
+        work.alloc(sizeof(double2) * ((size_t)nc + 8) + sizeof(int) * ((size_t)nc + 8));
+        // (Z_B^* Z_B^T)[i][j] = sum_k conj(Z_B[i][k]) Z_B[j][k]: X[k][j] = Z_B[j][k]
+        margin_gemm<double>(op.ZB.as<double2>(), NA, 1, true, op.ZB.as<double2>(), 1, NA, Pc.as<double2>(), nc, nc, NA,
+                            nc, false, part.as<double2>(), wk.stream);
+        // (Z_C^H Z_C)[i][j] = sum_l conj(Z_C[l][i]) Z_C[l][j]
+        margin_gemm<double>(op.ZC.as<double2>(), 1, nc, true, op.ZC.as<double2>(), nc, 1, Pc.as<double2>(), nc, nc, nc,
+                            nc, true, nullptr, wk.stream);
+        op.PcInv.alloc(sizeof(double2) * (size_t)nc * nc);
+        double2* colbuf = work.as<double2>();
+        int* piv = reinterpret_cast<int*>(colbuf + nc + 8);
+        gj_inverse(Pc.as<double2>(), op.PcInv.as<double2>(), nc, colbuf, piv, piv + nc, wk.stream);
+    }
     op.has_pa = true;
 }
 
@@ -227,6 +246,15 @@ static void build_32(OpData& op, Worker& wk) {
     convert<double2, float2>(op.tw.as<double2>(), op.tw32.as<float2>(), g.Px + g.Py, wk.stream);
     op.PkInv32.alloc(sizeof(float2) * MM);
     convert<double2, float2>(op.PkInv.as<double2>(), op.PkInv32.as<float2>(), MM, wk.stream);
+    if (g.Nc > 0) {
+        const int64_t nb = (int64_t)g.Nc * g.NA(), nc2 = (int64_t)g.Nc * g.Nc;
+        op.ZB32.alloc(sizeof(float2) * nb);
+        convert<double2, float2>(op.ZB.as<double2>(), op.ZB32.as<float2>(), nb, wk.stream);
+        op.ZC32.alloc(sizeof(float2) * nc2);
+        convert<double2, float2>(op.ZC.as<double2>(), op.ZC32.as<float2>(), nc2, wk.stream);
+        op.ZcInv32.alloc(sizeof(float2) * nc2);
+        convert<double2, float2>(op.ZcInv.as<double2>(), op.ZcInv32.as<float2>(), nc2, wk.stream);
+    }
     MBT_HIP(hipStreamSynchronize(wk.stream));
     op.has32 = true;
 }
@@ -237,6 +265,11 @@ static void build_32_pa(OpData& op, Worker& wk) {
     const int64_t MM = (int64_t)g.M * g.M;
     op.PaInv32.alloc(sizeof(float2) * g.P * MM);
     convert<double2, float2>(op.PaInv.as<double2>(), op.PaInv32.as<float2>(), g.P * MM, wk.stream);
+    if (g.Nc > 0) {
+        const int64_t nc2 = (int64_t)g.Nc * g.Nc;
+        op.PcInv32.alloc(sizeof(float2) * nc2);
+        convert<double2, float2>(op.PcInv.as<double2>(), op.PcInv32.as<float2>(), nc2, wk.stream);
+    }
     MBT_HIP(hipStreamSynchronize(wk.stream));
 }
 
@@ -310,6 +343,22 @@ static std::shared_ptr<OpData> build_op(const mbt_array* arr, double s, Worker& 
                                wk.stream));
         int* piv = reinterpret_cast<int*>(A + MM + g.M);
         gj_inverse(A, op->PkInv.as<double2>(), g.M, A + MM, piv, piv + g.M, wk.stream);
+        MBT_HIP(hipStreamSynchronize(wk.stream));
+    }
+    if (g.Nc > 0) {
+        MBT_REQUIRE(arr->zb && arr->zc, "margin blocks missing");
+        const int nc = g.Nc;
+        op->ZB.alloc(sizeof(double2) * (size_t)nc * g.NA());
+        MBT_HIP(hipMemcpyAsync(op->ZB.p, arr->zb->data(), op->ZB.bytes, hipMemcpyHostToDevice, wk.stream));
+        op->ZC.alloc(sizeof(double2) * (size_t)nc * nc);
+        MBT_HIP(hipMemcpyAsync(op->ZC.p, arr->zc->data(), op->ZC.bytes, hipMemcpyHostToDevice, wk.stream));
+        DBuf work;
+        work.alloc(sizeof(double2) * ((size_t)nc * nc + nc + 8) + sizeof(int) * ((size_t)nc + 8));
+        double2* A = work.as<double2>();
+        MBT_HIP(hipMemcpyAsync(A, op->ZC.p, op->ZC.bytes, hipMemcpyDeviceToDevice, wk.stream));
+        op->ZcInv.alloc(sizeof(double2) * (size_t)nc * nc);
+        int* piv = reinterpret_cast<int*>(A + (size_t)nc * nc + nc + 8);
+        gj_inverse(A, op->ZcInv.as<double2>(), nc, A + (size_t)nc * nc, piv, piv + nc, wk.stream);
         MBT_HIP(hipStreamSynchronize(wk.stream));
     }
     // P_K^{-1} acts on the basis index of every element alike, so it commutes with
@@ -399,7 +448,28 @@ template <typename T> struct OpV {
     int fmt = kFmtNone;                  // 16-bit per-bin products (FP32 view only)
     const uint32_t* Chat16 = nullptr;
     float out_scale = 1.0f;              // undoes the power-of-two scaling of Chat16
+    // margin blocks (nc > 0): Z_B, Z_C, the margin's preconditioner inverse, and scratch
+    // (mtmp: nc x R; mpart: margin_ksplit(P*M) x nc x R) attached by the caller
+    int nc = 0;
+    const cplx<T>* zb = nullptr;
+    const cplx<T>* zc = nullptr;
+    const cplx<T>* pcinv = nullptr;
+    cplx<T>* mtmp = nullptr;
+    cplx<T>* mpart = nullptr;
 };
+
+// scratch bytes a view of a margin array needs for R columns (FP64-sized, shared by both views)
+static size_t margin_scratch_bytes(const Geom& g, int R) {
+    if (g.Nc == 0) return 0;
+    return sizeof(double2) * (size_t)g.Nc * R * (1 + margin_ksplit(g.NA())) + 512;
+}
+
+template <typename T> static void attach_margin(OpV<T>& v, void* scratch) {
+    if (v.nc == 0) return;
+    MBT_REQUIRE(scratch != nullptr, "margin scratch missing");
+    v.mtmp = static_cast<cplx<T>*>(scratch);
+    v.mpart = v.mtmp + (size_t)v.nc * v.R;
+}
 
 template <typename T>
 static OpV<T> make_view(const OpData& op, int pc, void* Xh, void* Yh, void* tmp, int R, hipStream_t s,
@@ -410,7 +480,14 @@ OpV<double> make_view<double>(const OpData& op, int pc, void* Xh, void* Yh, void
     OpV<double> v;
     v.g = &op.g;
     v.Chat = op.Chat.as<double2>();
-    if (pc == MBT_PC_ELEMENT_BLOCK) v.ChatA = op.ChatK.as<double2>();
+    // the folded P_K^{-1} C^ covers element rows only: margin arrays apply P_K^{-1} Z directly
+    if (pc == MBT_PC_ELEMENT_BLOCK && op.g.Nc == 0) v.ChatA = op.ChatK.as<double2>();
+    if (op.g.Nc > 0) {
+        v.nc = op.g.Nc;
+        v.zb = op.ZB.as<double2>();
+        v.zc = op.ZC.as<double2>();
+        v.pcinv = pc == MBT_PC_NORMAL_EQ ? op.PcInv.as<double2>() : op.ZcInv.as<double2>();
+    }
     v.pinv = pc == MBT_PC_NORMAL_EQ ? op.PaInv.as<double2>() : op.PkInv.as<double2>();
     v.pstride = pc == MBT_PC_NORMAL_EQ ? (int64_t)op.g.M * op.g.M : 0;
     v.twx = op.tw.as<double2>();
@@ -435,7 +512,14 @@ OpV<float> make_view<float>(const OpData& op, int pc, void* Xh, void* Yh, void* 
     }
     v.g = &op.g;
     v.Chat = op.Chat32.as<float2>();
-    if (pc == MBT_PC_ELEMENT_BLOCK && fmt == kFmtNone) v.ChatA = op.ChatK32.as<float2>();
+    if (pc == MBT_PC_ELEMENT_BLOCK && fmt == kFmtNone && op.g.Nc == 0) v.ChatA = op.ChatK32.as<float2>();
+    if (op.g.Nc > 0) {
+        MBT_REQUIRE(fmt == kFmtNone, "16-bit products are not available for arrays with a margin");
+        v.nc = op.g.Nc;
+        v.zb = op.ZB32.as<float2>();
+        v.zc = op.ZC32.as<float2>();
+        v.pcinv = pc == MBT_PC_NORMAL_EQ ? op.PcInv32.as<float2>() : op.ZcInv32.as<float2>();
+    }
     v.pinv = pc == MBT_PC_NORMAL_EQ ? op.PaInv32.as<float2>() : op.PkInv32.as<float2>();
     v.pstride = pc == MBT_PC_NORMAL_EQ ? (int64_t)op.g.M * op.g.M : 0;
     v.twx = op.tw32.as<float2>();
@@ -451,12 +535,47 @@ OpV<float> make_view<float>(const OpData& op, int pc, void* Xh, void* Yh, void* 
 
 // y = Z x (opz 0) or Z^H x (opz 1) by FFT over the lattice, per-bin products, inverse FFT and crop;
 // chat replaces the block spectra (the preconditioned operator's, FP64/FP32 products only)
+// Margin part of y = Z x (opz 0) or Z^H x (opz 1) for Z = [[Z_A, Z_B^T], [Z_B, Z_C]]: before the lattice
+// transform (which may overwrite x's element rows when y == x) the margin rows
+// t = op(Z_B) x_A + op(Z_C) x_C go to scratch; after it, the element rows receive op(Z_B^T) x_C and the
+// margin rows t.  Z^H = [[Z_A^H, Z_B^H], [Z_B^*, Z_C^H]].
+template <typename T> static void margin_pre(const OpV<T>& o, int opz, const cplx<T>* x) {
+    const Geom& g = *o.g;
+    const int64_t NA = g.NA();
+    const int nc = o.nc, R = o.R;
+    // t = Z_B x_A or Z_B^* x_A (row-major Z_B: op(A)(m, k) = Z_B[m][k])
+    margin_gemm<T>(o.zb, NA, 1, opz == 1, x, R, 1, o.mtmp, R, nc, NA, R, false, o.mpart, o.s);
+    // t += Z_C x_C (Z_C[m][k]) or Z_C^H x_C (conj Z_C[k][m])
+    if (opz == 0)
+        margin_gemm<T>(o.zc, nc, 1, false, x + NA * R, R, 1, o.mtmp, R, nc, nc, R, true, nullptr, o.s);
+    else
+        margin_gemm<T>(o.zc, 1, nc, true, x + NA * R, R, 1, o.mtmp, R, nc, nc, R, true, nullptr, o.s);
+}
+template <typename T> static void margin_post(const OpV<T>& o, int opz, const cplx<T>* x, cplx<T>* y) {
+    const Geom& g = *o.g;
+    const int64_t NA = g.NA();
+    const int nc = o.nc, R = o.R;
+    // y_A += Z_B^T x_C (op(A)(m, k) = Z_B[k][m]) or Z_B^H x_C (conjugated)
+    margin_gemm<T>(o.zb, 1, NA, opz == 1, x + NA * R, R, 1, y, R, (int)NA, nc, R, true, nullptr, o.s);
+    convert<cplx<T>, cplx<T>>(o.mtmp, y + NA * R, (int64_t)nc * R, o.s);
+}
+
+template <typename T>
+static void zmul_lattice(const OpV<T>& o, int opz, const cplx<T>* x, cplx<T>* y, const cplx<T>* chat);
+
 template <typename T>
 static void zmul(const OpV<T>& o, int opz, const cplx<T>* x, cplx<T>* y, const cplx<T>* chat = nullptr) {
+    if (o.nc > 0) margin_pre<T>(o, opz, x);
+    zmul_lattice<T>(o, opz, x, y, chat);
+    if (o.nc > 0) margin_post<T>(o, opz, x, y);
+}
+
+template <typename T>
+static void zmul_lattice(const OpV<T>& o, int opz, const cplx<T>* x, cplx<T>* y, const cplx<T>* chat) {
     const Geom& g = *o.g;
     const int64_t B = (int64_t)g.M * o.R;
     const double sc = sizeof(cplx<T>);
-    const double spat = (double)g.N * o.R * sc, spec = (double)g.bins() * g.M * o.R * sc;
+    const double spat = (double)g.NA() * o.R * sc, spec = (double)g.bins() * g.M * o.R * sc;
     if constexpr (sizeof(T) == 4) {
         if (o.fmt != kFmtNone) {
             // 16-bit spectrum X^ (4 bytes per value), FP32 products Y^
@@ -503,9 +622,16 @@ static void zmul(const OpV<T>& o, int opz, const cplx<T>* x, cplx<T>* y, const c
 template <typename T> static void pinv(const OpV<T>& o, const cplx<T>* x, cplx<T>* y) {
     const double sc = sizeof(cplx<T>);
     const double blocks = o.pstride ? (double)o.g->P : 1.0;
-    ProfScope ps(kKPrecondApply, 2.0 * o.g->N * o.R * sc + blocks * o.g->M * o.g->M * sc,
-                 8.0 * o.g->P * o.g->M * o.g->M * o.R, o.s);
-    cgemm_batched<T>(o.pinv, o.pstride, x, y, o.g->M, o.R, o.g->P, 0, o.s);
+    {
+        ProfScope ps(kKPrecondApply, 2.0 * o.g->NA() * o.R * sc + blocks * o.g->M * o.g->M * sc,
+                     8.0 * o.g->P * o.g->M * o.g->M * o.R, o.s);
+        cgemm_batched<T>(o.pinv, o.pstride, x, y, o.g->M, o.R, o.g->P, 0, o.s);
+    }
+    if (o.nc > 0) {
+        // the margin's block: P_C^{-1} (normal equations) or Z_C^{-1} (element blocks)
+        const int64_t off = o.g->NA() * o.R;
+        margin_gemm<T>(o.pcinv, o.nc, 1, false, x + off, o.R, 1, y + off, o.R, o.nc, o.nc, o.R, false, nullptr, o.s);
+    }
 }
 
 // preconditioned operator: P_K^{-1} Z  or  P^{-1} Z^H Z
@@ -543,6 +669,7 @@ size_t solve_bytes(const Geom& g, int R, const mbt_solve_opts& o) {
     if (o.prec != MBT_FP64) b += NR * 16 + NR * 8;     // d, r32
     b += std::max(gmres_state_bytes(g.N, R, o.restart), std::max(pcg_state_bytes(g.N, R), cocg_state_bytes(g.N, R)));
     b += (size_t)R * 64 + ((size_t)g.N / 256 + 2) * R * 8 + (size_t)g.P * R * 16 + (1 << 20);
+    b += margin_scratch_bytes(g, R);
     return b;
 }
 
@@ -600,6 +727,7 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
     void* Xh = arena.get<double2>((size_t)g.bins() * g.M * R);
     void* Yh = arena.get<double2>((size_t)g.bins() * g.M * R);
     double2* tmp = arena.get<double2>(NR);
+    void* mscr = g.Nc > 0 ? arena.get<char>(margin_scratch_bytes(g, R)) : nullptr;
     GmresParams prm;
     prm.restart = m;
     prm.max_cycles = o.max_cycles;
@@ -617,6 +745,7 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
         double2* basis = arena.get<double2>((size_t)std::max(m + 1, 5) * NR);
         double2* b = arena.get<double2>(NR);
         OpV<double> ov = make_view<double>(op, o.pc, Xh, Yh, tmp, R, s);
+        attach_margin(ov, mscr);
         GmresResult gr;
         if (use_pcg) {
             // Z^H Z I = Z^H V with P_A (Sec. II-C)
@@ -668,6 +797,8 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
         double* unscale = arena.get<double>(R);   // ||r|| per RHS still refining, 0 once done
         OpV<double> ov = make_view<double>(op, o.pc, Xh, Yh, tmp, R, s);
         OpV<float> ov32 = make_view<float>(op, o.pc, Xh, Yh, tmp, R, s, fmt16_of(o.prec));
+        attach_margin(ov, mscr);
+        attach_margin(ov32, mscr);
         std::function<void(const float2*, float2*)> f = [&](const float2* x, float2* y) { apply_A<float>(ov32, x, y); };
         prm.tol = inner_tol(o);
         zero_d(X, NR, s);
@@ -752,6 +883,7 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
     // FP64 path: true residual ||V - Z X|| / ||V||
     {
         OpV<double> ov = make_view<double>(op, o.pc, Xh, Yh, tmp, R, s);
+        attach_margin(ov, mscr);
         double2* r64 = arena.get<double2>(NR);
         zmul<double>(ov, 0, X, tmp);
         out.matvecs += 1;
@@ -995,6 +1127,32 @@ mbt_status mbt_array_create_blocks(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t
     API_END
 }
 
+mbt_status mbt_array_create_margin(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t nbases, const double* T,
+                                   int32_t nmargin, const double* ZB, const double* ZC, mbt_array** out) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && T && ZB && ZC && out, "NULL argument");
+    MBT_REQUIRE(nmargin >= 1 && nmargin <= 2048, "nmargin must be within 1..2048");
+    std::unique_ptr<mbt_array> a(new mbt_array());
+    a->g = make_geom_blocks(nx, ny, nbases);
+    a->g.Nc = nmargin;
+    a->g.N = a->g.NA() + nmargin;
+    a->elem = mbt_dipole{0.0, 0.0, nbases};
+    a->lat = mbt_lattice{nx, ny, a->g.dx, a->g.dy};
+    auto copy = [](const double* src, size_t n) {
+        auto v = std::make_shared<std::vector<double2>>(n);
+        std::memcpy(v->data(), src, sizeof(double2) * n);
+        for (const double2& z : *v) MBT_REQUIRE(std::isfinite(z.x) && std::isfinite(z.y), "blocks must be finite");
+        return v;
+    };
+    a->blocks = copy(T, (size_t)(a->g.noff() * (int64_t)nbases * nbases));
+    a->zb = copy(ZB, (size_t)nmargin * (size_t)a->g.NA());
+    a->zc = copy(ZC, (size_t)nmargin * (size_t)nmargin);
+    static std::atomic<uint64_t> next_uid{1u << 30};
+    a->uid = next_uid++;
+    *out = a.release();
+    API_END
+}
+
 void mbt_array_destroy(mbt_array* a) { delete a; }
 
 mbt_status mbt_array_info(const mbt_array* a, int64_t* N, int32_t* P, int32_t* gx, int32_t* gy) {
@@ -1204,7 +1362,8 @@ mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t 
     Worker& wk = *ctx->main;
     auto op = get_op(ctx, arr, s, false, prec, wk);
     const int64_t NR = g.N * R;
-    DBuf hx, dx, dy, Xh, Yh, tmp, f1, f2;
+    DBuf hx, dx, dy, Xh, Yh, tmp, f1, f2, mscr;
+    mscr.alloc(margin_scratch_bytes(g, R));
     hx.alloc(sizeof(double2) * NR);
     dx.alloc(sizeof(double2) * NR);
     dy.alloc(sizeof(double2) * NR);
@@ -1215,6 +1374,7 @@ mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t 
     transpose_nr(hx.as<double2>(), dx.as<double2>(), g.N, R, true, wk.stream);
     if (prec == MBT_FP64) {
         OpV<double> ov = make_view<double>(*op, MBT_PC_ELEMENT_BLOCK, Xh.p, Yh.p, tmp.p, R, wk.stream);
+        attach_margin(ov, mscr.p);
         if (opz == 2) {
             zmul<double>(ov, 0, dx.as<double2>(), tmp.as<double2>());
             zmul<double>(ov, 1, tmp.as<double2>(), dy.as<double2>());
@@ -1225,6 +1385,7 @@ mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t 
         f1.alloc(sizeof(float2) * NR);
         f2.alloc(sizeof(float2) * NR);
         OpV<float> ov = make_view<float>(*op, MBT_PC_ELEMENT_BLOCK, Xh.p, Yh.p, tmp.p, R, wk.stream, fmt16_of(prec));
+        attach_margin(ov, mscr.p);
         convert<double2, float2>(dx.as<double2>(), f1.as<float2>(), NR, wk.stream);
         if (opz == 2) {
             zmul<float>(ov, 0, f1.as<float2>(), ov.tmp);
@@ -1258,7 +1419,7 @@ mbt_status mbt_dbg_precond_apply(mbt_ctx* ctx, const mbt_array* arr, double s, i
     MBT_HIP(hipMemcpyAsync(hx.p, x, sizeof(double2) * NR, hipMemcpyHostToDevice, wk.stream));
     transpose_nr(hx.as<double2>(), dx.as<double2>(), g.N, R, true, wk.stream);
     OpV<double> ov = make_view<double>(*op, pc, nullptr, nullptr, nullptr, R, wk.stream);
-    pinv<double>(ov, dx.as<double2>(), dy.as<double2>());
+    pinv<double>(ov, dx.as<double2>(), dy.as<double2>());   // the margin block needs no scratch
     transpose_nr(dy.as<double2>(), hx.as<double2>(), g.N, R, false, wk.stream);
     MBT_HIP(hipMemcpyAsync(y, hx.p, sizeof(double2) * NR, hipMemcpyDeviceToHost, wk.stream));
     MBT_HIP(hipStreamSynchronize(wk.stream));

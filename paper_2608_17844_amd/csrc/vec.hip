@@ -174,6 +174,7 @@ void convert(const TS* src, TD* dst, int64_t n, hipStream_t s) {
 template void convert<double2, float2>(const double2*, float2*, int64_t, hipStream_t);
 template void convert<float2, double2>(const float2*, double2*, int64_t, hipStream_t);
 template void convert<double2, double2>(const double2*, double2*, int64_t, hipStream_t);
+template void convert<float2, float2>(const float2*, float2*, int64_t, hipStream_t);
 
 template <int FMT>
 void pack16_d(const double2* src, uint32_t* dst, int64_t n, double scale, hipStream_t s) {

@@ -109,6 +109,8 @@ def lib():
                                             ctypes.POINTER(_vp)]),
             "mbt_array_create_blocks": (S, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp,
                                             ctypes.POINTER(_vp)]),
+            "mbt_array_create_margin": (S, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int32,
+                                            _dp, _dp, ctypes.POINTER(_vp)]),
             "mbt_array_destroy": (None, [_vp]),
             "mbt_array_info": (S, [_vp, ctypes.POINTER(ctypes.c_int64), _ip, _ip, _ip]),
             "mbt_footprint": (ctypes.c_size_t, [_vp, ctypes.c_int32, ctypes.POINTER(mbt_solve_opts)]),
@@ -163,7 +165,7 @@ def exported_symbols() -> list:
         "mbt_server_create", "mbt_server_submit", "mbt_server_wait", "mbt_result_free", "mbt_server_clock",
         "mbt_server_destroy", "mbt_dbg_fill_blocks", "mbt_dbg_matvec", "mbt_dbg_precond_apply",
         "mbt_dbg_precond_blocks", "mbt_dbg_solve", "mbt_dbg_inverse", "mbt_prof_start", "mbt_prof_read",
-        "mbt_predict", "mbt_predict_xi_s", "mbt_active_dev_noalloc",
+        "mbt_predict", "mbt_predict_xi_s", "mbt_active_dev_noalloc", "mbt_array_create_margin",
     ]
 
 
@@ -220,6 +222,19 @@ def mbt_array_create_blocks(ctx: int, T: np.ndarray) -> int:
     h = _vp()
     _check(lib().mbt_array_create_blocks(ctx, nx, ny, T.shape[2], T.ctypes.data_as(_dp), ctypes.byref(h)))
     return h.value
+
+
+def mbt_array_create_margin(ctx: int, T: np.ndarray, ZB: np.ndarray, ZC: np.ndarray) -> int:
+    """Partitioned array: unique blocks T (2ny-1, 2nx-1, M, M), margin coupling ZB
+    (nc x nx*ny*M) and margin block ZC (nc x nc), complex."""
+    T = np.ascontiguousarray(T, dtype=np.complex128)
+    ny2, nx2, M, _ = T.shape
+    ZB = np.ascontiguousarray(ZB, dtype=np.complex128)
+    ZC = np.ascontiguousarray(ZC, dtype=np.complex128)
+    out = _vp()
+    _check(lib().mbt_array_create_margin(ctx, (nx2 + 1) // 2, (ny2 + 1) // 2, M, _cd(T), ZC.shape[0], _cd(ZB), _cd(ZC),
+                                         ctypes.byref(out)))
+    return out.value
 
 
 def mbt_array_destroy(arr: int) -> None:

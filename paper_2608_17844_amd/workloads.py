@@ -124,6 +124,24 @@ def synthetic_blocks(nx: int, ny: int, nbases: int, seed: int = 0, coupling: flo
     return T
 
 
+def synthetic_margin(nx: int, ny: int, nbases: int, nmargin: int, seed: int = 0, rank: int = 6,
+                     coupling: float = 0.02):
+    """Seeded margin blocks of a partitioned array operator [[Z_A, Z_B^T], [Z_B, Z_C]]
+    for the block-defined workloads: Z_C (nmargin x nmargin) symmetric, a unit
+    diagonal (1 + 0.5j) plus a small random symmetric part; Z_B (nmargin x
+    nx*ny*nbases) of low rank `rank` (the element-margin coupling), entries of
+    size about `coupling`.  Returns (Z_B, Z_C), complex128."""
+    rng = np.random.default_rng(seed)
+    NA = nx * ny * nbases
+    G = (rng.standard_normal((nmargin, nmargin)) + 1j * rng.standard_normal((nmargin, nmargin))) / (
+        2.0 * np.sqrt(nmargin))
+    ZC = (1.0 + 0.5j) * np.eye(nmargin) + 0.1 * (G + G.T) / 2
+    U = rng.standard_normal((nmargin, rank)) + 1j * rng.standard_normal((nmargin, rank))
+    Vt = rng.standard_normal((rank, NA)) + 1j * rng.standard_normal((rank, NA))
+    ZB = coupling * (U @ Vt) / (2.0 * rank)
+    return ZB, ZC
+
+
 @dataclass
 class Request:
     """One serving request: an array, its frequencies and its scan set."""

@@ -1,0 +1,159 @@
+"""Arrays with a margin (Sec. II-A eq. (Zblock)) on the GPU: the operator
+Z = [[Z_A, Z_B^T], [Z_B, Z_C]] and its adjoint, the preconditioner
+blkdiag(P_A, P_C) of eq. (precond) and the element-block fallback, and
+GMRES / PCG solves on the normal equations of eq. (Z2), against the dense
+oracle on seeded synthetic blocks."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gmres as og
+from oracle import margin as omg
+from oracle import mom
+from paper_2608_17844_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2608_17844_amd import mbt
+    h = mbt.mbt_ctx_create(0)
+    yield h
+    mbt.mbt_ctx_destroy(h)
+
+
+# (nx, ny, M, nc): small, margin larger than the elements, a large block, and one
+# whose element count takes the split-K path of the Z_B product (N_A > 2048)
+CASES = [(3, 2, 7, 10), (2, 2, 5, 40), (5, 3, 48, 33), (8, 8, 40, 24)]
+
+
+def _make(mbt, ctx, case, seed):
+    nx, ny, M, nc = case
+    T = W.synthetic_blocks(nx, ny, M, seed=seed)
+    ZB, ZC = W.synthetic_margin(nx, ny, M, nc, seed=seed)
+    return T, ZB, ZC, mbt.mbt_array_create_margin(ctx, T, ZB, ZC)
+
+
+@pytest.mark.parametrize("case", CASES, ids=["%dx%d_m%d_c%d" % c for c in CASES])
+def test_margin_matvec_matches_dense(ctx, case):
+    from paper_2608_17844_amd import mbt
+    nx, ny, M, nc = case
+    T, ZB, ZC, a = _make(mbt, ctx, case, seed=M + nc)
+    try:
+        info = mbt.mbt_array_info(a)
+        assert info["N"] == nx * ny * M + nc
+        Z = omg.dense(T, nx, ny, ZB, ZC)
+        x = W.random_vectors(Z.shape[0], 13, seed=2)
+        for prec, tol in ((0, 1e-13), (1, 3e-6)):
+            for op in (0, 1, 2):
+                y = mbt.mbt_dbg_matvec(ctx, a, 1.0, x, op=op, prec=prec)
+                ref = Z @ x if op == 0 else (Z.conj().T @ x if op == 1 else Z.conj().T @ (Z @ x))
+                err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+                _say("%s prec=%d op=%d err=%.2e" % (case, prec, op, err))
+                assert err <= tol
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=["%dx%d_m%d_c%d" % c for c in CASES[:3]])
+def test_margin_preconditioners(ctx, case):
+    from paper_2608_17844_amd import mbt
+    nx, ny, M, nc = case
+    T, ZB, ZC, a = _make(mbt, ctx, case, seed=3 * M + nc)
+    try:
+        x = W.random_vectors(nx * ny * M + nc, 3, seed=4)
+        for kind, code in (("normal_eq", mbt.MBT_PC_NORMAL_EQ), ("element_block", mbt.MBT_PC_ELEMENT_BLOCK)):
+            sysm = omg.MarginSystem(T, nx, ny, ZB, ZC, kind)
+            y = mbt.mbt_dbg_precond_apply(ctx, a, 1.0, x, code)
+            ref = np.stack([sysm.pinv(x[:, j]) for j in range(3)], axis=1)
+            err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+            _say("%s %s P^-1 err %.2e" % (case, kind, err))
+            assert err <= 1e-11
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+def _parity(gpu, ref):
+    if gpu == ref.iters:
+        return True
+    k = min(gpu, ref.iters)
+    thr = 1e-10 * ref.restart_residuals[0]
+    return abs(gpu - ref.iters) == 1 and abs(ref.history[k - 1] / thr - 1.0) < 1e-8
+
+
+@pytest.mark.parametrize("kind", ["normal_eq", "element_block"])
+def test_margin_gmres_parity_and_admittance(ctx, kind):
+    """FP64 GMRES on the margin array: per-RHS step counts against the oracle's
+    GMRES on the same system, the port currents against LU; the mixed path
+    (FP32 inner solves, FP64 refinement) against LU too."""
+    from paper_2608_17844_amd import mbt
+    case = (4, 3, 7, 18)
+    nx, ny, M, nc = case
+    T, ZB, ZC, a = _make(mbt, ctx, case, seed=21)
+    try:
+        code = mbt.MBT_PC_NORMAL_EQ if kind == "normal_eq" else mbt.MBT_PC_ELEMENT_BLOCK
+        ports = list(range(nx * ny))
+        sysm = omg.MarginSystem(T, nx, ny, ZB, ZC, kind)
+        V = omg.excitation(nx, ny, M, nc, ports)
+        I_lu = mom.solve_lu(sysm.Z, V)
+        Yref = I_lu[np.array(ports) * M + (M - 1) // 2, :]
+        _, res = og.gmres_all(sysm, V, restart=20, tol=1e-10, orth="dcgs2")
+        opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=code, restart=20, tol=1e-10)
+        Y, iters, st = mbt.mbt_port_admittance(ctx, a, 1.0, ports, opts)
+        _say("%s gpu %s oracle %s" % (kind, list(int(v) for v in iters), [r.iters for r in res]))
+        bad = [(j, int(iters[j]), r.iters) for j, r in enumerate(res) if not _parity(int(iters[j]), r)]
+        assert not bad, bad
+        err = np.linalg.norm(Y - Yref) / np.linalg.norm(Yref)
+        o32 = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=code, restart=20, refine_tol=1e-11, refine_max=6)
+        Y32, _, st32 = mbt.mbt_port_admittance(ctx, a, 1.0, ports, o32)
+        err32 = np.linalg.norm(Y32 - Yref) / np.linalg.norm(Yref)
+        _say("%s admittance fp64 %.2e fp32 %.2e (outer %d)" % (kind, err, err32, st32["outer_steps"]))
+        assert err <= 1e-9 and err32 <= 1e-9
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+def test_margin_pcg_and_port_impedance(ctx):
+    """The paper's PCG on the normal equations of eq. (Z2) with P = blkdiag(P_A, P_C),
+    FP64 and mixed, and Z_p = Y_p^{-1} against the LU oracle."""
+    from paper_2608_17844_amd import mbt
+    case = (5, 4, 9, 30)
+    nx, ny, M, nc = case
+    T, ZB, ZC, a = _make(mbt, ctx, case, seed=5)
+    try:
+        Z = omg.dense(T, nx, ny, ZB, ZC)
+        P = nx * ny
+        V = omg.excitation(nx, ny, M, nc, list(range(P)))
+        I_lu = mom.solve_lu(Z, V)
+        Yp = I_lu[np.arange(P) * M + (M - 1) // 2, :]
+        Zp_ref = np.linalg.inv(Yp)
+        for prec in (mbt.MBT_FP64, mbt.MBT_FP32):
+            opts = mbt.mbt_default_opts(prec=prec, pc=mbt.MBT_PC_NORMAL_EQ, tol=1e-12, restart=50, max_cycles=40,
+                                        refine_tol=1e-11, refine_max=6, flags=mbt.MBT_FLAG_PCG)
+            Zp, st = mbt.mbt_port_impedance(ctx, a, 1.0, opts)
+            err = np.linalg.norm(Zp - Zp_ref) / np.linalg.norm(Zp_ref)
+            _say("pcg prec=%d |dZp|/|Zp| %.2e iters %d" % (prec, err, st["iters_max"]))
+            assert err <= 1e-9
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+def test_margin_limits(ctx):
+    from paper_2608_17844_amd import mbt
+    T, ZB, ZC, a = _make(mbt, ctx, (2, 2, 5, 6), seed=1)
+    try:
+        with pytest.raises(mbt.MbtError) as e:
+            mbt.mbt_port_admittance(ctx, a, 1.0, [0], mbt.mbt_default_opts(prec=mbt.MBT_BF16))
+        assert e.value.status == mbt.MBT_EINVAL
+    finally:
+        mbt.mbt_array_destroy(a)
+    with pytest.raises(mbt.MbtError) as e:
+        mbt.mbt_array_create_margin(ctx, T, ZB, np.full((6, 6), np.nan, complex))
+    assert e.value.status == mbt.MBT_EINVAL

@@ -712,3 +712,64 @@ def test_ideal_s_matrix_and_xi_s_closed_forms():
     p, q, z0, zcc = 0.1 + 0.2j, -0.05 + 0.03j, 50.0, 80 + 20j
     z12 = z0 / 2 * ((1 + p + q) / (1 - p - q) - (1 + p - q) / (1 - p + q))
     assert abs(opr.xi_s(lat2, 1.0, p, q, zcc, z0) - abs(z12) / abs(zcc)) < 1e-14
+
+
+# ----------------------------------------------------------------- arrays with a margin (eq. (Zblock), (Z2))
+
+from oracle import margin as omg  # noqa: E402
+
+
+def _margin_case(nx=3, ny=2, M=5, nc=9, seed=4):
+    T = W.synthetic_blocks(nx, ny, M, seed=seed)
+    ZB, ZC = W.synthetic_margin(nx, ny, M, nc, seed=seed)
+    return T, ZB, ZC
+
+
+def test_margin_matrix_layout_and_reciprocity():
+    T, ZB, ZC = _margin_case()
+    Z = omg.dense(T, 3, 2, ZB, ZC)
+    NA = 3 * 2 * 5
+    assert np.array_equal(Z[NA:, :NA], ZB) and np.array_equal(Z[:NA, NA:], ZB.T)
+    assert np.array_equal(Z[NA:, NA:], ZC)
+    assert np.linalg.norm(Z - Z.T) < 1e-15 * np.linalg.norm(Z)     # reciprocal blocks and symmetric Z_C
+    assert np.linalg.matrix_rank(ZB, tol=1e-12 * np.abs(ZB).max()) == 6
+
+
+def test_normal_equations_blocks_of_eq_z2():
+    """The four blocks of Z^H Z written in eq. (Z2) against the explicit product."""
+    T, ZB, ZC = _margin_case(nx=2, ny=3, M=4, nc=7, seed=9)
+    Z = omg.dense(T, 2, 3, ZB, ZC)
+    NA = 2 * 3 * 4
+    ZA = Z[:NA, :NA]
+    N2 = Z.conj().T @ Z
+    blocks = [[ZA.conj().T @ ZA + ZB.conj().T @ ZB, ZA.conj().T @ ZB.T + ZB.conj().T @ ZC],
+              [ZB.conj() @ ZA + ZC.conj().T @ ZB, ZB.conj() @ ZB.T + ZC.conj().T @ ZC]]
+    assert np.allclose(np.block(blocks), N2, rtol=0, atol=1e-13 * np.abs(N2).max())
+    # P_C is the lower-right block of Z^H Z; P_A leaves out the Z_B^H Z_B part of the upper-left blocks
+    assert np.allclose(omg.pc_block(ZB, ZC), N2[NA:, NA:], atol=1e-13 * np.abs(N2).max())
+    pa = omg.pa_blocks(ZA, 6, 4)
+    full = [N2[e * 4:(e + 1) * 4, e * 4:(e + 1) * 4] for e in range(6)]
+    part = [(ZB.conj().T @ ZB)[e * 4:(e + 1) * 4, e * 4:(e + 1) * 4] for e in range(6)]
+    for e in range(6):
+        assert np.allclose(pa[e] + part[e], full[e], atol=1e-13 * np.abs(full[e]).max())
+        assert np.abs(part[e]).max() > 1e-6 * np.abs(full[e]).max()
+
+
+@pytest.mark.parametrize("kind", ["normal_eq", "element_block"])
+def test_margin_gmres_and_pcg_reach_the_lu_solution(kind):
+    T, ZB, ZC = _margin_case(nx=3, ny=3, M=5, nc=12, seed=2)
+    sysm = omg.MarginSystem(T, 3, 3, ZB, ZC, kind)
+    V = omg.excitation(3, 3, 5, 12, [0, 4, 8])
+    I_lu = mom.solve_lu(sysm.Z, V)
+    I, res = og.gmres_all(sysm, V, restart=30, tol=1e-12, orth="dcgs2")
+    assert all(r.converged for r in res)
+    assert np.linalg.norm(I - I_lu) <= 1e-9 * np.linalg.norm(I_lu)
+    if kind == "normal_eq":
+        ZH = sysm.Z.conj().T
+        for j in range(3):
+            r = og.pcg(lambda v: ZH @ (sysm.Z @ v), sysm.pinv, ZH @ V[:, j], tol=1e-12)
+            assert r.converged and np.linalg.norm(r.x - I_lu[:, j]) <= 1e-8 * np.linalg.norm(I_lu[:, j])
+        # the preconditioned spectrum is real and positive (P and Z^H Z Hermitian, P positive definite)
+        A = np.stack([sysm.apply(e) for e in np.eye(sysm.Z.shape[0], dtype=complex)], axis=1)
+        lam = np.linalg.eigvals(A)
+        assert np.max(np.abs(lam.imag)) < 1e-9 * np.max(lam.real) and lam.real.min() > 0
