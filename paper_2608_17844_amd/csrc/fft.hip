@@ -380,8 +380,10 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_fwd_reg_kernel(co
 // Phase A: thread (bin b, column w) inverse-transforms the two y-parity
 // columns of bin b and sums them with their twiddles.  Phase B: thread (row iy,
 // column w) inverse-transforms the row and accumulates the x-parity with its
-// twiddle; only rows iy < ny and columns ix < nx are written.
-template <typename T, int LX, int LY, int W>
+// twiddle; only rows iy < ny and columns ix < nx are written.  NTL: the
+// spectrum is read with non-temporal loads (it is consumed once, so it need not
+// displace the lines that the next kernel reads from L2).
+template <typename T, int LX, int LY, int W, bool NTL = false>
 __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_inv_reg_kernel(const cplx<T>* __restrict__ Yh,
                                                                               cplx<T>* __restrict__ Y, int nx, int ny,
                                                                               int64_t B, const cplx<T>* __restrict__ twx,
@@ -408,8 +410,16 @@ __global__ __launch_bounds__((LX > LY ? LX : LY) * W) void fft_inv_reg_kernel(co
             for (int al = 0; al < 2; ++al) {
                 C g[LY];
 #pragma unroll
-                for (int a = 0; a < LY; ++a)
-                    g[a] = cv ? Yh[((int64_t)(2 * a + al) * PX + (2 * r + be)) * B + c] : mk<T>(0, 0);
+                for (int a = 0; a < LY; ++a) {
+                    const C* q = Yh + ((int64_t)(2 * a + al) * PX + (2 * r + be)) * B + c;
+                    if (!cv)
+                        g[a] = mk<T>(0, 0);
+                    else if constexpr (NTL)
+                        g[a] = mk<T>(__builtin_nontemporal_load(reinterpret_cast<const T*>(q)),
+                                     __builtin_nontemporal_load(reinterpret_cast<const T*>(q) + 1));
+                    else
+                        g[a] = *q;
+                }
                 fft_reg<T, LY, true>(g, twy);
 #pragma unroll
                 for (int iy = 0; iy < LY; ++iy) acc[iy] = cadd(acc[iy], (al && iy) ? cmul(g[iy], cconj(twy[iy])) : g[iy]);
@@ -701,12 +711,11 @@ void launch_fft_t(const Geom& g, const cplx<T>* in, cplx<T>* out, int64_t B, con
             hipLaunchKernelGGL((fft_fwd_reg_kernel<T, LX, LY, W, kFmtNone>), dim3((unsigned)blocks), dim3(NT), 0, s, in,
                                (void*)out, g.nx, g.ny, B, twx, twy);
         else {
-            // the inverse reads four times what it writes: half-size tiles put two
-            // workgroups on a CU, so one loads while the other transforms (pairs of
-            // workgroups that share 128-byte lines run on one XCD)
-            constexpr int WI = W > 8 ? 8 : W;
-            hipLaunchKernelGGL((fft_inv_reg_kernel<T, LX, LY, WI>), dim3((unsigned)((B + WI - 1) / WI)),
-                               dim3((LX > LY ? LX : LY) * WI), 0, s, in, out, g.nx, g.ny, B, twx, twy);
+            // the inverse reads four times what it writes and reads each spectrum
+            // value once: full-width tiles with non-temporal loads measured ahead of
+            // half-width tiles (two workgroups per CU) with either kind of load
+            hipLaunchKernelGGL((fft_inv_reg_kernel<T, LX, LY, W, true>), dim3((unsigned)blocks),
+                               dim3((LX > LY ? LX : LY) * W), 0, s, in, out, g.nx, g.ny, B, twx, twy);
         }
         MBT_LAUNCH_CHECK();
         return;

@@ -312,6 +312,8 @@ __global__ __launch_bounds__(NW * 64) void arnoldi_kernel(const TB* __restrict__
 }
 
 // ------------------------------------------------------------------ delayed reorthogonalisation (DCGS2)
+constexpr int kDotRows = 16;   // rows of u and w staged in LDS per step of the dot sweep
+
 // Dot sweep: with u the candidate (slot k) and w = A u (slot k+1),
 //   s_i = V_i^H u, z_i = V_i^H w (i < k), alpha = u^H u, beta = u^H w.
 // Partials per chunk: [s_0..s_{k-1}, z_0..z_{k-1}, alpha, beta].  One launch
@@ -337,54 +339,67 @@ __global__ __launch_bounds__(NW * 64, (std::is_same<TV, p24x2>::value && G <= 4 
 #pragma unroll
         for (int g = 0; g < G; ++g) as[g][k2] = az[g][k2] = make_double2(0, 0);
     }
-    Raw<TV, RPL> cur[G], nxt[G];
-    Raw<TB, RPL> cu, nu_, cw, nw_;
-    auto load_row = [&](int64_t n, Raw<TV, RPL>(&v)[G], Raw<TB, RPL>& ur, Raw<TB, RPL>& wr) {
-        const int64_t off = n * R + r0;
-        ur.load(u + off);
-        if (HASW) wr.load(w + off);
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int j = wave + NW * g;
-            if (j < nv) v[g].load(V + (int64_t)(i0 + j) * vstride + vofs<TV>(off));
-            else v[g].zero();
-        }
-    };
+    // Every wave of the workgroup needs the same rows of u and w: they are staged
+    // in LDS kDotRows rows at a time by all threads, so each value is read from
+    // memory once per workgroup (waves reading them independently drift apart
+    // over the chunk and re-fetch lines that the basis stream has evicted).
+    __shared__ Raw<TB, RPL> su[kDotRows][64];
+    __shared__ Raw<TB, RPL> sw[HASW ? kDotRows : 1][64];
     const bool ab_here = (i0 == 0) && (wave == 0);
-    // The packed basis (up to four vectors per wave) loads each row when it is
-    // used and runs four waves per SIMD, whose interleaving hides the load
-    // latency (a register prefetch would limit it to three); the other cases
-    // prefetch the next row.
-    constexpr bool kPrefetch = !(std::is_same<TV, p24x2>::value && G <= 4);
-    if (kPrefetch && live && n0 < n1) load_row(n0, cur, cu, cw);
-    for (int64_t n = n0; n < n1; ++n) {
-        if (live) {
-            if (!kPrefetch) load_row(n, cur, cu, cw);
-            else if (n + 1 < n1) load_row(n + 1, nxt, nu_, nw_);
+    for (int64_t nb = n0; nb < n1; nb += kDotRows) {
+        const int nrow = (int)min((int64_t)kDotRows, n1 - nb);
+        for (int i = threadIdx.x; i < kDotRows * 64; i += NW * 64) {
+            const int rr = i >> 6, l = i & 63;
+            const int c = (blockIdx.x * 64 + l) * RPL;
+            if (rr < nrow && c < R) {
+                su[rr][l].load(u + (nb + rr) * R + c);
+                if (HASW) sw[rr][l].load(w + (nb + rr) * R + c);
+            } else {
+                su[rr][l].zero();
+                if (HASW) sw[rr][l].zero();
+            }
         }
+        __syncthreads();
         if (live) {
-#pragma unroll
-            for (int k2 = 0; k2 < RPL; ++k2) {
-                const double2 uv = cu.get(k2);
-                const double2 wv = HASW ? cw.get(k2) : make_double2(0, 0);
+            // the packed basis (up to four vectors per wave) runs four waves per SIMD and loads each
+            // row when it is used; the other cases prefetch the next row of the block
+            constexpr bool kPrefetch = !(std::is_same<TV, p24x2>::value && G <= 4);
+            Raw<TV, RPL> cur[G], nxt[G];
+            auto load_row = [&](int rr, Raw<TV, RPL>(&v)[G]) {
+                const int64_t off = (nb + rr) * R + r0;
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    const double2 vv = cur[g].get(k2);
-                    as[g][k2] = cfmac(as[g][k2], vv, uv);
-                    if (HASW) az[g][k2] = cfmac(az[g][k2], vv, wv);
+                    const int j = wave + NW * g;
+                    if (j < nv) v[g].load(V + (int64_t)(i0 + j) * vstride + vofs<TV>(off));
+                    else v[g].zero();
                 }
-                if (ab_here) {
-                    aa[k2].x = nfma(aa[k2].x, uv);
-                    if (HASW) ab[k2] = cfmac(ab[k2], uv, wv);
+            };
+            if (kPrefetch) load_row(0, cur);
+            for (int rr = 0; rr < nrow; ++rr) {
+                if (!kPrefetch) load_row(rr, cur);
+                else if (rr + 1 < nrow) load_row(rr + 1, nxt);
+#pragma unroll
+                for (int k2 = 0; k2 < RPL; ++k2) {
+                    const double2 uv = su[rr][lane].get(k2);
+                    const double2 wv = HASW ? sw[rr][lane].get(k2) : make_double2(0, 0);
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const double2 vv = cur[g].get(k2);
+                        as[g][k2] = cfmac(as[g][k2], vv, uv);
+                        if (HASW) az[g][k2] = cfmac(az[g][k2], vv, wv);
+                    }
+                    if (ab_here) {
+                        aa[k2].x = nfma(aa[k2].x, uv);
+                        if (HASW) ab[k2] = cfmac(ab[k2], uv, wv);
+                    }
+                }
+                if (kPrefetch) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) cur[g] = nxt[g];
                 }
             }
         }
-        if (kPrefetch) {
-#pragma unroll
-            for (int g = 0; g < G; ++g) cur[g] = nxt[g];
-            cu = nu_;
-            cw = nw_;
-        }
+        __syncthreads();
     }
     if (!live) return;
 #pragma unroll
