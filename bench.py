@@ -118,6 +118,42 @@ def cpu_baseline(w, side=20):
             "phases_s": {"fill": t_fill, "lu": t_lu, "solve": t_solve, "extract": t_ext}}
 
 
+CPU_FULL_PROFILE = os.path.join(ROOT, "profiles", "cpu_oracle_dipole_32x32_m31.txt")
+
+
+def cpu_full(args):
+    """The CPU oracle on the whole 32x32 workload (N = 31,744, all 1024 ports):
+    dense fill, zgetrf, zgetrs of the 1024 port columns and the extraction, each
+    timed, beside the bounded-sample extrapolation of two sample sizes on the
+    same host (20x20 and 24x24 lattices scaled by fill N^2, LU N^3, solve N^2 P)."""
+    import platform
+    from oracle import mom
+    from paper_2608_17844_amd import workloads as W
+    w = W.gpu_size_32x32()
+    samples = {str(side): cpu_baseline(w, side) for side in (20, 24)}
+    log("cpu oracle, full 32x32 workload")
+    r = mom.solve_array(w.lattice, w.dipole, 1.0, w.theta, w.phi, z0=w.z0)
+    total = sum(r.times.values())
+    P = w.lattice.nx * w.lattice.ny
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"metric": "CPU oracle solves/s, 32x32 dipoles (dense fill + LAPACK LU)", "value": P / total,
+            "unit": "solves/s", "phases_s": r.times, "total_s": total,
+            "host": platform.processor() or platform.machine(), "cores": cores,
+            "threads": int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", cores))),
+            "samples": {k: {"value": v["value"], "phases_s": v["phases_s"],
+                            "error_vs_measured": v["value"] / (P / total) - 1.0} for k, v in samples.items()}}
+
+
+def measured_full_cpu():
+    """The full-size oracle run recorded in profiles/ (host, threads, phases)."""
+    if not os.path.exists(CPU_FULL_PROFILE):
+        return None
+    for line in open(CPU_FULL_PROFILE):
+        if line.startswith("{"):
+            return json.loads(line)
+    return None
+
+
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_dcgs2_update_dipole_32x32_m31_fp32.txt")
 
 
@@ -262,6 +298,14 @@ def headline(args):
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, bounded sample)")
         result["cpu_baseline"] = cpu_baseline(w)
+        full = measured_full_cpu()
+        if full:
+            # the whole workload measured on another host (the oracle takes minutes there)
+            result["cpu_baseline"]["measured_full"] = {
+                "value": full["value"], "unit": "solves/s", "host": full["host"], "threads": full["threads"],
+                "phases_s": full["phases_s"], "source": os.path.relpath(CPU_FULL_PROFILE, ROOT),
+                "sample_extrapolation_error_on_that_host": {k: v["error_vs_measured"]
+                                                            for k, v in full["samples"].items()}}
     else:
         result["cpu_baseline"] = None
     return result
@@ -289,8 +333,9 @@ def serve(args):
     def solves(r):
         return r.lattice.nx * r.lattice.ny * len(r.freqs)
 
-    def collect(tickets, reqs, t0):
-        """Results in submission order; each is logged as it completes."""
+    def collect(tickets, reqs, t0, keep=()):
+        """Results in submission order; each is logged as it completes.  Only
+        the requests in `keep` retain their Z_p (the rest drop it on arrival)."""
         out = [None] * len(tickets)
         pending = list(range(len(tickets)))
         while pending:
@@ -300,6 +345,8 @@ def serve(args):
                 if x is None:
                     still.append(i)
                     continue
+                if i not in keep:
+                    x["Zp"] = None
                 out[i] = x
                 r = reqs[i]
                 log("  request %d (%dx%d, M=%d, %d freq, %d scans) status %d, latency %.2f s, iters %s, at %.1f s" % (
@@ -314,28 +361,44 @@ def serve(args):
         warm = W.serving_stream(args.serve_warmup, 0.0, seed=1)
         log("serving: warm-up with %d requests" % len(warm))
         collect([submit(r) for r in warm], warm, mbt.mbt_server_clock(srv))
-        reqs = W.serving_stream(args.serve, 1.0, seed=0)
-        log("serving: saturation run, %d requests submitted at once" % len(reqs))
-        t0 = mbt.mbt_server_clock(srv)
-        tickets = [submit(r) for r in reqs]
-        res = collect(tickets, reqs, t0)
-        t_sat = max(x["t_done"] for x in res) - t0
-        sat_rate = len(reqs) / t_sat
-        sat_solves = sum(solves(r) for r in reqs) / t_sat
-        bad = sum(1 for x in res if x["status"] != mbt.MBT_OK)
-        log("serving: saturation %.2f requests/s, %.1f solves/s (%d not converged)" % (sat_rate, sat_solves, bad))
+        sat_n = args.serve_saturation if args.serve_saturation > 0 else args.serve
+        if args.serve_rate > 0:
+            sat_rate, sat_solves, bad = args.serve_rate, None, None
+            log("serving: saturation rate given: %.3f requests/s" % sat_rate)
+        else:
+            reqs = W.serving_stream(sat_n, 1.0, seed=0)
+            log("serving: saturation run, %d requests submitted at once" % len(reqs))
+            t0 = mbt.mbt_server_clock(srv)
+            tickets = [submit(r) for r in reqs]
+            res = collect(tickets, reqs, t0)
+            t_sat = max(x["t_done"] for x in res) - t0
+            okm = [x["status"] == mbt.MBT_OK for x in res]
+            sat_rate = len(reqs) / t_sat
+            sat_solves = sum(solves(r) for r, g in zip(reqs, okm) if g) / t_sat
+            bad = int(len(res) - sum(okm))
+            log("serving: saturation %.3f requests/s, %.1f solves/s of converged requests (%d not converged)" % (
+                sat_rate, sat_solves, bad))
         loads = [float(v) for v in str(args.load).split(",")]
 
         def summary(res, reqs, t0):
-            lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
-            wait = np.array([x["t_start"] - x["t_submit"] for x in res]) * 1e3
+            """Throughput and latency count only requests that met the accuracy
+            target (status MBT_OK); unconverged ones are reported beside them."""
+            ok = [x["status"] == mbt.MBT_OK for x in res]
+            lat = np.array([x["t_done"] - x["t_submit"] for x, g in zip(res, ok) if g]) * 1e3
+            wait = np.array([x["t_start"] - x["t_submit"] for x, g in zip(res, ok) if g]) * 1e3
+            lat_all = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
             span = max(x["t_done"] for x in res) - t0
-            return {"solves_per_s": sum(solves(r) for r in reqs) / span, "span_s": span,
+            return {"solves_per_s": sum(solves(r) for r, g in zip(reqs, ok) if g) / span, "span_s": span,
+                    "solves_per_s_incl_unconverged": sum(solves(r) for r in reqs) / span,
+                    "requests_ok": int(sum(ok)), "requests": len(res),
                     "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                                   "mean": float(lat.mean()), "queue_wait_p50": float(np.percentile(wait, 50))},
-                    "not_converged": sum(1 for x in res if x["status"] != mbt.MBT_OK)}
+                                   "mean": float(lat.mean()), "queue_wait_p50": float(np.percentile(wait, 50)),
+                                   "p99_incl_unconverged": float(np.percentile(lat_all, 99))},
+                    "not_converged": int(len(res) - sum(ok)),
+                    "not_converged_requests": [i for i, g in enumerate(ok) if not g]}
 
         runs = []
+        checks = {}
         if not any(load > 0 for load in loads):
             # the latencies reported are those of the saturation run
             runs.append(dict(summary(res, reqs, t0), load_vs_saturation=0.0, rate_rps=None))
@@ -344,7 +407,14 @@ def serve(args):
                 continue
             rate = load * sat_rate
             reqs = W.serving_stream(args.serve, rate, seed=0)
-            log("serving: Poisson stream at %.3f requests/s (%.0f%% of saturation)" % (rate, 100 * load))
+            # a seeded sample of requests small enough for the dense CPU oracle, and one of them
+            # re-served alone afterwards for the alone-versus-in-the-mix comparison
+            small = [i for i, r in enumerate(reqs) if r.lattice.nx * r.lattice.ny * r.dipole.nbases <= 12000]
+            rng = np.random.default_rng(5)
+            keep = set(int(i) for i in rng.choice(small, size=min(args.serve_verify, len(small)), replace=False)) \
+                if args.serve_verify > 0 and small else set()
+            log("serving: Poisson stream at %.3f requests/s (%.0f%% of saturation), %d requests" % (
+                rate, 100 * load, len(reqs)))
             t0 = mbt.mbt_server_clock(srv)
             tickets = []
             for r in reqs:
@@ -352,11 +422,14 @@ def serve(args):
                 if dt > 0:
                     time.sleep(dt)
                 tickets.append(submit(r))
-            res = collect(tickets, reqs, t0)
+            res = collect(tickets, reqs, t0, keep)
             runs.append(dict(summary(res, reqs, t0), load_vs_saturation=load, rate_rps=rate))
-            log("serving: load %.2f: %.1f solves/s, p50 %.1f s, p99 %.1f s" % (
-                load, runs[-1]["solves_per_s"], runs[-1]["latency_ms"]["p50"] / 1e3,
-                runs[-1]["latency_ms"]["p99"] / 1e3))
+            log("serving: load %.2f: %.1f solves/s (converged requests), %d of %d converged, p50 %.1f s, "
+                "p99 %.1f s" % (load, runs[-1]["solves_per_s"], runs[-1]["requests_ok"], len(reqs),
+                                runs[-1]["latency_ms"]["p50"] / 1e3, runs[-1]["latency_ms"]["p99"] / 1e3))
+            if keep and not checks:
+                checks = verify_served(mbt, srv, submit, collect, reqs, res, sorted(keep))
+                log("serving: verification %s" % checks)
     finally:
         mbt.mbt_server_destroy(srv)
         mbt.mbt_ctx_destroy(ctx)
@@ -371,8 +444,43 @@ def serve(args):
                        "restart": args.restart, "refine_tol": args.refine_tol, "inner_tol": args.inner_tol,
                        "max_cycles": args.serve_max_cycles},
             "latency_ms": head["latency_ms"],
-            "saturation": {"requests_per_s": sat_rate, "solves_per_s": sat_solves, "not_converged": bad},
-            "not_converged": head["not_converged"], "span_s": head["span_s"], "loads": runs}
+            "saturation": {"requests_per_s": sat_rate, "solves_per_s": sat_solves, "not_converged": bad,
+                           "requests": sat_n if args.serve_rate <= 0 else None},
+            "not_converged": head["not_converged"], "span_s": head["span_s"], "loads": runs,
+            "verification": checks}
+
+
+def verify_served(mbt, srv, submit, collect, reqs, res, ids):
+    """Served results of a seeded sample of the stream against the dense CPU
+    oracle (every frequency: Z_p norm-wise and entry-wise, the ARC), and the
+    first sampled request served again alone, compared bit for bit with its
+    result from inside the stream."""
+    from oracle import mom
+    out = {"requests": [], "target": 1e-6}
+    worst = 0.0
+    for i in ids:
+        r, x = reqs[i], res[i]
+        if x["status"] != mbt.MBT_OK:
+            out["requests"].append({"id": i, "status": int(x["status"])})
+            continue
+        ez, ee, eg = [], [], []
+        for fi, s in enumerate(r.freqs):
+            o = mom.solve_array(r.lattice, r.dipole, s, r.theta, r.phi, z0=r.z0)
+            d = x["Zp"][fi] - o.Zp
+            ez.append(float(np.linalg.norm(d) / np.linalg.norm(o.Zp)))
+            ee.append(float(np.max(np.abs(d)) / np.max(np.abs(o.Zp))))
+            eg.append(float(np.max(np.abs(x["Gamma"][fi] - o.Gamma) / np.maximum(1.0, np.abs(o.Gamma)))))
+        worst = max(worst, max(ez), max(ee))
+        out["requests"].append({"id": i, "nx": r.lattice.nx, "ny": r.lattice.ny, "nbases": r.dipole.nbases,
+                                "freqs": list(r.freqs), "zp_rel": max(ez), "zp_max_entry_rel": max(ee),
+                                "gamma_rel": max(eg)})
+    out["zp_worst"] = worst
+    out["meets_target"] = bool(worst <= 1e-6)
+    j = ids[0]
+    alone = collect([submit(reqs[j])], [reqs[j]], mbt.mbt_server_clock(srv), keep={0})[0]
+    same = all(np.array_equal(alone[k], res[j][k]) for k in ("Zp", "Za", "Gamma", "Gamma_wave"))
+    out["alone_vs_mix"] = {"id": j, "bit_identical": bool(same)}
+    return out
 
 
 def blocks_shape(args):
@@ -630,7 +738,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-kernel-table", action="store_true")
     ap.add_argument("--serve", type=int, default=0, help="run the serving stream with this many requests instead")
-    ap.add_argument("--serve-warmup", type=int, default=4)
+    ap.add_argument("--serve-warmup", type=int, default=20)
+    ap.add_argument("--serve-saturation", type=int, default=0,
+                    help="requests of the saturation run (default: as many as the stream)")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="use this saturation rate (requests/s) instead of measuring it")
+    ap.add_argument("--serve-verify", type=int, default=3,
+                    help="served requests checked against the dense CPU oracle (and one re-served alone)")
     ap.add_argument("--serve-max-cycles", type=int, default=8,
                     help="restart cycles per inner solve in the serving run (slow-converging requests report ENOCONV)")
     ap.add_argument("--slots", type=int, default=4)
@@ -647,6 +761,8 @@ def main():
                     help="run the coupling-predictor sweep over N x N arrays up to this N (odd) instead")
     ap.add_argument("--predict-freq", type=float, default=1.1,
                     help="frequency ratio of the predictor sweep (1.1: spacing 0.55 wavelengths)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the CPU oracle on the whole 32x32 workload (minutes; no GPU) instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy kernel three times (a known-size reference "
                          "for hardware traffic counters)")
@@ -676,6 +792,8 @@ def main():
         result = blocks_shape(args)
     elif args.predict > 0:
         result = predict(args)
+    elif args.cpu_full:
+        result = cpu_full(args)
     else:
         result = headline(args)
     print(json.dumps(result), flush=True)
