@@ -142,6 +142,96 @@ def synthetic_margin(nx: int, ny: int, nbases: int, nmargin: int, seed: int = 0,
     return ZB, ZC
 
 
+@dataclass(frozen=True)
+class PlanarMesh:
+    """Triangle mesh of one planar element in the plane z = 0, in its own frame
+    (wavelengths at f0): vertices (nv, 2), triangles (nt, 3) as counterclockwise
+    vertex-index triples, the feed-gap edges (ne, 2) as vertex-index pairs, and
+    the direction of the gap field in the element plane."""
+    vertices: np.ndarray
+    triangles: np.ndarray
+    port_edges: np.ndarray
+    port_dir: Tuple[float, float] = (1.0, 0.0)
+
+
+def _strip_between(a: List[int], ta: np.ndarray, b: List[int], tb: np.ndarray) -> List[Tuple[int, int, int]]:
+    """Triangles joining two node rows (node ids a, b at parameters ta, tb in
+    [0, 1] across the strip): walk both rows and always advance on the row whose
+    next node comes first."""
+    out = []
+    i = k = 0
+    while i < len(a) - 1 or k < len(b) - 1:
+        if k == len(b) - 1 or (i < len(a) - 1 and ta[i + 1] <= tb[k + 1]):
+            out.append((a[i], a[i + 1], b[k]))
+            i += 1
+        else:
+            out.append((a[i], b[k + 1], b[k]))
+            k += 1
+    return out
+
+
+def _ccw(vert: np.ndarray, tris: List[Tuple[int, int, int]]) -> np.ndarray:
+    t = np.array(tris, dtype=np.int32)
+    p, q, r = vert[t[:, 0]], vert[t[:, 1]], vert[t[:, 2]]
+    cross = (q[:, 0] - p[:, 0]) * (r[:, 1] - p[:, 1]) - (q[:, 1] - p[:, 1]) * (r[:, 0] - p[:, 0])
+    t[cross < 0] = t[cross < 0][:, [0, 2, 1]]
+    return t
+
+
+def bowtie_mesh(span: float = 0.45, flare_deg: float = 60.0, feed_width: float = 0.04,
+                counts: Tuple[int, ...] = (3, 4, 4, 5, 6, 6)) -> PlanarMesh:
+    """Planar bowtie along x: two wings of full flare angle `flare_deg` joined on
+    the feed line x = 0 of width `feed_width`, tip to tip `span`.  Each wing is a
+    structured mesh of node rows at x_j = +-(span/2) j/s (j = 0..s, s =
+    len(counts) - 1) with counts[j] nodes spread evenly over the wing width
+    feed_width + 2|x_j| tan(flare/2); row 0 is the shared feed line, whose edges
+    are the port.  The default has 74 triangles and 96 interior edges."""
+    s = len(counts) - 1
+    half = np.tan(np.radians(flare_deg) / 2.0)
+    rows = []
+    vert = []
+    for j in range(-s, s + 1):
+        x = 0.5 * span * j / s
+        c = counts[abs(j)]
+        w = feed_width + 2.0 * abs(x) * half
+        ys = np.linspace(-0.5 * w, 0.5 * w, c)
+        rows.append(list(range(len(vert), len(vert) + c)))
+        vert.extend((x, y) for y in ys)
+    vert = np.array(vert, dtype=np.float64)
+    tris = []
+    for r0, r1 in zip(rows[:-1], rows[1:]):
+        tris += _strip_between(r0, np.linspace(0, 1, len(r0)), r1, np.linspace(0, 1, len(r1)))
+    feed = rows[s]
+    port = np.array([(feed[i], feed[i + 1]) for i in range(len(feed) - 1)], dtype=np.int32)
+    return PlanarMesh(vert, _ccw(vert, tris), port, (1.0, 0.0))
+
+
+def strip_mesh(length: float = 0.5, width: float = 0.02, nseg: int = 20, nacross: int = 1) -> PlanarMesh:
+    """Flat strip dipole along x (length x width), nseg cells along (even, so
+    that x = 0 is a node row) and nacross across, each cell split by its
+    diagonal; the port is the row of edges at x = 0."""
+    if nseg % 2:
+        raise ValueError("nseg must be even")
+    xs = np.linspace(-0.5 * length, 0.5 * length, nseg + 1)
+    ys = np.linspace(-0.5 * width, 0.5 * width, nacross + 1)
+    vert = np.array([(x, y) for x in xs for y in ys], dtype=np.float64)
+    rows = [list(range(i * (nacross + 1), (i + 1) * (nacross + 1))) for i in range(nseg + 1)]
+    tris = []
+    for r0, r1 in zip(rows[:-1], rows[1:]):
+        tris += _strip_between(r0, np.linspace(0, 1, len(r0)), r1, np.linspace(0, 1, len(r1)))
+    feed = rows[nseg // 2]
+    port = np.array([(feed[i], feed[i + 1]) for i in range(len(feed) - 1)], dtype=np.int32)
+    return PlanarMesh(vert, _ccw(vert, tris), port, (1.0, 0.0))
+
+
+def bowtie_64x64_workload():
+    """Largest single-GPU instance: 64 x 64 bowties (96 RWG bases each,
+    N = 393,216) on a 0.5-wavelength square lattice, 32 excitations (broadside
+    first, then seeded scan directions) at 5 frequencies in 0.5-1.5 f0."""
+    theta, phi = scan_angles(32, seed=5, broadside_first=True)
+    return bowtie_mesh(), Lattice(64, 64, 0.5, 0.5), np.linspace(0.5, 1.5, 5), theta, phi
+
+
 @dataclass
 class Request:
     """One serving request: an array, its frequencies and its scan set."""
