@@ -197,31 +197,39 @@ def green_smooth(k: float, R: np.ndarray) -> np.ndarray:
 
 
 def pair_integrals(k: float, test_xy: np.ndarray, src_xy: np.ndarray, near: np.ndarray):
-    """For one test triangle (3, 2) and source triangles (n, 3, 2):
-    I0 = <<G>>, Ir = <<r G>> (n, 2), Irp = <<r' G>> (n, 2), Irr = <<r . r' G>>,
-    double surface integrals over test x source; near[j] selects the closed-form
-    static part for source j."""
+    """For one test triangle (3, 2) and source triangles (n, 3, 2), with c and
+    c' the test and source centroids:
+    I0 = <<G>>, Ir = <<(r - c) G>> (n, 2), Irp = <<(r' - c') G>> (n, 2),
+    Irr = <<(r - c) . (r' - c') G>>, double surface integrals over test x source
+    (positions taken from the centroids so that no large coordinate cancels);
+    near[j] selects the closed-form static part for source j.  Also returns c (2,)
+    and c' (n, 2)."""
     bary, w = rule7()
-    ro = tri_points(test_xy, bary)                    # (7, 2)
-    wo = w * tri_area(test_xy)                        # (7,)
-    rs = tri_points(src_xy, bary)                     # (n, 7, 2)
-    ws = w[None, :] * tri_area(src_xy)[:, None]       # (n, 7)
+    ct = test_xy.mean(axis=0)
+    cs = src_xy.mean(axis=1)                                          # (n, 2)
+    ro_l = tri_points(test_xy - ct, bary)                             # (7, 2) from the test centroid
+    rs_l = tri_points(src_xy - cs[:, None, :], bary)                  # (n, 7, 2) from each source centroid
+    ro = ro_l + ct
+    rs = rs_l + cs[:, None, :]
+    wo = w * tri_area(test_xy)                                        # (7,)
+    ws = w[None, :] * tri_area(src_xy)[:, None]                       # (n, 7)
     R = np.linalg.norm(ro[None, :, None, :] - rs[:, None, :, :], axis=-1)   # (n, 7o, 7s)
     Gf = np.empty(R.shape, dtype=np.complex128)
     Gf[near] = green_smooth(k, R[near])
     Gf[~near] = green(k, R[~near])
     g0 = np.einsum("nij,nj->ni", Gf, ws)              # inner integral of G at each outer point
-    g1 = np.einsum("nij,nj,njd->nid", Gf, ws, rs)     # inner integral of r' G
+    g1 = np.einsum("nij,nj,njd->nid", Gf, ws, rs_l)   # inner integral of (r' - c') G
     jn = np.nonzero(near)[0]
     if len(jn):
         S0, S1 = static_potentials(src_xy[jn], ro)                       # (nn, 7), (nn, 7, 2)
         g0[jn] += S0 / (4 * np.pi)
-        g1[jn] += (S1 + ro[None] * S0[:, :, None]) / (4 * np.pi)
+        # int (r' - c')/R = S1 + (rho - c') S0
+        g1[jn] += (S1 + (ro[None] - cs[jn][:, None, :]) * S0[:, :, None]) / (4 * np.pi)
     I0 = g0 @ wo
-    Ir = np.einsum("ni,i,id->nd", g0, wo, ro)
+    Ir = np.einsum("ni,i,id->nd", g0, wo, ro_l)
     Irp = np.einsum("nid,i->nd", g1, wo)
-    Irr = np.einsum("nid,i,id->n", g1, wo, ro)
-    return I0, Ir, Irp, Irr
+    Irr = np.einsum("nid,i,id->n", g1, wo, ro_l)
+    return I0, Ir, Irp, Irr, ct, cs
 
 
 # --------------------------------------------------------------------------- fill
@@ -234,7 +242,7 @@ def _assemble_rows(el: RwgElement, k: float, eta: float, t: int, vt: np.ndarray,
                    src_vplus, src_vminus, src_tplus, src_tminus, length_n):
     """Rows of the test bases on triangle t (their contributions from this
     triangle only): dict m -> row over the source bases."""
-    I0, Ir, Irp, Irr = ints
+    I0, Ir, Irp, Irr, ct, cs = ints
     At = el.area[t]
     rows = {}
     for m in range(el.M):
@@ -245,8 +253,11 @@ def _assemble_rows(el: RwgElement, k: float, eta: float, t: int, vt: np.ndarray,
         else:
             continue
         row = np.zeros(len(length_n), dtype=np.complex128)
+        am = vm - ct
         for sn, tn, vn in ((1.0, src_tplus, src_vplus), (-1.0, src_tminus, src_vminus)):
-            A = Irr[tn] - np.einsum("nd,nd->n", vn, Ir[tn]) - Irp[tn] @ vm + (vn @ vm) * I0[tn]
+            # <<(r - v_m) . (r' - v_n) G>> from the centroid moments
+            an = vn - cs[tn]
+            A = Irr[tn] - np.einsum("nd,nd->n", an, Ir[tn]) - Irp[tn] @ am + (an @ am) * I0[tn]
             An = src_tri_area[tn]
             row += sm * sn * el.length[m] * length_n * (
                 1j * k * eta * A / (4 * At * An) - 1j * (eta / k) * I0[tn] / (At * An))
