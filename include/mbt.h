@@ -14,17 +14,21 @@
  * (eq. (ARC)) of the center element, and the wave-excited reflection
  * coefficient from the phased S-sum (Sec. II-E with eq. (S2Z)).
  *
- * Element: a z-directed thin-wire dipole (length, radius in wavelengths at the
+ * Elements: a z-directed thin-wire dipole (length, radius in wavelengths at the
  * reference frequency f0; nbases odd rooftops; port at the center rooftop),
  * filled by Galerkin EFIE with the reduced kernel exp(-jkR)/(4 pi R),
- * R = sqrt(rho^2 + (z-z')^2 + a^2), and 4-point Gauss-Legendre per segment.
+ * R = sqrt(rho^2 + (z-z')^2 + a^2), and 4-point Gauss-Legendre per segment;
+ * or a planar element given by its triangle mesh, discretised with RWG
+ * functions (paper Sec. I, Sec. II-B), port at a delta gap across feed edges
+ * (mbt_array_create_rwg).
  *
  * Conventions
  *  - complex numbers are interleaved FP64 {re, im} pairs (C99 double _Complex,
  *    numpy complex128); a "complex array of n entries" is 2n doubles;
  *  - host matrices are column-major: A[i + ld*j];
  *  - unknown index n = e*M + p, element e = iy*nx + ix at (ix*dx, iy*dy);
- *    port j is element j (its center rooftop p_c = (M-1)/2);
+ *    port j is element j (dipoles and block arrays: its center basis
+ *    p_c = (M-1)/2; RWG elements: the gap across the feed edges);
  *  - the center element is (nx/2, ny/2) (integer division);
  *  - a frequency is the ratio s = f/f0 (wavenumber k = 2 pi s);
  *  - unless stated, pointers are host memory owned by the caller; handles
@@ -167,6 +171,41 @@ mbt_status mbt_array_create_dipole(mbt_ctx* ctx, const mbt_dipole* elem, const m
  * positions).  Errors: MBT_EINVAL (sizes, non-finite values). */
 mbt_status mbt_array_create_blocks(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t nbases, const double* T,
                                    mbt_array** out);
+/* Planar element in the plane z = 0, given by its triangle mesh in the element
+ * frame (wavelengths at f0).  vert: nvert (x, y) pairs; tri: ntri vertex-index
+ * triples; port_edges: nport_edges vertex-index pairs, the edges of the feed
+ * gap; port_dir: direction of the gap field in the element plane.  All copied
+ * at the call. */
+typedef struct {
+    int32_t nvert;
+    const double* vert;
+    int32_t ntri;
+    const int32_t* tri;
+    int32_t nport_edges;
+    const int32_t* port_edges;
+    double port_dir[2];
+} mbt_rwg_mesh;
+
+/* Array of planar elements (paper Sec. I, Sec. II-B: elements discretised with
+ * Rao-Wilton-Glisson functions; the paper gives no fill rules, so these are
+ * this library's).  Basis m is the m-th interior edge (an edge of exactly two
+ * triangles) in increasing (smaller vertex, larger vertex) order, with
+ * f_m = +-(l_m / 2A)(r - v) on its two triangles, + on the lower-index one (v
+ * the vertex opposite the edge).  Blocks: Galerkin EFIE
+ * Z_mn = j k eta <<f_m . f_n, G>> - j (eta/k) <<div f_m, div f_n, G>>,
+ * G = exp(-jkR)/(4 pi R), Radon's seven-point rule on every triangle, and for
+ * elements at most one lattice step apart in x and y the static part of the
+ * source integral in closed form (coplanar potential integrals, Wilton et al.
+ * 1984).  Port: a delta gap; gap voltage V drives basis m of a feed edge with
+ * V sign_m l_m, and the gap current is sum sign_m l_m I_m (sign_m = +1 when the
+ * basis's + -> - direction has a positive component along port_dir); Y_p and
+ * Z_p are in these gap voltages and currents.  Limits: 1..128 interior edges,
+ * 2..256 triangles, 3..4096 vertices, 1..8 feed edges, nx, ny 1..64; 16-bit
+ * products only up to 32 bases.  Errors: MBT_EINVAL (sizes, non-finite or
+ * degenerate geometry, an edge of more than two triangles, a feed edge that is
+ * not interior or is parallel to port_dir). */
+mbt_status mbt_array_create_rwg(mbt_ctx* ctx, const mbt_rwg_mesh* mesh, const mbt_lattice* lat, mbt_array** out);
+
 /* Array whose impedance matrix has a margin besides its elements (Sec. II-A
  * eq. (Zblock)): Z = [[Z_A, Z_B^T], [Z_B, Z_C]], Z_A the block-Toeplitz element
  * interaction given by its unique blocks T as in mbt_array_create_blocks, and
@@ -231,6 +270,23 @@ mbt_status mbt_port_impedance(mbt_ctx* ctx, const mbt_array* arr, double freq_ra
 mbt_status mbt_solve(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, const mbt_solve_opts* opts,
                      const double* theta, const double* phi, int32_t nscan, double z0, double* Zp,
                      double* Za, double* Gamma, double* Gamma_wave, mbt_stats* stats);
+
+/* Phased voltage excitation (Sec. II-D eq. (eqProb) with V built from the
+ * scan phases of Sec. II-E): for each of the nscan directions every port gap is
+ * driven with V_e = exp(-j k (x_e u + y_e v)), u = sin(theta) cos(phi),
+ * v = sin(theta) sin(phi) (the main beam at (theta, phi) under the fill's
+ * exp(-jkR) kernel), Z I = V is solved, and the outputs are the gap currents Ip
+ * (P x nscan complex, column-major; may be NULL), the active impedance of
+ * element `center` (< 0: (nx/2, ny/2)) Za = V_c / Ip_c (eq. (actZ) for the port
+ * currents this excitation produces) and its ARC Gamma = (Za - z0)/(Za + z0)
+ * (eq. (ARC)), nscan complex each.  One solve per direction, no full Z_p: the
+ * form for arrays too large for all-port excitation.  iters (nscan, may be
+ * NULL) receives per-direction iteration counts.  Errors: MBT_EINVAL (NULL
+ * argument, nscan < 1, non-finite angle, center out of range, block-defined
+ * array), MBT_ENOMEM, MBT_ENOCONV, MBT_EBREAKDOWN, MBT_EDEVICE. */
+mbt_status mbt_scan_solve(mbt_ctx* ctx, const mbt_array* arr, double freq_ratio, const mbt_solve_opts* opts,
+                          const double* theta, const double* phi, int32_t nscan, double z0, int32_t center,
+                          double* Ip, double* Za, double* Gamma, int32_t* iters, mbt_stats* stats);
 
 /* Scan quantities from a given Z_p (host, P x P, column-major): Za
  * (eqs. (actZ), (actZmat)), Gamma (eq. (ARC)) and Gamma_wave (Sec. II-E, S from

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmbt.so")
 SOURCES = ["fill.hip", "fft.hip", "cgemm.hip", "precond.hip", "vec.hip", "gmres.hip", "extract.hip",
-           "runtime.hip", "server.hip", "prof.hip", "predict.hip", "margin.hip"]
+           "runtime.hip", "server.hip", "prof.hip", "predict.hip", "margin.hip", "rwg.hip"]
 ARCH = os.environ.get("MBT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -134,6 +134,15 @@ class ProfScope {
 constexpr int kMaxBlockM = 128;
 
 // ------------------------------------------------------------------ geometry
+// The port of an element: the bases its gap drives and their weights.  A gap
+// voltage V puts V * w[i] on basis idx[i]; the gap current is sum_i w[i] I[idx[i]].
+constexpr int kMaxPortBases = 8;
+struct PortDef {
+    int n = 1;
+    int idx[kMaxPortBases] = {0};
+    double w[kMaxPortBases] = {1.0};
+};
+
 struct Geom {
     int nx = 0, ny = 0, M = 0;     // lattice size, bases per element
     double dx = 0, dy = 0;         // lattice spacing (wavelengths at f0)
@@ -145,6 +154,7 @@ struct Geom {
     int nox = 0, noy = 0;          // offsets per axis 2nx-1, 2ny-1
     int pc = 0;                    // port basis (M-1)/2
     int Nc = 0;                    // margin unknowns after the P*M element unknowns (N = P*M + Nc)
+    PortDef port;                  // dipoles and block arrays: basis pc with weight 1
     int64_t NA() const { return (int64_t)P * M; }
     int64_t bins() const { return (int64_t)Px * Py; }
     int64_t noff() const { return (int64_t)nox * noy; }

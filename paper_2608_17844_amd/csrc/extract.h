@@ -20,4 +20,12 @@ void s_matrix_dev_perm(const double2* Zp, double2* S, double2* work, int n, doub
 void scans(const Geom& g, double k, const double2* Zp, const double2* S, int c, const double* theta, const double* phi,
            int nscan, double z0, double2* Za, double2* G, double2* Gw, hipStream_t s);
 
+// Phased voltage excitation of every gap (R columns, layout [n][r]):
+// V = w_i exp(-j k (x_e u + y_e v)) at the port bases of each element e.
+void scan_voltages(const Geom& g, double k, const double* theta, const double* phi, int R, double2* V,
+                   hipStream_t s);
+// Center-element active impedance V_c / I_p,c and ARC from the gap currents Ip (P x nscan, column-major).
+void scan_active(const Geom& g, double k, const double2* Ip, int nscan, int c, const double* theta,
+                 const double* phi, double z0, double2* Za, double2* G, hipStream_t s);
+
 }  // namespace mbt

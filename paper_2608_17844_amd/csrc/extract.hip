@@ -8,7 +8,11 @@
 //   the main beam at (theta, phi) (Sec. II-E), I_j = exp(-j k (x_j u + y_j v))
 //   under the e^{-jkR} kernel of the fill (eqs. (actZ), (actZmat)), its ARC
 //   (eq. (ARC)), and the wave-excited reflection coefficient, the phased S-sum
-//   of Sec. II-E.
+//   of Sec. II-E;
+// * for a phased voltage excitation of every gap, V_j = exp(-j k (x_j u + y_j v))
+//   on the same beam-steering convention, the right-hand sides and, from the
+//   gap currents the solve returns, the center element's active impedance
+//   Z_a,c = V_c / I_p,c (eq. (actZ) with those port currents) and its ARC.
 //
 // The dense inverses use Gauss-Jordan elimination with partial pivoting.  For
 // 64 <= n <= 1024 it is blocked: one workgroup factors a panel of eight
@@ -538,6 +542,56 @@ void scans(const Geom& g, double k, const double2* Zp, const double2* S, int c, 
     if (nscan <= 0) return;
     hipLaunchKernelGGL(scan_kernel, dim3(nscan), dim3(256), 0, s, Zp, S, g.nx, g.ny, g.dx, g.dy, k, c, theta, phi, z0,
                        Za, G, Gw);
+    MBT_LAUNCH_CHECK();
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// V[(e*M + idx_i)][r] = w_i exp(-j k (x_e u_r + y_e v_r)) for every element e (V pre-zeroed)
+__global__ void scan_voltages_kernel(int nx, int P, double dx, double dy, double k, const double* __restrict__ theta,
+                                     const double* __restrict__ phi, int R, int M, PortDef pd,
+                                     double2* __restrict__ V) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)P * R) return;
+    const int r = (int)(t % R);
+    const int e = (int)(t / R);
+    const double u = sin(theta[r]) * cos(phi[r]), v = sin(theta[r]) * sin(phi[r]);
+    double sn, cs;
+    sincos(k * ((e % nx) * dx * u + (e / nx) * dy * v), &sn, &cs);
+    for (int i = 0; i < pd.n; ++i) V[((int64_t)e * M + pd.idx[i]) * R + r] = make_double2(pd.w[i] * cs, -pd.w[i] * sn);
+}
+
+// Za[r] = V_c,r / Ip[c + P r], G[r] = (Za - z0)/(Za + z0)
+__global__ void scan_active_kernel(const double2* __restrict__ Ip, int P, int nscan, int c, int nx, double dx,
+                                   double dy, double k, const double* __restrict__ theta,
+                                   const double* __restrict__ phi, double z0, double2* __restrict__ Za,
+                                   double2* __restrict__ G) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nscan) return;
+    const double u = sin(theta[r]) * cos(phi[r]), v = sin(theta[r]) * sin(phi[r]);
+    double sn, cs;
+    sincos(k * ((c % nx) * dx * u + (c / nx) * dy * v), &sn, &cs);
+    const double2 za = cdiv(make_double2(cs, -sn), Ip[(int64_t)c + (int64_t)P * r]);
+    Za[r] = za;
+    G[r] = cdiv(make_double2(za.x - z0, za.y), make_double2(za.x + z0, za.y));
+}
+
+void scan_voltages(const Geom& g, double k, const double* theta, const double* phi, int R, double2* V,
+                   hipStream_t s) {
+    zero_d(V, g.N * R, s);
+    const int64_t n = (int64_t)g.P * R;
+    hipLaunchKernelGGL(scan_voltages_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.nx, g.P, g.dx, g.dy,
+                       k, theta, phi, R, g.M, g.port, V);
+    MBT_LAUNCH_CHECK();
+}
+
+void scan_active(const Geom& g, double k, const double2* Ip, int nscan, int c, const double* theta,
+                 const double* phi, double z0, double2* Za, double2* G, hipStream_t s) {
+    hipLaunchKernelGGL(scan_active_kernel, dim3((nscan + 63) / 64), dim3(64), 0, s, Ip, g.P, nscan, c, g.nx, g.dx,
+                       g.dy, k, theta, phi, z0, Za, G);
     MBT_LAUNCH_CHECK();
 }
 

@@ -12,6 +12,7 @@
 #include "../../include/mbt.h"
 #include "common.h"
 #include "gmres.h"
+#include "rwg.h"
 
 namespace mbt {
 
@@ -102,6 +103,8 @@ struct mbt_array {
     std::shared_ptr<const std::vector<double2>> blocks;
     // partitioned operators: margin blocks Z_B (Nc x P*M) and Z_C (Nc x Nc), row-major host copies
     std::shared_ptr<const std::vector<double2>> zb, zc;
+    // planar elements: RWG functions of the element mesh (filled per frequency)
+    std::shared_ptr<const mbt::RwgMesh> rwg;
     uint64_t uid = 0;
 };
 

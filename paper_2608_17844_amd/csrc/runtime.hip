@@ -139,6 +139,7 @@ Geom make_geom(const mbt_dipole& d, const mbt_lattice& l) {
     g.nox = 2 * l.nx - 1;
     g.noy = 2 * l.ny - 1;
     g.pc = (g.M - 1) / 2;
+    g.port.idx[0] = g.pc;
     return g;
 }
 
@@ -159,6 +160,7 @@ Geom make_geom_blocks(int nx, int ny, int M) {
     g.nox = 2 * nx - 1;
     g.noy = 2 * ny - 1;
     g.pc = (M - 1) / 2;
+    g.port.idx[0] = g.pc;
     return g;
 }
 
@@ -194,6 +196,7 @@ static std::string op_key(const mbt_array* arr, double s) {
     std::ostringstream os;
     os.precision(17);
     if (arr->blocks) os << "blocks#" << arr->uid << ',';
+    if (arr->rwg) os << "rwg#" << arr->uid << ',';
     os << g.nx << ',' << g.ny << ',' << g.M << ',' << g.dx << ',' << g.dy << ',' << g.L << ',' << g.a << ',' << s;
     return os.str();
 }
@@ -308,6 +311,8 @@ static std::shared_ptr<OpData> build_op(const mbt_array* arr, double s, Worker& 
     if (arr->blocks) {
         MBT_REQUIRE((int64_t)arr->blocks->size() == g.noff() * MM, "block array size mismatch");
         MBT_HIP(hipMemcpyAsync(op->T.p, arr->blocks->data(), op->T.bytes, hipMemcpyHostToDevice, wk.stream));
+    } else if (arr->rwg) {
+        rwg_fill_blocks(g, *arr->rwg, op->k, op->T.as<double2>(), wk.stream);
     } else {
         fill_blocks(g, op->k, op->T.as<double2>(), wk.stream);
     }
@@ -971,6 +976,103 @@ SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t*
     return total;
 }
 
+// Phased voltage excitation of every gap for each scan direction: solve, gap
+// currents, center-element active impedance and ARC (all on the device).
+static SolveOut scan_solve(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_solve_opts& o, size_t budget,
+                                  const double* theta, const double* phi, int nscan, double z0, int c, double* Ip,
+                           double* Za, double* Gamma, Worker& wk, mbt_stats* st) {
+    const Geom& g = arr->g;
+    const double t0 = now_s();
+    std::shared_ptr<OpData> op;
+    if (o.flags & MBT_FLAG_NO_CACHE) {
+        MBT_REQUIRE(fmt16_of(o.prec) == kFmtNone || g.M <= 32, "16-bit products support at most 32 bases per element");
+        op = build_op(arr, s, wk);
+        if (o.pc == MBT_PC_NORMAL_EQ) build_pa(*op, wk);
+        if (o.prec != MBT_FP64) build_32(*op, wk);
+        if (fmt16_of(o.prec) != kFmtNone) build_16(*op, fmt16_of(o.prec), wk);
+    } else {
+        op = get_op(ctx, arr, s, o.pc == MBT_PC_NORMAL_EQ, o.prec, wk);
+    }
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    const double t1 = now_s();
+    const int chunk = choose_chunk(budget, g, nscan, o);
+    // angles laid out chunk by chunk, odd chunks padded with their last direction
+    std::vector<double> th, ph;
+    for (int c0 = 0; c0 < nscan; c0 += chunk) {
+        const int R = std::min(chunk, nscan - c0);
+        th.insert(th.end(), theta + c0, theta + c0 + R);
+        ph.insert(ph.end(), phi + c0, phi + c0 + R);
+        if (padded(R, o) > R) {
+            th.push_back(theta[c0 + R - 1]);
+            ph.push_back(phi[c0 + R - 1]);
+        }
+    }
+    const size_t need = solve_bytes(g, padded(chunk, o), o) + sizeof(double) * 2 * (th.size() + nscan) +
+                        sizeof(double2) * ((size_t)g.P * nscan + 2 * (size_t)nscan) + 8 * 256;
+    wk.ensure(need);
+    DevArena arena;
+    arena.base = wk.ws.as<char>();
+    arena.cap = wk.ws.bytes;
+    double* dth = arena.get<double>(th.size());
+    double* dph = arena.get<double>(ph.size());
+    double* dth0 = arena.get<double>(nscan);
+    double* dph0 = arena.get<double>(nscan);
+    double2* dIp = arena.get<double2>((size_t)g.P * nscan);
+    double2* dZa = arena.get<double2>(nscan);
+    double2* dG = arena.get<double2>(nscan);
+    MBT_HIP(hipMemcpyAsync(dth, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, wk.stream));
+    MBT_HIP(hipMemcpyAsync(dph, ph.data(), sizeof(double) * ph.size(), hipMemcpyHostToDevice, wk.stream));
+    MBT_HIP(hipMemcpyAsync(dth0, theta, sizeof(double) * nscan, hipMemcpyHostToDevice, wk.stream));
+    MBT_HIP(hipMemcpyAsync(dph0, phi, sizeof(double) * nscan, hipMemcpyHostToDevice, wk.stream));
+    SolveOut total;
+    total.iters.assign(nscan, 0);
+    const size_t base_mark = arena.off;
+    int64_t a0 = 0;
+    for (int c0 = 0; c0 < nscan; c0 += chunk) {
+        const int R = std::min(chunk, nscan - c0);
+        const int Rs = padded(R, o);
+        arena.off = base_mark;
+        double2* V = arena.get<double2>((size_t)g.N * Rs);
+        double2* X = arena.get<double2>((size_t)g.N * Rs);
+        scan_voltages(g, op->k, dth + a0, dph + a0, Rs, V, wk.stream);
+        a0 += Rs;
+        SolveOut so = solve_rhs(*op, o, V, Rs, X, wk, arena);
+        gather_ports(g, X, Rs, R, dIp + (int64_t)c0 * g.P, wk.stream);
+        for (int r = 0; r < R; ++r) {
+            total.iters[c0 + r] = so.iters[r];
+            total.nconv += so.conv[r];
+            total.nflag += so.flag[r];
+        }
+        total.cycles = std::max(total.cycles, so.cycles);
+        total.outer = std::max(total.outer, so.outer);
+        total.matvecs += so.matvecs;
+        total.relres_max = std::max(total.relres_max, so.relres_max);
+    }
+    scan_active(g, op->k, dIp, nscan, c, dth0, dph0, z0, dZa, dG, wk.stream);
+    MBT_HIP(hipMemcpyAsync(Za, dZa, sizeof(double2) * nscan, hipMemcpyDeviceToHost, wk.stream));
+    MBT_HIP(hipMemcpyAsync(Gamma, dG, sizeof(double2) * nscan, hipMemcpyDeviceToHost, wk.stream));
+    if (Ip)
+        MBT_HIP(hipMemcpyAsync(Ip, dIp, sizeof(double2) * (size_t)g.P * nscan, hipMemcpyDeviceToHost, wk.stream));
+    MBT_HIP(hipStreamSynchronize(wk.stream));
+    const double t2 = now_s();
+    if (st) {
+        st->nrhs = nscan;
+        st->nconverged = total.nconv;
+        st->cycles = total.cycles;
+        st->outer_steps = total.outer;
+        st->iters_min = *std::min_element(total.iters.begin(), total.iters.end());
+        st->iters_max = *std::max_element(total.iters.begin(), total.iters.end());
+        st->iters_total = 0;
+        for (int v : total.iters) st->iters_total += v;
+        st->matvecs = total.matvecs;
+        st->true_relres_max = total.relres_max;
+        st->t_setup = t1 - t0;
+        st->t_solve = t2 - t1;
+        st->t_extract = 0;
+    }
+    return total;
+}
+
 SolveOut solve_frequency(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_solve_opts& o, size_t budget,
                          const double* theta, const double* phi, int nscan, double z0, double* Zp, double* Za,
                          double* Gamma, double* Gamma_wave, Worker& wk, mbt_stats* st) {
@@ -1127,6 +1229,27 @@ mbt_status mbt_array_create_blocks(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t
     API_END
 }
 
+mbt_status mbt_array_create_rwg(mbt_ctx* ctx, const mbt_rwg_mesh* mesh, const mbt_lattice* l, mbt_array** out) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && mesh && l && out, "NULL argument");
+    MBT_REQUIRE(l->dx > 0 && l->dy > 0 && std::isfinite(l->dx) && std::isfinite(l->dy),
+                "lattice spacing must be positive");
+    auto h = std::make_shared<RwgMesh>(rwg_from_mesh(*mesh));
+    std::unique_ptr<mbt_array> a(new mbt_array());
+    a->g = make_geom_blocks(l->nx, l->ny, h->M);
+    a->g.dx = l->dx;
+    a->g.dy = l->dy;
+    a->g.port = h->port;
+    a->g.pc = h->port.idx[0];
+    a->elem = mbt_dipole{0.0, 0.0, h->M};
+    a->lat = *l;
+    a->rwg = h;
+    static std::atomic<uint64_t> next_uid{2u << 30};
+    a->uid = next_uid++;
+    *out = a.release();
+    API_END
+}
+
 mbt_status mbt_array_create_margin(mbt_ctx* ctx, int32_t nx, int32_t ny, int32_t nbases, const double* T,
                                    int32_t nmargin, const double* ZB, const double* ZC, mbt_array** out) {
     API_BEGIN
@@ -1250,6 +1373,30 @@ mbt_status mbt_solve(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_sol
     API_BEGIN
     MBT_REQUIRE(ctx && arr && opts, "NULL argument");
     return solve_impl(ctx, arr, s, opts, theta, phi, nscan, z0, Zp, Za, Gamma, Gamma_wave, st);
+    API_END
+}
+
+mbt_status mbt_scan_solve(mbt_ctx* ctx, const mbt_array* arr, double s, const mbt_solve_opts* opts,
+                          const double* theta, const double* phi, int32_t nscan, double z0, int32_t center, double* Ip,
+                          double* Za, double* Gamma, int32_t* iters, mbt_stats* st) {
+    API_BEGIN
+    MBT_REQUIRE(ctx && arr && opts && theta && phi && Za && Gamma, "NULL argument");
+    MBT_REQUIRE(nscan >= 1, "nscan must be >= 1");
+    MBT_REQUIRE(s > 0 && std::isfinite(s), "freq_ratio must be positive");
+    MBT_REQUIRE(z0 > 0 && std::isfinite(z0), "z0 must be positive");
+    MBT_REQUIRE(!arr->blocks, "scan excitations need element positions: dipole or RWG arrays only");
+    for (int r = 0; r < nscan; ++r)
+        MBT_REQUIRE(std::isfinite(theta[r]) && std::isfinite(phi[r]), "scan angles must be finite");
+    std::lock_guard<std::mutex> lk(ctx->api_mu);
+    DevScope ds(ctx->device);
+    validate_opts(*opts);
+    const Geom& g = arr->g;
+    const int c = center < 0 ? (g.ny / 2) * g.nx + g.nx / 2 : center;
+    MBT_REQUIRE(c < g.P, "center out of range");
+    SolveOut so = scan_solve(ctx, arr, s, *opts, ctx->budget, theta, phi, nscan, z0, c, Ip, Za, Gamma, *ctx->main, st);
+    if (iters)
+        for (int r = 0; r < nscan; ++r) iters[r] = so.iters[r];
+    return finish_status(so);
     API_END
 }
 

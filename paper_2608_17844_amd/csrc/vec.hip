@@ -47,10 +47,11 @@ __global__ __launch_bounds__(1024) void max_abs_kernel(const double2* __restrict
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
-// V[n][r] = 1 at the port basis of element ports[r], 0 elsewhere (V pre-zeroed)
-__global__ void scatter_ports_kernel(const int32_t* __restrict__ ports, int R, int M, int pc, double2* V) {
+// V[n][r] = the port weights at the port bases of element ports[r], 0 elsewhere (V pre-zeroed)
+__global__ void scatter_ports_kernel(const int32_t* __restrict__ ports, int R, int M, PortDef pd, double2* V) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < R) V[((int64_t)ports[r] * M + pc) * R + r] = make_double2(1.0, 0.0);
+    if (r < R)
+        for (int i = 0; i < pd.n; ++i) V[((int64_t)ports[r] * M + pd.idx[i]) * R + r] = make_double2(pd.w[i], 0.0);
 }
 
 __global__ void axpby_kernel(double2* __restrict__ y, const double2* __restrict__ x, double a, double b, int64_t n) {
@@ -117,15 +118,21 @@ __global__ __launch_bounds__(512) void colnorm_final_kernel(const double* __rest
     }
 }
 
-// Y[i + P*r] = I[(i*M + pc)][r]   (column-major P x R output)
-// Y[r][i] = I[i*M + pc][r] for the first R of the Rs columns of I
-__global__ void gather_ports_kernel(const double2* __restrict__ I, int P, int M, int pc, int Rs, int R,
+// Y[i + P*r] = sum_k w_k I[(i*M + idx_k)][r]   (column-major P x R output: the gap
+// current of element i) for the first R of the Rs columns of I
+__global__ void gather_ports_kernel(const double2* __restrict__ I, int P, int M, PortDef pd, int Rs, int R,
                                     double2* __restrict__ Y) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= (int64_t)P * R) return;
     const int i = (int)(t % P);
     const int r = (int)(t / P);
-    Y[t] = I[((int64_t)i * M + pc) * Rs + r];
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k = 0; k < pd.n; ++k) {
+        const double2 v = I[((int64_t)i * M + pd.idx[k]) * Rs + r];
+        acc.x += pd.w[k] * v.x;
+        acc.y += pd.w[k] * v.y;
+    }
+    Y[t] = acc;
 }
 
 // to_device_layout: dst[n][r] = src[n + N*r]; else dst[n + N*r] = src[n][r]
@@ -192,7 +199,7 @@ void max_abs_d(const double2* src, int64_t n, double* out, hipStream_t s) {
 
 void scatter_ports(const Geom& g, const int32_t* ports, int R, double2* V, hipStream_t s) {
     zero_d(V, g.N * R, s);
-    hipLaunchKernelGGL(scatter_ports_kernel, dim3((R + 255) / 256), dim3(256), 0, s, ports, R, g.M, g.pc, V);
+    hipLaunchKernelGGL(scatter_ports_kernel, dim3((R + 255) / 256), dim3(256), 0, s, ports, R, g.M, g.port, V);
     MBT_LAUNCH_CHECK();
 }
 
@@ -228,8 +235,8 @@ void column_norms(const double2* X, int64_t N, int R, double* partial, double* o
 void gather_ports(const Geom& g, const double2* I, int Rs, int R, double2* Y, hipStream_t s) {
     MBT_REQUIRE(R <= Rs, "gather_ports: more columns than solved");
     const int64_t n = (int64_t)g.P * R;
-    hipLaunchKernelGGL(gather_ports_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, I, g.P, g.M, g.pc, Rs, R,
-                       Y);
+    hipLaunchKernelGGL(gather_ports_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, I, g.P, g.M, g.port, Rs,
+                       R, Y);
     MBT_LAUNCH_CHECK();
 }
 

@@ -60,6 +60,12 @@ class mbt_predictors(ctypes.Structure):
                 ("s_1", ctypes.c_double * 2)]
 
 
+class mbt_rwg_mesh(ctypes.Structure):
+    _fields_ = [("nvert", ctypes.c_int32), ("vert", ctypes.POINTER(ctypes.c_double)), ("ntri", ctypes.c_int32),
+                ("tri", ctypes.POINTER(ctypes.c_int32)), ("nport_edges", ctypes.c_int32),
+                ("port_edges", ctypes.POINTER(ctypes.c_int32)), ("port_dir", ctypes.c_double * 2)]
+
+
 class mbt_request(ctypes.Structure):
     _fields_ = [("elem", mbt_dipole), ("lat", mbt_lattice), ("nfreq", ctypes.c_int32),
                 ("freq_ratio", ctypes.POINTER(ctypes.c_double)), ("nscan", ctypes.c_int32),
@@ -111,6 +117,10 @@ def lib():
                                             ctypes.POINTER(_vp)]),
             "mbt_array_create_margin": (S, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int32,
                                             _dp, _dp, ctypes.POINTER(_vp)]),
+            "mbt_array_create_rwg": (S, [_vp, ctypes.POINTER(mbt_rwg_mesh), ctypes.POINTER(mbt_lattice),
+                                         ctypes.POINTER(_vp)]),
+            "mbt_scan_solve": (S, [_vp, _vp, ctypes.c_double, ctypes.POINTER(mbt_solve_opts), _dp, _dp, ctypes.c_int32,
+                                   ctypes.c_double, ctypes.c_int32, _dp, _dp, _dp, _ip, ctypes.POINTER(mbt_stats)]),
             "mbt_array_destroy": (None, [_vp]),
             "mbt_array_info": (S, [_vp, ctypes.POINTER(ctypes.c_int64), _ip, _ip, _ip]),
             "mbt_footprint": (ctypes.c_size_t, [_vp, ctypes.c_int32, ctypes.POINTER(mbt_solve_opts)]),
@@ -166,6 +176,7 @@ def exported_symbols() -> list:
         "mbt_server_destroy", "mbt_dbg_fill_blocks", "mbt_dbg_matvec", "mbt_dbg_precond_apply",
         "mbt_dbg_precond_blocks", "mbt_dbg_solve", "mbt_dbg_inverse", "mbt_prof_start", "mbt_prof_read",
         "mbt_predict", "mbt_predict_xi_s", "mbt_active_dev_noalloc", "mbt_array_create_margin",
+        "mbt_array_create_rwg", "mbt_scan_solve",
     ]
 
 
@@ -235,6 +246,20 @@ def mbt_array_create_margin(ctx: int, T: np.ndarray, ZB: np.ndarray, ZC: np.ndar
     _check(lib().mbt_array_create_margin(ctx, (nx2 + 1) // 2, (ny2 + 1) // 2, M, _cd(T), ZC.shape[0], _cd(ZB), _cd(ZC),
                                          ctypes.byref(out)))
     return out.value
+
+
+def mbt_array_create_rwg(ctx: int, mesh, lattice) -> int:
+    """Array of planar RWG elements; mesh has vertices (nv, 2), triangles (nt, 3),
+    port_edges (ne, 2) and port_dir (2,)."""
+    v = np.ascontiguousarray(mesh.vertices, dtype=np.float64)
+    t = np.ascontiguousarray(mesh.triangles, dtype=np.int32)
+    e = np.ascontiguousarray(mesh.port_edges, dtype=np.int32)
+    m = mbt_rwg_mesh(v.shape[0], _cd(v), t.shape[0], _ci(t), e.shape[0], _ci(e),
+                     (ctypes.c_double * 2)(*[float(x) for x in mesh.port_dir]))
+    l = mbt_lattice(lattice.nx, lattice.ny, lattice.dx, lattice.dy)
+    h = _vp()
+    _check(lib().mbt_array_create_rwg(ctx, ctypes.byref(m), ctypes.byref(l), ctypes.byref(h)))
+    return h.value
 
 
 def mbt_array_destroy(arr: int) -> None:
@@ -316,6 +341,26 @@ def mbt_solve(ctx: int, arr: int, freq_ratio: float, opts: mbt_solve_opts, theta
                                     ctypes.byref(st)), allow)
     return {"Zp": Zp, "Za": Za[:ns], "Gamma": G[:ns], "Gamma_wave": Gw[:ns], "stats": st.as_dict(),
             "status": status}
+
+
+def mbt_scan_solve(ctx: int, arr: int, freq_ratio: float, opts: mbt_solve_opts, theta, phi, z0: float = 50.0,
+                   center: int = -1, want_ip: bool = True, allow_noconv: bool = False):
+    """Phased voltage excitation of every gap per scan direction: gap currents Ip
+    (P x nscan), the center element's active impedance and ARC."""
+    P = mbt_array_info(arr)["P"]
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    ns = th.size
+    Ip = np.zeros((P, ns), dtype=np.complex128, order="F") if want_ip else None
+    Za = np.zeros(ns, dtype=np.complex128)
+    G = np.zeros(ns, dtype=np.complex128)
+    it = np.zeros(ns, dtype=np.int32)
+    st = mbt_stats()
+    allow = (MBT_OK, MBT_ENOCONV) if allow_noconv else (MBT_OK,)
+    status = _check(lib().mbt_scan_solve(ctx, arr, freq_ratio, ctypes.byref(opts), _cd(th), _cd(ph), ns, z0, center,
+                                         _cd(Ip) if want_ip else None, _cd(Za), _cd(G), _ci(it),
+                                         ctypes.byref(st)), allow)
+    return {"Ip": Ip, "Za": Za, "Gamma": G, "iters": it, "stats": st.as_dict(), "status": status}
 
 
 def mbt_active_dev_noalloc(ctx: int, arr: int, freq_ratio: float, Zp_ptr: int, theta_ptr: int, phi_ptr: int,

@@ -1,0 +1,190 @@
+"""Planar RWG elements on the GPU against the oracle (oracle/rwg.py): the
+interaction blocks of every lattice offset on small arrays and of sampled
+offsets on the 64 x 64 array, the port admittance of all ports (element-block
+and normal-equation preconditioners), the phased-voltage scan solve in FP64 and
+mixed precision, its agreement with the port admittance on dipole arrays, and
+the validation of bad meshes."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mom, rwg
+from paper_2608_17844_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2608_17844_amd import mbt
+    h = mbt.mbt_ctx_create(0)
+    yield h
+    mbt.mbt_ctx_destroy(h)
+
+
+@pytest.fixture(scope="module")
+def bowtie():
+    mesh = W.bowtie_mesh()
+    return mesh, rwg.rwg_element(mesh)
+
+
+def _block_err(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+# Both sides evaluate the same formulas in FP64.  The closed-form vector
+# potential at test points a few triangle sizes from the source (the neighbour
+# elements' blocks) cancels about three orders of magnitude between its edge
+# terms, and the four charge terms of a basis pair cancel about two more, so
+# entries of the smaller near blocks carry ~1e-12..1e-11 of their block's
+# maximum in rounding (the oracle alone moves by that much when the whole array
+# is translated); far blocks agree to ~1e-13.
+BLOCK_TOL = 1e-10
+
+
+@pytest.mark.parametrize("s", [1.0, 0.6, 1.45])
+def test_rwg_blocks_match_oracle_every_offset(ctx, bowtie, s):
+    from paper_2608_17844_amd import mbt
+    mesh, el = bowtie
+    lat = W.Lattice(3, 2, 0.5, 0.5)
+    a = mbt.mbt_array_create_rwg(ctx, mesh, lat)
+    try:
+        assert mbt.mbt_array_info(a)["N"] == 6 * 96
+        T = mbt.mbt_dbg_fill_blocks(ctx, a, s, lat, el.M)
+        worst = 0.0
+        for oy in range(-1, 2):
+            for ox in range(-2, 3):
+                ref = rwg.offset_block(el, lat, s, ox, oy)
+                worst = max(worst, _block_err(T[oy + 1, ox + 2], ref))
+        _say("s=%.2f worst block error %.2e" % (s, worst))
+        assert worst < BLOCK_TOL
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+def test_rwg_blocks_full_size_sampled_offsets(ctx, bowtie):
+    """64 x 64 bowties (127 x 127 offsets, N = 393,216): sampled offsets, near and far."""
+    from paper_2608_17844_amd import mbt
+    mesh, el = bowtie
+    lat = W.Lattice(64, 64, 0.5, 0.5)
+    a = mbt.mbt_array_create_rwg(ctx, mesh, lat)
+    try:
+        T = mbt.mbt_dbg_fill_blocks(ctx, a, 1.0, lat, el.M)
+        worst = 0.0
+        for ox, oy in ((0, 0), (1, 0), (0, -1), (1, 1), (-1, 1), (2, 0), (5, -3), (63, 63), (-63, 0), (0, -63),
+                       (-40, 22), (17, 50)):
+            ref = rwg.offset_block(el, lat, 1.0, ox, oy)
+            e = _block_err(T[oy + 63, ox + 63], ref)
+            worst = max(worst, e)
+            _say("offset (%d, %d): %.2e" % (ox, oy, e))
+        assert worst < BLOCK_TOL
+        assert np.isfinite(T).all()
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+@pytest.fixture(scope="module")
+def small_oracle(bowtie):
+    mesh, el = bowtie
+    lat = W.Lattice(3, 2, 0.5, 0.5)
+    Z = rwg.fill_dense(el, lat, 0.9)
+    return lat, Z, rwg.port_admittance(Z, el, lat)
+
+
+@pytest.mark.parametrize("pc", ["element_block", "normal_eq"])
+def test_rwg_port_admittance_fp64(ctx, bowtie, small_oracle, pc):
+    from paper_2608_17844_amd import mbt
+    mesh, el = bowtie
+    lat, Z, Yref = small_oracle
+    a = mbt.mbt_array_create_rwg(ctx, mesh, lat)
+    try:
+        pcv = mbt.MBT_PC_ELEMENT_BLOCK if pc == "element_block" else mbt.MBT_PC_NORMAL_EQ
+        opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=pcv, restart=50, tol=1e-13, max_cycles=200)
+        Y, it, st = mbt.mbt_port_admittance(ctx, a, 0.9, None, opts)
+        err = np.linalg.norm(Y - Yref) / np.linalg.norm(Yref)
+        emax = np.abs(Y - Yref).max() / np.abs(Yref).max()
+        _say("%s: Y_p error %.2e (max entry %.2e), iterations %s" % (pc, err, emax, list(it)))
+        assert err < 1e-9 and emax < 1e-9
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rwg_scan_solve_matches_oracle(ctx, bowtie, small_oracle, prec):
+    from paper_2608_17844_amd import mbt
+    mesh, el = bowtie
+    lat, Z, Yref = small_oracle
+    theta, phi = W.scan_angles(7, seed=3, broadside_first=True)
+    Ipr, Zar, Gr = rwg.scan_solve(Z, el, lat, 0.9, theta, phi)
+    a = mbt.mbt_array_create_rwg(ctx, mesh, lat)
+    try:
+        if prec == "fp64":
+            opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, restart=50, tol=1e-13, max_cycles=200)
+            bar = 1e-9
+        else:
+            opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, restart=32, refine_tol=1e-10, refine_max=6)
+            bar = 1e-6
+        r = mbt.mbt_scan_solve(ctx, a, 0.9, opts, theta, phi)
+        e_ip = np.abs(r["Ip"] - Ipr).max() / np.abs(Ipr).max()
+        e_za = np.max(np.abs(r["Za"] - Zar) / np.abs(Zar))
+        e_g = np.max(np.abs(r["Gamma"] - Gr) / np.maximum(1.0, np.abs(Gr)))
+        _say("%s: Ip %.2e Za %.2e Gamma %.2e iters %s" % (prec, e_ip, e_za, e_g, list(r["iters"])))
+        assert e_ip < bar and e_za < bar and e_g < bar
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+def test_scan_solve_on_dipoles_matches_admittance_route(ctx, cfg1, cfg1_oracle):
+    """On the 5x5 dipole array the gap currents of the phased voltages are
+    Y_p V (the oracle's admittance), and Z_a = V_c / I_c."""
+    from paper_2608_17844_amd import mbt
+    lat, dip = cfg1.lattice, cfg1.dipole
+    V = rwg.scan_voltages(lat, 1.0, cfg1.theta, cfg1.phi)
+    Ipr = cfg1_oracle.Yp @ V
+    c = mom.center_element(lat)
+    a = mbt.mbt_array_create_dipole(ctx, dip, lat)
+    try:
+        opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, tol=1e-13)
+        r = mbt.mbt_scan_solve(ctx, a, 1.0, opts, cfg1.theta, cfg1.phi)
+        assert np.abs(r["Ip"] - Ipr).max() < 1e-9 * np.abs(Ipr).max()
+        assert np.max(np.abs(r["Za"] - V[c] / Ipr[c]) / np.abs(V[c] / Ipr[c])) < 1e-9
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
+def test_rwg_mesh_validation(ctx):
+    from paper_2608_17844_amd import mbt
+    lat = W.Lattice(2, 2, 0.5, 0.5)
+    good = W.bowtie_mesh()
+
+    def bad(**kw):
+        d = dict(vertices=good.vertices, triangles=good.triangles, port_edges=good.port_edges,
+                 port_dir=good.port_dir)
+        d.update(kw)
+        with pytest.raises(mbt.MbtError) as e:
+            mbt.mbt_array_create_rwg(ctx, W.PlanarMesh(**d), lat)
+        assert e.value.status == mbt.MBT_EINVAL
+        return str(e.value)
+
+    # a boundary edge (on the tip row) as the port
+    assert "interior" in bad(port_edges=np.array([[0, 1]]))
+    # a third triangle on an interior edge
+    e0 = good.port_edges[0]
+    extra = np.vstack([good.triangles, [[e0[0], e0[1], 0]]])
+    assert "more than two" in bad(triangles=extra)
+    # a degenerate triangle
+    v = good.vertices.copy()
+    v[1] = v[0]
+    assert "degenerate" in bad(vertices=v)
+    # no gap field
+    assert "port_dir" in bad(port_dir=(0.0, 0.0))
+    # vertex index out of range
+    t = good.triangles.copy()
+    t[0, 0] = 10_000
+    assert "out of range" in bad(triangles=t)
