@@ -624,48 +624,83 @@ __global__ void twiddle_kernel(int P, double2* tw) {
     }
 }
 
-// Stage 1 of the block spectrum: tmp[oy][kx][e] = sum_ox T[oy][ox][e] W_Px^{kx*dx}, dx = ox-(nx-1).
-__global__ void embed_x_kernel(const double2* __restrict__ T, double2* __restrict__ tmp, int nx, int noy, int Px,
-                               int MM, const double2* __restrict__ twx) {
-    const int64_t total = (int64_t)noy * Px * MM;
-    const int nox = 2 * nx - 1;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int e = (int)(t % MM);
-        const int kx = (int)((t / MM) % Px);
-        const int oy = (int)(t / ((int64_t)MM * Px));
-        double sr = 0, si = 0;
-        for (int ox = 0; ox < nox; ++ox) {
-            const int dxo = ox - (nx - 1);
-            const int idx = (int)((((int64_t)kx * dxo) % Px + Px) % Px);
-            const double2 w = twx[idx];
-            const double2 v = T[((int64_t)oy * nox + ox) * MM + e];
-            sr += v.x * w.x - v.y * w.y;
-            si += v.x * w.y + v.y * w.x;
-        }
-        tmp[t] = make_double2(sr, si);
+// One axis of the block spectrum.  For every line (outer index o, block entry e),
+//   out[o][k][e] = sc * sum_{i < 2n-1} in[o][i][e] W_P^{k (i - (n-1))},
+// i.e. the P-point DFT of the offsets -(n-1)..n-1 placed circularly (eq. (multL)'s
+// circulant embedding), by an in-place radix-2 decimation-in-time FFT in LDS: the
+// input is loaded at bit-reversed positions, log2 P butterfly stages follow, the
+// output is in natural order.  A workgroup holds EC consecutive block entries of
+// one line, so loads and stores are EC consecutive complex values per row.
+template <int P, int EC>
+__global__ __launch_bounds__(256) void embed_axis_kernel(const double2* __restrict__ in, double2* __restrict__ out,
+                                                         int n, int64_t in_outer, int64_t in_stride,
+                                                         int64_t out_outer, int64_t out_stride, int64_t MM,
+                                                         double sc, const double2* __restrict__ tw) {
+    constexpr int kLog = P == 8 ? 3 : P == 16 ? 4 : P == 32 ? 5 : P == 64 ? 6 : 7;
+    static_assert((1 << kLog) == P, "P must be a power of two in 8..128");
+    constexpr int kSub = 256 / EC;
+    __shared__ double2 buf[P * EC];
+    const int64_t o = blockIdx.y;
+    const int col = threadIdx.x % EC, sub = threadIdx.x / EC;
+    const int64_t e = (int64_t)blockIdx.x * EC + col;
+    const bool live = e < MM;
+    for (int i = sub; i < P; i += kSub) buf[i * EC + col] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const int nlen = 2 * n - 1;
+    for (int i = sub; i < nlen; i += kSub) {
+        int pos = i - (n - 1);
+        if (pos < 0) pos += P;
+        const int br = (int)(__brev((unsigned)pos) >> (32 - kLog));
+        buf[br * EC + col] = live ? in[o * in_outer + (int64_t)i * in_stride + e] : make_double2(0.0, 0.0);
     }
+    __syncthreads();
+#pragma unroll
+    for (int lh = 0; lh < kLog; ++lh) {
+        const int h = 1 << lh;
+        for (int bfly = sub; bfly < P / 2; bfly += kSub) {
+            const int pos = bfly & (h - 1);
+            const int i0 = ((bfly >> lh) << (lh + 1)) + pos, i1 = i0 + h;
+            const double2 w = tw[pos << (kLog - 1 - lh)];   // W_{2h}^{pos} = W_P^{pos P / 2h}
+            const double2 x0 = buf[i0 * EC + col];
+            const double2 x1 = cmul(buf[i1 * EC + col], w);
+            buf[i0 * EC + col] = cadd(x0, x1);
+            buf[i1 * EC + col] = csub(x0, x1);
+        }
+        __syncthreads();
+    }
+    if (live)
+        for (int kk = sub; kk < P; kk += kSub) {
+            const double2 v = buf[kk * EC + col];
+            out[o * out_outer + (int64_t)kk * out_stride + e] = make_double2(sc * v.x, sc * v.y);
+        }
 }
 
-// Stage 2: Chat[ky][kx][e] = scale * sum_oy tmp[oy][kx][e] W_Py^{ky*dy}.
-__global__ void embed_y_kernel(const double2* __restrict__ tmp, double2* __restrict__ Chat, int ny, int Px, int Py,
-                               int MM, double scale, const double2* __restrict__ twy) {
-    const int64_t total = (int64_t)Py * Px * MM;
-    const int noy = 2 * ny - 1;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int e = (int)(t % MM);
-        const int kx = (int)((t / MM) % Px);
-        const int ky = (int)(t / ((int64_t)MM * Px));
-        double sr = 0, si = 0;
-        for (int oy = 0; oy < noy; ++oy) {
-            const int dyo = oy - (ny - 1);
-            const int idx = (int)((((int64_t)ky * dyo) % Py + Py) % Py);
-            const double2 w = twy[idx];
-            const double2 v = tmp[((int64_t)oy * Px + kx) * MM + e];
-            sr += v.x * w.x - v.y * w.y;
-            si += v.x * w.y + v.y * w.x;
-        }
-        Chat[t] = make_double2(sr * scale, si * scale);
+void launch_embed_axis(int P, const double2* in, double2* out, int n, int64_t nlines, int64_t in_outer,
+                       int64_t in_stride, int64_t out_outer, int64_t out_stride, int64_t MM, double sc,
+                       const double2* tw, hipStream_t s) {
+    constexpr int EC = 32;
+    const dim3 grid((unsigned)((MM + EC - 1) / EC), (unsigned)nlines);
+    MBT_REQUIRE(nlines < 65536, "embed: too many lines");
+    switch (P) {
+        case 16:
+            hipLaunchKernelGGL((embed_axis_kernel<16, EC>), grid, dim3(256), 0, s, in, out, n, in_outer, in_stride,
+                               out_outer, out_stride, MM, sc, tw);
+            break;
+        case 32:
+            hipLaunchKernelGGL((embed_axis_kernel<32, EC>), grid, dim3(256), 0, s, in, out, n, in_outer, in_stride,
+                               out_outer, out_stride, MM, sc, tw);
+            break;
+        case 64:
+            hipLaunchKernelGGL((embed_axis_kernel<64, EC>), grid, dim3(256), 0, s, in, out, n, in_outer, in_stride,
+                               out_outer, out_stride, MM, sc, tw);
+            break;
+        case 128:
+            hipLaunchKernelGGL((embed_axis_kernel<128, EC>), grid, dim3(256), 0, s, in, out, n, in_outer, in_stride,
+                               out_outer, out_stride, MM, sc, tw);
+            break;
+        default: throw Error(-1, "embed: unsupported grid size");
     }
+    MBT_LAUNCH_CHECK();
 }
 
 // Columns per workgroup: fill a 128 KB LDS tile (one workgroup per CU), at
@@ -808,16 +843,16 @@ void make_twiddles(int P, double2* tw, hipStream_t s) {
 
 void embed_blocks_fft(const Geom& g, const double2* T, double2* Chat, double scale, double2* scratch, hipStream_t s) {
     // scratch: noy * Px * M*M complex; twiddle tables are placed after it
-    const int MM = g.M * g.M;
+    const int64_t MM = (int64_t)g.M * g.M;
     double2* tmp = scratch;
     double2* twx = scratch + (int64_t)g.noy * g.Px * MM;
     double2* twy = twx + g.Px;
     make_twiddles(g.Px, twx, s);
     make_twiddles(g.Py, twy, s);
-    hipLaunchKernelGGL(embed_x_kernel, dim3(2048), dim3(256), 0, s, T, tmp, g.nx, g.noy, g.Px, MM, twx);
-    MBT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(embed_y_kernel, dim3(2048), dim3(256), 0, s, tmp, Chat, g.ny, g.Px, g.Py, MM, scale, twy);
-    MBT_LAUNCH_CHECK();
+    // x: lines (oy, e) over the 2nx-1 offsets ox -> tmp[oy][kx][e]
+    launch_embed_axis(g.Px, T, tmp, g.nx, g.noy, (int64_t)g.nox * MM, MM, (int64_t)g.Px * MM, MM, MM, 1.0, twx, s);
+    // y: lines (kx, e) over the 2ny-1 offsets oy -> Chat[ky][kx][e]
+    launch_embed_axis(g.Py, tmp, Chat, g.ny, g.Px, MM, (int64_t)g.Px * MM, MM, (int64_t)g.Px * MM, MM, scale, twy, s);
 }
 
 template <typename T>
