@@ -409,7 +409,7 @@ def serve(args):
             reqs = W.serving_stream(args.serve, rate, seed=0)
             # a seeded sample of requests small enough for the dense CPU oracle, and one of them
             # re-served alone afterwards for the alone-versus-in-the-mix comparison
-            small = [i for i, r in enumerate(reqs) if r.lattice.nx * r.lattice.ny * r.dipole.nbases <= 12000]
+            small = [i for i, r in enumerate(reqs) if r.lattice.nx * r.lattice.ny * r.dipole.nbases <= 6000]
             rng = np.random.default_rng(5)
             keep = set(int(i) for i in rng.choice(small, size=min(args.serve_verify, len(small)), replace=False)) \
                 if args.serve_verify > 0 and small else set()
@@ -466,6 +466,8 @@ def verify_served(mbt, srv, submit, collect, reqs, res, ids):
         ez, ee, eg = [], [], []
         for fi, s in enumerate(r.freqs):
             o = mom.solve_array(r.lattice, r.dipole, s, r.theta, r.phi, z0=r.z0)
+            log("  verify: request %d (%dx%d, M=%d) frequency %.4f checked against the oracle"
+                % (i, r.lattice.nx, r.lattice.ny, r.dipole.nbases, s))
             d = x["Zp"][fi] - o.Zp
             ez.append(float(np.linalg.norm(d) / np.linalg.norm(o.Zp)))
             ee.append(float(np.max(np.abs(d)) / np.max(np.abs(o.Zp))))
@@ -543,6 +545,88 @@ def blocks_shape(args):
             out["kernels"][name] = {"achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "achieved_TFs": tfs,
                                     "fp32_mfma_frac": tfs / 157.3, "avg_launch_ms": p["ms"] / p["launches"],
                                     "launches": p["launches"]}
+    return out
+
+
+def bowtie(args):
+    """Largest single-GPU instance: 64 x 64 planar bowties (96 RWG functions
+    each, N = 393,216, FFT grid 128 x 128), 32 phased-voltage excitations
+    (broadside first, then seeded scan directions) at 5 frequencies in 0.5-1.5
+    f0, with the center element's active impedance and ARC.  Each frequency runs
+    the whole path with nothing cached: RWG fill, block spectra, preconditioner,
+    solve, extraction.  The mixed path (FP32 products, FP64 refinement) is timed
+    against the FP64 path and their Za / Gamma are compared."""
+    from paper_2608_17844_amd import mbt
+    from paper_2608_17844_amd import workloads as W
+    mesh, lat, freqs, theta, phi = W.bowtie_64x64_workload()
+    ctx = mbt.mbt_ctx_create(0)
+    arr = mbt.mbt_array_create_rwg(ctx, mesh, lat)
+    paths = {
+        "mixed": mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=args.restart,
+                                      refine_tol=1e-9, refine_max=6, inner_tol=args.inner_tol,
+                                      flags=mbt.MBT_FLAG_NO_CACHE),
+        "fp64": mbt.mbt_default_opts(prec=mbt.MBT_FP64, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=50, tol=1e-10,
+                                     flags=mbt.MBT_FLAG_NO_CACHE),
+    }
+    res = {name: [] for name in paths}
+    kern = {}
+    try:
+        log("bowtie: 64x64 x 96 RWG, %d frequencies x %d scans; warm-up" % (len(freqs), len(theta)))
+        mbt.mbt_scan_solve(ctx, arr, float(freqs[2]), paths["mixed"], theta[:2], phi[:2], want_ip=False,
+                           allow_noconv=True)
+        for name, opts in paths.items():
+            for s in freqs:
+                t0 = time.perf_counter()
+                r = mbt.mbt_scan_solve(ctx, arr, float(s), opts, theta, phi, want_ip=False, allow_noconv=True)
+                dt = time.perf_counter() - t0
+                st = r["stats"]
+                res[name].append({"freq_ratio": float(s), "seconds": dt, "setup_s": st["t_setup"],
+                                  "solve_s": st["t_solve"], "iters_min": st["iters_min"], "iters_max": st["iters_max"],
+                                  "outer_steps": st["outer_steps"], "matvecs": st["matvecs"],
+                                  "true_relres_max": st["true_relres_max"], "status": int(r["status"]),
+                                  "Za": r["Za"], "Gamma": r["Gamma"]})
+                log("  %s s=%.2f: %.3f s (setup %.3f, solve %.3f), iters %d..%d, outer %d, relres %.1e, status %d, "
+                    "Za[0] %.4f%+.4fj" % (name, s, dt, st["t_setup"], st["t_solve"], st["iters_min"],
+                                          st["iters_max"], st["outer_steps"], st["true_relres_max"], r["status"],
+                                          r["Za"][0].real, r["Za"][0].imag))
+        # kernel classes of the mixed path's solve (operator cached for these runs)
+        cached = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=args.restart,
+                                      refine_tol=1e-9, refine_max=6, inner_tol=args.inner_tol)
+        mbt.mbt_scan_solve(ctx, arr, 1.0, cached, theta, phi, want_ip=False, allow_noconv=True)
+        for kc, kname in ((6, "bin_product"), (4, "fft_fwd_pad"), (5, "fft_inv_crop"), (2, "arnoldi_update_dots")):
+            mbt.mbt_prof_start(kc)
+            mbt.mbt_scan_solve(ctx, arr, 1.0, cached, theta, phi, want_ip=False, allow_noconv=True)
+            kern[kname] = mbt.mbt_prof_read()
+            mbt.mbt_prof_start(0)
+    finally:
+        mbt.mbt_array_destroy(arr)
+        mbt.mbt_ctx_destroy(ctx)
+    nsolve = len(theta) * len(freqs)
+    t_mixed = sum(x["seconds"] for x in res["mixed"])
+    t_fp64 = sum(x["seconds"] for x in res["fp64"])
+    za_err = max(float(np.max(np.abs(a["Za"] - b["Za"]) / np.abs(b["Za"]))) for a, b in zip(res["mixed"], res["fp64"]))
+    g_err = max(float(np.max(np.abs(a["Gamma"] - b["Gamma"]) / np.maximum(1.0, np.abs(b["Gamma"]))))
+                for a, b in zip(res["mixed"], res["fp64"]))
+    for v in res.values():
+        for x in v:
+            x["Za_first"] = [float(x["Za"][0].real), float(x["Za"][0].imag)]
+            del x["Za"], x["Gamma"]
+    out = {"metric": "scan-excitation solves/s, 64x64 planar bowties (96 RWG bases), whole path per frequency",
+           "value": nsolve / t_mixed, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "bowtie_64x64_m96", "nx": 64, "ny": 64, "nbases": 96, "unknowns": 64 * 64 * 96,
+                      "grid": [128, 128], "scans": len(theta), "freq_ratio": [float(f) for f in freqs],
+                      "mixed": {"restart": args.restart, "inner_tol": args.inner_tol, "refine_tol": 1e-9,
+                                "refine_max": 6},
+                      "fp64": {"restart": 50, "tol": 1e-10}, "preconditioner": "element_block"},
+           "fp64_solves_per_s": nsolve / t_fp64, "speedup_vs_fp64": t_fp64 / t_mixed,
+           "mixed_vs_fp64": {"za_max_rel": za_err, "gamma_max_rel": g_err},
+           "per_frequency": res, "kernels": {}}
+    for name, p in kern.items():
+        if p["launches"] and p["ms"] > 0:
+            gbs = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+            out["kernels"][name] = {"achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                                    "avg_launch_ms": p["ms"] / p["launches"], "launches": p["launches"]}
     return out
 
 
@@ -757,6 +841,8 @@ def main():
                     help="time one GPU's share of the ports (this many RHS, admittance only) instead")
     ap.add_argument("--blocks", type=int, default=0,
                     help="run the 64x64x96 synthetic-block shape with this many operators (1..5) instead")
+    ap.add_argument("--bowtie", action="store_true",
+                    help="run the 64x64 planar-bowtie scan workload (RWG fill, 5 frequencies x 32 scans) instead")
     ap.add_argument("--predict", type=int, default=0,
                     help="run the coupling-predictor sweep over N x N arrays up to this N (odd) instead")
     ap.add_argument("--predict-freq", type=float, default=1.1,
@@ -790,6 +876,8 @@ def main():
         result = small(args)
     elif args.blocks > 0:
         result = blocks_shape(args)
+    elif args.bowtie:
+        result = bowtie(args)
     elif args.predict > 0:
         result = predict(args)
     elif args.cpu_full:

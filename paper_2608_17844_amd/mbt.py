@@ -506,15 +506,19 @@ def mbt_dbg_precond_blocks(ctx: int, arr: int, freq_ratio: float, pc: int, nbloc
 
 
 def mbt_dbg_solve(ctx: int, arr: int, freq_ratio: float, opts: mbt_solve_opts, V: np.ndarray,
-                  allow_noconv: bool = False):
+                  allow_noconv: bool = False, allow_breakdown: bool = False):
     Vf = np.asfortranarray(V, dtype=np.complex128)
     I = np.zeros_like(Vf, order="F")
     iters = np.zeros(Vf.shape[1], dtype=np.int32)
     st = mbt_stats()
     allow = (MBT_OK, MBT_ENOCONV) if allow_noconv else (MBT_OK,)
-    _check(lib().mbt_dbg_solve(ctx, arr, freq_ratio, ctypes.byref(opts), _cd(Vf), Vf.shape[1],
-                               _cd(I), _ci(iters), ctypes.byref(st)), allow)
-    return I, iters, st.as_dict()
+    if allow_breakdown:
+        allow = allow + (MBT_EBREAKDOWN,)
+    status = _check(lib().mbt_dbg_solve(ctx, arr, freq_ratio, ctypes.byref(opts), _cd(Vf), Vf.shape[1],
+                                        _cd(I), _ci(iters), ctypes.byref(st)), allow)
+    out = st.as_dict()
+    out["status"] = status
+    return I, iters, out
 
 
 def mbt_dbg_inverse(ctx: int, A: np.ndarray) -> np.ndarray:

@@ -227,9 +227,10 @@ def strip_mesh(length: float = 0.5, width: float = 0.02, nseg: int = 20, nacross
 def bowtie_64x64_workload():
     """Largest single-GPU instance: 64 x 64 bowties (96 RWG bases each,
     N = 393,216) on a 0.5-wavelength square lattice, 32 excitations (broadside
-    first, then seeded scan directions) at 5 frequencies in 0.5-1.5 f0."""
-    theta, phi = scan_angles(32, seed=5, broadside_first=True)
-    return bowtie_mesh(), Lattice(64, 64, 0.5, 0.5), np.linspace(0.5, 1.5, 5), theta, phi
+    first, then seeded scan directions) at 5 frequencies 0.9-1.3 f0, the band
+    around the frequency where the lattice spacing is 0.55 wavelengths."""
+    theta, phi = scan_angles(31, seed=5, broadside_first=True)
+    return bowtie_mesh(), Lattice(64, 64, 0.5, 0.5), np.linspace(0.9, 1.3, 5), theta, phi
 
 
 @dataclass
