@@ -417,11 +417,13 @@ def serve(args):
                 rate, 100 * load, len(reqs)))
             t0 = mbt.mbt_server_clock(srv)
             tickets = []
-            for r in reqs:
+            for i, r in enumerate(reqs):
                 dt = t0 + r.arrival - mbt.mbt_server_clock(srv)
                 if dt > 0:
                     time.sleep(dt)
                 tickets.append(submit(r))
+                log("  submitted request %d (%dx%d, M=%d, %d freq) at %.1f s" % (
+                    i, r.lattice.nx, r.lattice.ny, r.dipole.nbases, len(r.freqs), mbt.mbt_server_clock(srv) - t0))
             res = collect(tickets, reqs, t0, keep)
             runs.append(dict(summary(res, reqs, t0), load_vs_saturation=load, rate_rps=rate))
             log("serving: load %.2f: %.1f solves/s (converged requests), %d of %d converged, p50 %.1f s, "

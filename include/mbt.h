@@ -64,7 +64,7 @@ typedef enum {
  * products run in FP32 (FP32 MFMA, FP32 accumulation).  MBT_BF16 / MBT_FP16: as
  * MBT_FP32, but the forward FFT stores the spectrum X^ in 16-bit complex and
  * the per-bin products take X^ and the block spectra C^ in bfloat16 / binary16
- * on the 16x16x16 MFMA with FP32 accumulation and FP32 output.  In every
+ * on the 16x16x32 MFMA with FP32 accumulation and FP32 output.  In every
  * reduced precision the Krylov basis is stored in FP32 with FP64 dot products,
  * Givens rotations are FP64, the preconditioner apply is FP32, and FP64
  * iterative refinement with an FP64 residual recovers the accuracy (inner

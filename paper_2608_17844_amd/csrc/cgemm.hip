@@ -309,31 +309,32 @@ void launch_big(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y,
 }
 
 // ---------------------------------------------------------------- 16-bit inputs
-// The same real formulation on the 16x16x16 MFMA with 16-bit inputs and FP32
-// accumulation.  A lane supplies four consecutive K values; with K interleaving
-// (q, re/im), K slots 4g..4g+3 of a 16-wide block are the two complex values
-// X[q0][col], X[q0+1][col] (q0 = 8s + 2g), i.e. two packed 32-bit words as they
-// sit in memory.  The A row (p, re) needs (A.re, -A.im) pairs and the row
-// (p, im) the swapped (A.im, A.re) pairs: a sign-bit flip and a half-word
-// rotation of the packed words.
-typedef short s4 __attribute__((ext_vector_type(4)));
-typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+// The same real formulation on gfx950's doubled-K 16x16x32 MFMA with 16-bit
+// inputs and FP32 accumulation.  A lane supplies eight consecutive K values;
+// with K interleaving (q, re/im), K slots 8g..8g+7 of a 32-wide block are the
+// four complex values X[q0..q0+3][col] (q0 = 16s + 4g), i.e. four packed 32-bit
+// words as they sit in memory.  The A row (p, re) needs (A.re, -A.im) pairs and
+// the row (p, im) the swapped (A.im, A.re) pairs: a sign-bit flip and a
+// half-word rotation of the packed words.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4w __attribute__((ext_vector_type(4)));
 
-template <int FMT> __device__ __forceinline__ f4 mfma16(u2 a, u2 b, f4 c) {
+template <int FMT> __device__ __forceinline__ f4 mfma16(u4w a, u4w b, f4 c) {
     if constexpr (FMT == kFmtBf16)
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b), c, 0, 0,
-                                                         0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                       0);
     else
-        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b), c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
 }
 
 template <int FMT, int MP, bool HERM>
 __global__ __launch_bounds__(256) void cgemm16_kernel(const uint32_t* __restrict__ A, int64_t strideA,
                                                       const uint32_t* __restrict__ X, float2* __restrict__ Y, int M,
                                                       int R, int groups, int tpw, float osc) {
-    constexpr int NRT = MP / 8;   // 16-row tiles of the 2MP-row real matrix
-    constexpr int NKB = MP / 8;   // 16-wide real K blocks (8 complex q each)
+    static_assert(MP % 16 == 0, "MP must be a multiple of 16");
+    constexpr int NRT = MP / 8;    // 16-row tiles of the 2MP-row real matrix
+    constexpr int NKB = MP / 16;   // 32-wide real K blocks (16 complex q each)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t b = blockIdx.x / groups;
@@ -350,7 +351,7 @@ __global__ __launch_bounds__(256) void cgemm16_kernel(const uint32_t* __restrict
     const int li = lane & 15;
 
     // A fragments: row rho = 16t + li of the real matrix is (p, re/im), p = rho/2
-    u2 af[NRT][NKB];
+    u4w af[NRT][NKB];
 #pragma unroll
     for (int t = 0; t < NRT; ++t) {
         const int rho = 16 * t + li;
@@ -359,8 +360,8 @@ __global__ __launch_bounds__(256) void cgemm16_kernel(const uint32_t* __restrict
 #pragma unroll
         for (int s = 0; s < NKB; ++s) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int q = 8 * s + 2 * g + h;
+            for (int h = 0; h < 4; ++h) {
+                const int q = 16 * s + 4 * g + h;
                 uint32_t w = 0;
                 if (p < M && q < M) {
                     w = HERM ? Ab[(int64_t)q * M + p] : Ab[(int64_t)p * M + q];
@@ -371,14 +372,14 @@ __global__ __launch_bounds__(256) void cgemm16_kernel(const uint32_t* __restrict
         }
     }
 
-    u2 bcur[NKB], bnext[NKB];
-    auto load = [&](int tile, u2* dst) {
+    u4w bcur[NKB], bnext[NKB];
+    auto load = [&](int tile, u4w* dst) {
         const int col = tile * 16 + li;
 #pragma unroll
         for (int s = 0; s < NKB; ++s) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int q = 8 * s + 2 * g + h;
+            for (int h = 0; h < 4; ++h) {
+                const int q = 16 * s + 4 * g + h;
                 dst[s][h] = (q < M && col < R) ? Xb[(int64_t)q * R + col] : 0u;
             }
         }

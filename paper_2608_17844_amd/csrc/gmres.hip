@@ -561,14 +561,20 @@ void launch_dcgs2_dots_rpl(const TV* V, int64_t vs, int k, int i0, int nv, const
 // accumulated.  Summation over i is sequential per (row, RHS).
 template <typename TB, int RB>
 __global__ __launch_bounds__(256) void dcgs2_update_rows_kernel(const TB* __restrict__ V, int64_t vstride, int k,
-                                                                TB* u, TB* w, const double2* __restrict__ cs,
-                                                                const double2* __restrict__ cc,
-                                                                const double* __restrict__ inv_nu, int64_t N, int R) {
+                                                                TB* u, TB* w, const double2* __restrict__ cs_,
+                                                                const double2* __restrict__ cc_,
+                                                                const double* __restrict__ inv_nu_, int64_t N, int R,
+                                                                int Rt) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r = blockIdx.x * 64 + lane;
     const int64_t n0 = ((int64_t)blockIdx.y * 4 + wave) * RB;
     if (r >= R || n0 >= N) return;
+    // folded rows (R = F * Rt columns per row): column r is RHS r mod Rt
+    const int rt = r % Rt;
+    const double2* cs = cs_ + rt;
+    const double2* cc = cc_ + rt;
+    const double* inv_nu = inv_nu_ + rt;
     const int nr = (int)min<int64_t>(RB, N - n0);
     double2 a[RB], c[RB];
 #pragma unroll
@@ -585,15 +591,15 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows_kernel(const TB* __rest
     double2 fs = make_double2(0, 0), fc = make_double2(0, 0);
     if (k > 0) {
         load(0, cur);
-        fs = cs[r];
-        fc = cc[r];
+        fs = cs[0];
+        fc = cc[0];
     }
     for (int i = 0; i < k; ++i) {
         double2 fs_n = make_double2(0, 0), fc_n = make_double2(0, 0);
         if (i + 1 < k) {
             load(i + 1, nxt);
-            fs_n = cs[(int64_t)(i + 1) * R + r];
-            fc_n = cc[(int64_t)(i + 1) * R + r];
+            fs_n = cs[(int64_t)(i + 1) * Rt];
+            fc_n = cc[(int64_t)(i + 1) * Rt];
         }
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
@@ -606,8 +612,8 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows_kernel(const TB* __rest
         fs = fs_n;
         fc = fc_n;
     }
-    const double inu = inv_nu[r];
-    const double2 ckv = cc[(int64_t)k * R + r];
+    const double inu = inv_nu[0];
+    const double2 ckv = cc[(int64_t)k * Rt];
 #pragma unroll
     for (int j = 0; j < RB; ++j) {
         if (j < nr) {
@@ -629,14 +635,20 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows_kernel(const TB* __rest
 template <int RB>
 __global__ __launch_bounds__(256) void dcgs2_update_rows24_kernel(const p24x2* __restrict__ V, int64_t vstride, int k,
                                                                   float2* u, const float2* __restrict__ w,
-                                                                  p24x2* __restrict__ vk, const double2* __restrict__ cs,
-                                                                  const double2* __restrict__ cc,
-                                                                  const double* __restrict__ inv_nu, int64_t N, int R) {
+                                                                  p24x2* __restrict__ vk, const double2* __restrict__ cs_,
+                                                                  const double2* __restrict__ cc_,
+                                                                  const double* __restrict__ inv_nu_, int64_t N, int R,
+                                                                  int Rt) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r0 = 2 * (blockIdx.x * 64 + lane);
     const int64_t n0 = ((int64_t)blockIdx.y * 4 + wave) * RB;
     if (r0 >= R || n0 >= N) return;
+    // folded rows (R = F * Rt columns per row, Rt even): columns r0, r0+1 are RHS r0 mod Rt and the next
+    const int rt = r0 % Rt;
+    const double2* cs = cs_ + rt;
+    const double2* cc = cc_ + rt;
+    const double* inv_nu = inv_nu_ + rt;
     const int nr = (int)min<int64_t>(RB, N - n0);
     const int64_t rw = R / 2;   // packed words per row
     double2 a[RB][2], c[RB][2];
@@ -658,8 +670,8 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows24_kernel(const p24x2* _
         load(0, cur);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            fs[q] = cs[r0 + q];
-            fc[q] = cc[r0 + q];
+            fs[q] = cs[q];
+            fc[q] = cc[q];
         }
     }
     for (int i = 0; i < k; ++i) {
@@ -668,8 +680,8 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows24_kernel(const p24x2* _
             load(i + 1, nxt);
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                fs_n[q] = cs[(int64_t)(i + 1) * R + r0 + q];
-                fc_n[q] = cc[(int64_t)(i + 1) * R + r0 + q];
+                fs_n[q] = cs[(int64_t)(i + 1) * Rt + q];
+                fc_n[q] = cc[(int64_t)(i + 1) * Rt + q];
             }
         }
 #pragma unroll
@@ -692,8 +704,8 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows24_kernel(const p24x2* _
     double2 ckv[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        inu[q] = inv_nu[r0 + q];
-        ckv[q] = cc[(int64_t)k * R + r0 + q];
+        inu[q] = inv_nu[q];
+        ckv[q] = cc[(int64_t)k * Rt + q];
     }
 #pragma unroll
     for (int j = 0; j < RB; ++j) {
@@ -715,14 +727,16 @@ __global__ __launch_bounds__(256) void dcgs2_update_rows24_kernel(const p24x2* _
 }
 
 void launch_dcgs2_update24(const p24x2* V, int64_t vs, int k, float2* u, const float2* w, p24x2* vk,
-                           const double2* cs, const double2* cc, const double* inv_nu, int64_t N, int R, hipStream_t s) {
+                           const double2* cs, const double2* cc, const double* inv_nu, int64_t N, int R, int Rt,
+                           hipStream_t s) {
     constexpr int RB = 8;
     MBT_REQUIRE(R % 2 == 0, "packed basis needs an even number of RHS");
     const int64_t rows_per_block = 4 * RB;
     const int64_t gy = (N + rows_per_block - 1) / rows_per_block;
     MBT_REQUIRE(gy < 65536, "dcgs2 update: too many row blocks");
+    MBT_REQUIRE(Rt % 2 == 0 && R % Rt == 0, "packed basis: folded width must be a multiple of the even RHS count");
     hipLaunchKernelGGL((dcgs2_update_rows24_kernel<RB>), dim3((unsigned)((R / 2 + 63) / 64), (unsigned)gy), dim3(256), 0,
-                       s, V, vs, k, u, w, vk, cs, cc, inv_nu, N, R);
+                       s, V, vs, k, u, w, vk, cs, cc, inv_nu, N, R, Rt);
     MBT_LAUNCH_CHECK();
 }
 
@@ -732,13 +746,14 @@ void launch_dcgs2_update24(const p24x2* V, int64_t vs, int k, float2* u, const f
 // of the other RHS ran.
 template <typename TV, int RPL, int RB>
 __global__ __launch_bounds__(256) void solution_update_kernel(const TV* __restrict__ V, int64_t vstride, int steps,
-                                                              const double2* __restrict__ y, double2* __restrict__ x,
-                                                              int64_t N, int R) {
+                                                              const double2* __restrict__ y_, double2* __restrict__ x,
+                                                              int64_t N, int R, int Rt) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r0 = (blockIdx.x * 64 + lane) * RPL;
     const int64_t n0 = ((int64_t)blockIdx.y * 4 + wave) * RB;
     if (r0 >= R || n0 >= N) return;
+    const double2* y = y_ + r0 % Rt;   // folded rows: column r0 is RHS r0 mod Rt
     const int nr = (int)min<int64_t>(RB, N - n0);
     double2 acc[RB][RPL];
 #pragma unroll
@@ -757,7 +772,7 @@ __global__ __launch_bounds__(256) void solution_update_kernel(const TV* __restri
     if (steps > 0) {
         load(0, cur);
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) yc[q] = y[r0 + q];
+        for (int q = 0; q < RPL; ++q) yc[q] = y[q];
     }
     for (int i = 0; i < steps; ++i) {
         double2 yn[RPL];
@@ -766,7 +781,7 @@ __global__ __launch_bounds__(256) void solution_update_kernel(const TV* __restri
         if (i + 1 < steps) {
             load(i + 1, nxt);
 #pragma unroll
-            for (int q = 0; q < RPL; ++q) yn[q] = y[(int64_t)(i + 1) * R + r0 + q];
+            for (int q = 0; q < RPL; ++q) yn[q] = y[(int64_t)(i + 1) * Rt + q];
         }
 #pragma unroll
         for (int j = 0; j < RB; ++j)
@@ -789,17 +804,18 @@ __global__ __launch_bounds__(256) void solution_update_kernel(const TV* __restri
 
 template <typename TV>
 void launch_solution_update(const TV* V, int64_t vs, int steps, const double2* y, double2* x, int64_t N, int R,
-                            hipStream_t s) {
+                            int Rt, hipStream_t s) {
+    MBT_REQUIRE(R % Rt == 0, "folded width must be a multiple of the RHS count");
     constexpr int RB = 8;
     const int64_t gy = (N + 4 * RB - 1) / (4 * RB);
     MBT_REQUIRE(gy < 65536, "solution update: too many row blocks");
     if constexpr (std::is_same<TV, p24x2>::value) {
         MBT_REQUIRE(R % 2 == 0, "packed basis needs an even number of RHS");
         hipLaunchKernelGGL((solution_update_kernel<TV, 2, RB>), dim3((unsigned)((R / 2 + 63) / 64), (unsigned)gy),
-                           dim3(256), 0, s, V, vs, steps, y, x, N, R);
+                           dim3(256), 0, s, V, vs, steps, y, x, N, R, Rt);
     } else {
         hipLaunchKernelGGL((solution_update_kernel<TV, 1, RB>), dim3((unsigned)((R + 63) / 64), (unsigned)gy),
-                           dim3(256), 0, s, V, vs, steps, y, x, N, R);
+                           dim3(256), 0, s, V, vs, steps, y, x, N, R, Rt);
     }
     MBT_LAUNCH_CHECK();
 }
@@ -829,15 +845,14 @@ void launch_dcgs2_dots(const TV* V, int64_t vs, int k, const TB* u, const TB* w,
 
 template <typename TB>
 void launch_dcgs2_update(const TB* V, int64_t vs, int k, TB* u, TB* w, const double2* cs, const double2* cc,
-                         const double* inv_nu, int64_t N, int R, int64_t rpc, int nchunk, hipStream_t s) {
-    (void)rpc;
-    (void)nchunk;
+                         const double* inv_nu, int64_t N, int R, int Rt, hipStream_t s) {
+    MBT_REQUIRE(R % Rt == 0, "folded width must be a multiple of the RHS count");
     constexpr int RB = 8;
     const int64_t rows_per_block = 4 * RB;
     const int64_t gy = (N + rows_per_block - 1) / rows_per_block;
     MBT_REQUIRE(gy < 65536, "dcgs2 update: too many row blocks");
     hipLaunchKernelGGL((dcgs2_update_rows_kernel<TB, RB>), dim3((unsigned)((R + 63) / 64), (unsigned)gy), dim3(256), 0,
-                       s, V, vs, k, u, w, cs, cc, inv_nu, N, R);
+                       s, V, vs, k, u, w, cs, cc, inv_nu, N, R, Rt);
     MBT_LAUNCH_CHECK();
 }
 
@@ -914,6 +929,17 @@ void launch_reduce_partials(const double2* partial, int nchunk, int nvec, int R,
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nout + 63) / 64)), dim3(64 * kRedWaves), 0, s, partial,
                        nchunk, nvec, R, out);
     MBT_LAUNCH_CHECK();
+}
+
+// out[i][r] = sum_{f < F} in[i][f * R + r] in order of f (partials of folded rows)
+__global__ void unfold_kernel(const double2* __restrict__ in, int nvec, int R, int F, double2* __restrict__ out) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nvec * R) return;
+    const int64_t i = t / R;
+    const int r = (int)(t % R);
+    double2 acc = in[i * R * F + r];
+    for (int f = 1; f < F; ++f) acc = cadd(acc, in[i * R * F + (int64_t)f * R + r]);
+    out[t] = acc;
 }
 
 template <typename TB>
@@ -1111,6 +1137,21 @@ inline unsigned ew_grid(int64_t n) {
 int64_t gmres_rows_per_chunk(int64_t N) { return std::max<int64_t>(128, (N + 2047) / 2048); }
 int gmres_nchunk(int64_t N) { return (int)((N + gmres_rows_per_chunk(N) - 1) / gmres_rows_per_chunk(N)); }
 
+// Row folding: the DCGS2 sweeps give each lane one RHS column (two with the
+// packed basis) of a row, so batches narrower than 64 (128) columns would leave
+// lanes idle.  F consecutive rows of an N x R vector are the same memory as one
+// row of F*R columns; the sweeps run on N/F rows of F*R columns, index the
+// per-RHS coefficients by column mod R, and the dot partials of the F copies of
+// a RHS are summed afterwards in a fixed order.  F depends on N only, so a
+// RHS's sums have the same order whatever the width of its batch.
+int gmres_fold(int64_t N) { return N % 4 == 0 ? 4 : (N % 2 == 0 ? 2 : 1); }
+
+static size_t partial_values(int64_t N, int R, int m) {
+    const int F = gmres_fold(N);
+    return std::max((size_t)gmres_nchunk(N) * (2 * m + 2) * R,            // unfolded (CGS2)
+                    (size_t)gmres_nchunk(N / F) * (2 * m + 2) * R * F);   // folded (DCGS2)
+}
+
 size_t gmres_state_bytes(int64_t N, int R, int m) {
     const int nchunk = gmres_nchunk(N);
     size_t s = 0;
@@ -1120,7 +1161,9 @@ size_t gmres_state_bytes(int64_t N, int R, int m) {
     s += sizeof(double2) * (size_t)(m + 1) * R;                // g
     s += sizeof(double2) * (size_t)(m + 1) * R * 2;            // h1, h2
     s += sizeof(double2) * (size_t)m * R;                      // y
-    s += sizeof(double2) * (size_t)nchunk * (2 * m + 2) * R;   // partials
+    (void)nchunk;
+    s += sizeof(double2) * partial_values(N, R, m);            // partials (of folded rows too)
+    s += sizeof(double2) * (size_t)(2 * m + 2) * R * gmres_fold(N) + 256;   // chunk sums of folded rows
     s += sizeof(double2) * (size_t)R + 256;                    // reduced squared norms
     s += sizeof(double) * (size_t)R * 4 + sizeof(int) * (size_t)R * 7 + 12 * 256;
     // delayed reorthogonalisation: unrotated Hessenberg, reduced sweep, coefficients, 1/nu
@@ -1158,7 +1201,8 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     double2* h1 = arena.get<double2>((size_t)(m + 1) * R);
     double2* h2 = arena.get<double2>((size_t)(m + 1) * R);
     double2* y = arena.get<double2>((size_t)m * R);
-    double2* partial = arena.get<double2>((size_t)nchunk * (2 * m + 2) * R);
+    double2* partial = arena.get<double2>(partial_values(N, R, m));
+    double2* redf = arena.get<double2>((size_t)(2 * m + 2) * R * gmres_fold(N));
     double2* nrm2 = arena.get<double2>(R);
     double2* Hraw = nullptr;
     double2* red = nullptr;
@@ -1201,6 +1245,12 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
     const int64_t vs24 = vs / 2;
     TB* r0v = Vbasis;                                 // residual / first candidate (both layouts)
     TB* xb = Vbasis + vs;                             // iterate in the basis type (both layouts)
+    // the DCGS2 sweeps and the solution update run on folded rows
+    const int F = prm.dcgs2 ? gmres_fold(N) : 1;
+    const int64_t Nf = N / F;
+    const int Rf = R * F;
+    const int64_t rpcf = gmres_rows_per_chunk(Nf);
+    const int nchunkf = gmres_nchunk(Nf);
 
     // x = 0, r0 = b
     hipLaunchKernelGGL(zero_kernel, dim3(ew_grid(vs)), dim3(256), 0, s, x, vs);
@@ -1236,13 +1286,20 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
                 ProfScope ps(kKArnoldiDots, k * bbytes + (hasw ? 2 : 1) * vbytes, 8.0 * (2 * k + 2) * vs, s);
                 if (packed) {
                     if constexpr (std::is_same<TB, float2>::value)
-                        launch_dcgs2_dots<TB, p24x2>(V24, vs24, k, u, w, N, R, rpc, nchunk, partial, s);
+                        launch_dcgs2_dots<TB, p24x2>(V24, vs24, k, u, w, Nf, Rf, rpcf, nchunkf, partial, s);
                 } else {
-                    launch_dcgs2_dots<TB, TB>(Vbasis, vs, k, u, w, N, R, rpc, nchunk, partial, s);
+                    launch_dcgs2_dots<TB, TB>(Vbasis, vs, k, u, w, Nf, Rf, rpcf, nchunkf, partial, s);
                 }
             }
             const int nred = 2 * k + 2;
-            launch_reduce_partials(partial, nchunk, nred, R, red, s);
+            if (F == 1) {
+                launch_reduce_partials(partial, nchunkf, nred, R, red, s);
+            } else {
+                launch_reduce_partials(partial, nchunkf, nred, Rf, redf, s);
+                hipLaunchKernelGGL(unfold_kernel, dim3((unsigned)((nred * R + 255) / 256)), dim3(256), 0, s, redf, nred,
+                                   R, F, red);
+                MBT_LAUNCH_CHECK();
+            }
             hipLaunchKernelGGL(dcgs2_finalize_kernel, gR, bR, 0, s, st, Hraw, red, R, k, m, inv_nu);
             MBT_LAUNCH_CHECK();
             steps = k;
@@ -1255,10 +1312,10 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
                 ProfScope ps(kKArnoldiUpdateDots, (k + 1) * bbytes + 3 * vbytes, 16.0 * k * vs, s);
                 if (packed) {
                     if constexpr (std::is_same<TB, float2>::value)
-                        launch_dcgs2_update24(V24, vs24, k, U, Wv, V24 + (int64_t)k * vs24, coef_s, coef_c, inv_nu, N,
-                                              R, s);
+                        launch_dcgs2_update24(V24, vs24, k, U, Wv, V24 + (int64_t)k * vs24, coef_s, coef_c, inv_nu, Nf,
+                                              Rf, R, s);
                 } else {
-                    launch_dcgs2_update<TB>(Vbasis, vs, k, u, w, coef_s, coef_c, inv_nu, N, R, rpc, nchunk, s);
+                    launch_dcgs2_update<TB>(Vbasis, vs, k, u, w, coef_s, coef_c, inv_nu, Nf, Rf, R, s);
                 }
             }
         }
@@ -1296,9 +1353,9 @@ GmresResult gmres_batched(const std::function<void(const TB*, TB*)>& apply, cons
         // configuration fixed by m: a RHS's update x += V y does not depend on how long
         // the other RHS of the batch kept the cycle going
         if (packed)
-            launch_solution_update<p24x2>(V24, vs24, steps, y, x, N, R, s);
+            launch_solution_update<p24x2>(V24, vs24, steps, y, x, Nf, Rf, R, s);
         else
-            launch_solution_update<TB>(Vbasis, vs, steps, y, x, N, R, s);
+            launch_solution_update<TB>(Vbasis, vs, steps, y, x, Nf, Rf, R, s);
         // explicit residual r = b - A x into V_0 (x cast to the basis type into V_1 first)
         hipLaunchKernelGGL((from_f64_kernel<TB>), dim3(ew_grid(vs)), dim3(256), 0, s, x, xb, vs);
         MBT_LAUNCH_CHECK();

@@ -18,6 +18,11 @@
 // combines the moments of its two triangles in a fixed order:
 //   <<(r - v_m) . (r' - v_q) G>> = hw - v_q . hv,
 // so the block row is deterministic.  The work is FP64 transcendental-bound.
+// Blocks two or more lattice steps apart use the same rule on test and source
+// side, so T[-d] = T[d]^T for them (Galerkin reciprocity of the discrete
+// operator): only one of each such pair is integrated and the other is its
+// transpose; the nearer blocks, whose static part is integrated one-sidedly,
+// are all integrated.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -113,6 +118,7 @@ __global__ __launch_bounds__(512) void rwg_fill_kernel(RwgDev d, int nt, int M, 
     // the test element sits at lattice offset (ox, oy) from the source element at the origin
     const double sx = ox * ldx, sy = oy * ldy;
     const bool near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
+    if (!near && (oy < 0 || (oy == 0 && ox < 0))) return;   // the transpose of T[-d], filled afterwards
     for (int task = threadIdx.x; task < 2 * nt; task += blockDim.x) {
         const int side = task / nt, u = task - side * nt;
         const int t = d.btri[2 * m + side];
@@ -193,6 +199,19 @@ __global__ __launch_bounds__(512) void rwg_fill_kernel(RwgDev d, int nt, int M, 
         }
         T[((int64_t)off * M + m) * M + qb] = sum;
     }
+}
+
+// T[d] = T[-d]^T for the far offsets that the fill kernel skipped (one row p per thread block)
+__global__ __launch_bounds__(128) void rwg_mirror_kernel(int M, int nx, int ny, double2* __restrict__ T) {
+    const int nox = 2 * nx - 1;
+    const int off = blockIdx.x;
+    const int ox = off % nox - (nx - 1), oy = off / nox - (ny - 1);
+    const bool near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
+    if (near || !(oy < 0 || (oy == 0 && ox < 0))) return;
+    const int mirror = (-oy + (ny - 1)) * nox + (-ox + (nx - 1));
+    const int p = blockIdx.y;
+    for (int q = threadIdx.x; q < M; q += blockDim.x)
+        T[((int64_t)off * M + p) * M + q] = T[((int64_t)mirror * M + q) * M + p];
 }
 
 }  // namespace
@@ -326,6 +345,8 @@ void rwg_fill_blocks(const Geom& g, const RwgMesh& h, double k, double2* T, hipS
     const int threads = std::min(512, ((2 * nt + 63) / 64) * 64);
     hipLaunchKernelGGL(rwg_fill_kernel, dim3((unsigned)g.noff(), (unsigned)M), dim3(threads), 0, s, d, nt, M, g.nx,
                        g.ny, g.dx, g.dy, k, T);
+    MBT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rwg_mirror_kernel, dim3((unsigned)g.noff(), (unsigned)M), dim3(128), 0, s, M, g.nx, g.ny, T);
     MBT_LAUNCH_CHECK();
     // the tables are freed when this returns: wait for the kernel
     MBT_HIP(hipStreamSynchronize(s));
