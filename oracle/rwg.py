@@ -296,6 +296,43 @@ def fill_dense(el: RwgElement, lat, s: float, eta: float = ETA0) -> np.ndarray:
     return Z
 
 
+def z_rows(el: RwgElement, lat, s: float, unknowns, eta: float = ETA0, chunk: int = 256) -> np.ndarray:
+    """Rows of the dense Z (len(unknowns) x N) for arrays too large to fill
+    whole, from absolute positions exactly as fill_dense computes them (source
+    elements taken chunk elements at a time)."""
+    k = mom.wavenumber(s)
+    P = lat.nx * lat.ny
+    M, nt = el.M, len(el.tri)
+    pos = element_positions(lat)
+    ixy = np.stack(np.divmod(np.arange(P), lat.nx)[::-1], axis=1)
+    txy = el.vert[el.tri]
+    all_area = np.tile(el.area, P)
+    e_of_n = np.repeat(np.arange(P), M)
+    m_of_n = np.tile(np.arange(M), P)
+    src_tplus = e_of_n * nt + el.tplus[m_of_n]
+    src_tminus = e_of_n * nt + el.tminus[m_of_n]
+    src_vplus = el.vert[el.vplus[m_of_n]] + pos[e_of_n]
+    src_vminus = el.vert[el.vminus[m_of_n]] + pos[e_of_n]
+    length_n = el.length[m_of_n]
+    out = np.zeros((len(unknowns), P * M), dtype=np.complex128)
+    for i, n in enumerate(unknowns):
+        e, m = divmod(int(n), M)
+        near_e = np.repeat(np.max(np.abs(ixy - ixy[e]), axis=1) <= 1, nt)
+        vt = el.vert + pos[e]
+        for t in (el.tplus[m], el.tminus[m]):
+            parts = []
+            for e0 in range(0, P, chunk):
+                e1 = min(P, e0 + chunk)
+                src = (pos[e0:e1, None, None, :] + txy[None]).reshape((e1 - e0) * nt, 3, 2)
+                parts.append(pair_integrals(k, txy[t] + pos[e], src, near_e[e0 * nt:e1 * nt]))
+            ints = tuple(np.concatenate([p[j] for p in parts]) for j in range(4)) + (
+                parts[0][4], np.concatenate([p[5] for p in parts]))
+            rows = _assemble_rows(el, k, eta, t, vt, ints, all_area, src_vplus, src_vminus, src_tplus,
+                                  src_tminus, length_n)
+            out[i] += rows[m]
+    return out
+
+
 def offset_block(el: RwgElement, lat, s: float, dx: int, dy: int, eta: float = ETA0) -> np.ndarray:
     """The M x M block between a test element and the source element (-dx, -dy)
     lattice steps away (Z[t][s] = T[t - s]), from their absolute positions:

@@ -89,6 +89,42 @@ def test_rwg_blocks_full_size_sampled_offsets(ctx, bowtie):
         mbt.mbt_array_destroy(a)
 
 
+def test_rwg_full_size_solution_satisfies_oracle_rows(ctx, bowtie):
+    """64 x 64 bowties (N = 393,216), too large for the oracle to factor: the FP64
+    GPU solution of four phased-voltage excitations satisfies sampled rows of
+    Z I = V, with those rows of Z computed by the oracle from absolute positions
+    (gap bases of the center and a corner element, an interior basis, a border
+    element)."""
+    from paper_2608_17844_amd import mbt
+    mesh, el = bowtie
+    lat = W.Lattice(64, 64, 0.5, 0.5)
+    s = 1.1
+    P, M = lat.nx * lat.ny, el.M
+    theta, phi = W.scan_angles(3, seed=4, broadside_first=True)
+    Vp = rwg.scan_voltages(lat, s, theta, phi)                       # (P, 4) gap voltages
+    V = np.zeros((P * M, Vp.shape[1]), dtype=np.complex128)
+    idx = np.arange(P)[:, None] * M + el.port_bases[None, :]
+    V[idx, :] = el.port_weights[None, :, None] * Vp[:, None, :]
+    a = mbt.mbt_array_create_rwg(ctx, mesh, lat)
+    try:
+        opts = mbt.mbt_default_opts(prec=mbt.MBT_FP64, restart=50, tol=1e-11, max_cycles=100)
+        I, it, st = mbt.mbt_dbg_solve(ctx, a, s, opts, V)
+        _say("64x64 FP64 solve: iterations %s, true residual %.2e" % (list(it), st["true_relres_max"]))
+        c = mom.center_element(lat)
+        rows = [c * M + int(el.port_bases[0]), c * M + 10, 63 * M + int(el.port_bases[1]), (64 * 40 + 7) * M + 80]
+        Zr = rwg.z_rows(el, lat, s, rows)
+        res = Zr @ I - V[rows, :]
+        rel = np.abs(res) / np.linalg.norm(V, axis=0)[None, :]
+        _say("sampled rows of Z I - V over ||V||: %s" % np.array2string(rel.max(axis=1), precision=2))
+        assert rel.max() < 1e-8
+        # the gap currents the scan entry point returns are W^T I of the same solve
+        r = mbt.mbt_scan_solve(ctx, a, s, opts, theta, phi)
+        Ip = (el.port_weights[None, :, None] * I[idx, :]).sum(axis=1)
+        assert np.abs(r["Ip"] - Ip).max() < 1e-9 * np.abs(Ip).max()
+    finally:
+        mbt.mbt_array_destroy(a)
+
+
 @pytest.fixture(scope="module")
 def small_oracle(bowtie):
     mesh, el = bowtie

@@ -213,3 +213,10 @@ def test_port_passivity_and_scan_consistency(array_3x2):
     assert np.abs(Ip - Yp @ V).max() < 1e-9 * np.abs(Ip).max()
     c = mom.center_element(lat)
     assert np.abs(Za - (Zp @ Ip)[c] / Ip[c]).max() < 1e-8 * np.abs(Za).max()
+
+
+def test_z_rows_equal_dense_rows(array_3x2):
+    """Rows computed for arrays too large to fill whole equal the dense fill's."""
+    el, lat, Z = array_3x2
+    n = [0, 47, 4 * el.M + 50, Z.shape[0] - 1]
+    assert np.array_equal(rwg.z_rows(el, lat, 1.0, n, chunk=2), Z[n])
