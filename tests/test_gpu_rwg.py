@@ -121,6 +121,14 @@ def test_rwg_full_size_solution_satisfies_oracle_rows(ctx, bowtie):
         r = mbt.mbt_scan_solve(ctx, a, s, opts, theta, phi)
         Ip = (el.port_weights[None, :, None] * I[idx, :]).sum(axis=1)
         assert np.abs(r["Ip"] - Ip).max() < 1e-9 * np.abs(Ip).max()
+        # the mixed path (FP32 products, FP64 refinement) reaches the same gap currents and Z_a
+        mixed = mbt.mbt_default_opts(prec=mbt.MBT_FP32, restart=32, inner_tol=3e-3, refine_tol=1e-10,
+                                     refine_max=8)
+        rm = mbt.mbt_scan_solve(ctx, a, s, mixed, theta, phi)
+        e_ip = np.abs(rm["Ip"] - Ip).max() / np.abs(Ip).max()
+        e_za = np.max(np.abs(rm["Za"] - r["Za"]) / np.abs(r["Za"]))
+        _say("mixed against FP64: Ip %.2e, Za %.2e, outer steps %d" % (e_ip, e_za, rm["stats"]["outer_steps"]))
+        assert e_ip < 1e-8 and e_za < 1e-8
     finally:
         mbt.mbt_array_destroy(a)
 
