@@ -489,8 +489,8 @@ def verify_served(mbt, srv, submit, collect, reqs, res, ids):
 
 def blocks_shape(args):
     """Largest single-GPU shape: 64 x 64 elements of 96 bases (N = 393,216, FFT
-    grid 128 x 128) with seeded synthetic blocks (the planar element's fill is
-    not built), 32 port excitations per operator, 5 operators; FP32 products
+    grid 128 x 128) with seeded synthetic blocks (a solver-only variant of the
+    bowtie workload, --bowtie), 32 port excitations per operator, 5 operators; FP32 products
     with FP64 refinement.  Reports operator applications per second and the
     rooflines of the per-bin product (large-block MFMA kernel) and the FFTs."""
     from paper_2608_17844_amd import mbt

@@ -85,8 +85,8 @@ def gpu_size_32x32() -> Workload:
 def blocks_64x64_m96_shape():
     """The largest single-GPU shape: 64 x 64 elements of 96 bases (N = 393,216),
     FFT grid 128 x 128, 32 port excitations per operator and 5 operators (one
-    per frequency; seeds 0..4 of synthetic_blocks), since the 96-basis planar
-    element fill is not part of this build.  Returns (nx, ny, M, seeds, ports)."""
+    per frequency; seeds 0..4 of synthetic_blocks): the solver-only variant of
+    the bowtie workload.  Returns (nx, ny, M, seeds, ports)."""
     rng = np.random.default_rng(0)
     ports = np.sort(rng.choice(64 * 64, size=32, replace=False)).astype(np.int32)
     return 64, 64, 96, [0, 1, 2, 3, 4], ports
@@ -100,8 +100,8 @@ def sweep_5x5_21f() -> Workload:
 
 
 def synthetic_blocks(nx: int, ny: int, nbases: int, seed: int = 0, coupling: float = 0.05) -> np.ndarray:
-    """Seeded unique blocks of a block-Toeplitz lattice operator for workloads
-    whose element fill is not built (the 96-basis planar elements): T[dy][dx]
+    """Seeded unique blocks of a block-Toeplitz lattice operator for solver-only
+    workloads (caller-given blocks instead of an element fill): T[dy][dx]
     (M x M complex, offsets dy + ny - 1, dx + nx - 1) with the reciprocity of a
     Galerkin operator, T(-d) = T(d)^T, a symmetric self block I (1 + 0.5j) plus
     a small random part, and random coupling blocks whose size decays as 1/|d|.

@@ -1,6 +1,6 @@
-"""Block-defined lattice operators on the GPU (the 96-basis elements of the
-largest single-GPU shape, with seeded synthetic blocks since their fill is not
-built): the per-bin products of large blocks (LDS-staged MFMA), the matvec
+"""Block-defined lattice operators on the GPU (caller-given blocks of up to 128
+bases per element, here seeded synthetic blocks; the RWG elements of the largest
+single-GPU shape have their own tests in test_gpu_rwg.py): the per-bin products of large blocks (LDS-staged MFMA), the matvec
 and preconditioned solves against the dense oracle on small lattices, and at
 the full 64 x 64 x 96 shape sampled entries of Z x and of the residual
 V - Z I computed entry by entry by the oracle."""
