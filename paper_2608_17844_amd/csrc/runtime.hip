@@ -807,7 +807,9 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
         std::function<void(const float2*, float2*)> f = [&](const float2* x, float2* y) { apply_A<float>(ov32, x, y); };
         prm.tol = inner_tol(o);
         zero_d(X, NR, s);
-        std::vector<int> done(R, 0), flagged(R, 0);
+        std::vector<int> done(R, 0), flagged(R, 0), raised(R, 0);
+        // FP64 residual norm before the last correction (X = 0 at first: ||V||)
+        std::vector<double> prev(vn), hundo(R);
         for (int outer = 0; outer < o.refine_max; ++outer) {
             if (outer == 0) {
                 convert<double2, double2>(V, r64, NR, s);
@@ -818,13 +820,33 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
             }
             std::vector<double> rn;
             norms_host(r64, g.N, R, arena, rn, s);
+            // Refinement contracts only while the reduced-precision operator's error is small
+            // against the smallest singular values of Z; where it is not, the iterates can
+            // grow without bound.  A correction that raised the FP64 residual is taken back
+            // (d still holds it) and that RHS stops refining with the better iterate.
+            int nundo = 0;
+            for (int r = 0; r < R; ++r) {
+                hundo[r] = 0.0;
+                if (outer > 0 && !raised[r] && rn[r] > prev[r]) {
+                    hundo[r] = 1.0;
+                    raised[r] = 1;
+                    ++nundo;
+                } else if (!raised[r]) {
+                    prev[r] = rn[r];
+                }
+            }
+            if (nundo > 0) {
+                MBT_HIP(hipMemcpyAsync(mask, hundo.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+                scale_columns_d(d, mask, g.N, R, s);
+                sub_d(X, d, X, NR, s);
+            }
             // the correction equation Z d = r is solved for r / ||r|| (unit columns keep the
             // reduced-precision spectra inside the 16-bit range), then d is scaled back
             std::vector<double> hmask(2 * R);
             int left = 0;
             for (int r = 0; r < R; ++r) {
                 const double rel = vn[r] > 0 ? rn[r] / vn[r] : 0.0;
-                done[r] = (rel <= o.refine_tol) || flagged[r] || !(rn[r] > 0);
+                done[r] = (rel <= o.refine_tol) || flagged[r] || raised[r] || !(rn[r] > 0);
                 hmask[r] = done[r] ? 0.0 : 1.0 / rn[r];
                 hmask[R + r] = done[r] ? 0.0 : rn[r];
                 left += done[r] ? 0 : 1;
@@ -1533,6 +1555,24 @@ mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t 
         f2.alloc(sizeof(float2) * NR);
         OpV<float> ov = make_view<float>(*op, MBT_PC_ELEMENT_BLOCK, Xh.p, Yh.p, tmp.p, R, wk.stream, fmt16_of(prec));
         attach_margin(ov, mscr.p);
+        // The 16-bit spectra carry no scale of their own: columns go in with unit norm, as
+        // the solvers' Krylov vectors do (binary16 overflows at 65504), and come out rescaled.
+        DBuf cs;
+        std::vector<double> hs(2 * (size_t)R, 1.0);
+        if (prec != MBT_FP32) {
+            for (int r = 0; r < R; ++r) {
+                double ss = 0;
+                for (int64_t i = 0; i < 2 * g.N; ++i) ss += x[2 * g.N * r + i] * x[2 * g.N * r + i];
+                const double nrm = std::sqrt(ss);
+                if (nrm > 0 && std::isfinite(nrm)) {
+                    hs[r] = 1.0 / nrm;
+                    hs[R + r] = nrm;
+                }
+            }
+            cs.alloc(sizeof(double) * 2 * R);
+            MBT_HIP(hipMemcpyAsync(cs.p, hs.data(), sizeof(double) * 2 * R, hipMemcpyHostToDevice, wk.stream));
+            scale_columns_d(dx.as<double2>(), cs.as<double>(), g.N, R, wk.stream);
+        }
         convert<double2, float2>(dx.as<double2>(), f1.as<float2>(), NR, wk.stream);
         if (opz == 2) {
             zmul<float>(ov, 0, f1.as<float2>(), ov.tmp);
@@ -1541,6 +1581,7 @@ mbt_status mbt_dbg_matvec(mbt_ctx* ctx, const mbt_array* arr, double s, int32_t 
             zmul<float>(ov, opz, f1.as<float2>(), f2.as<float2>());
         }
         convert<float2, double2>(f2.as<float2>(), dy.as<double2>(), NR, wk.stream);
+        if (prec != MBT_FP32) scale_columns_d(dy.as<double2>(), cs.as<double>() + R, g.N, R, wk.stream);
     }
     transpose_nr(dy.as<double2>(), hx.as<double2>(), g.N, R, false, wk.stream);
     MBT_HIP(hipMemcpyAsync(y, hx.p, sizeof(double2) * NR, hipMemcpyDeviceToHost, wk.stream));
