@@ -200,10 +200,13 @@ typedef struct {
  * V sign_m l_m, and the gap current is sum sign_m l_m I_m (sign_m = +1 when the
  * basis's + -> - direction has a positive component along port_dir); Y_p and
  * Z_p are in these gap voltages and currents.  Limits: 1..128 interior edges,
- * 2..256 triangles, 3..4096 vertices, 1..8 feed edges, nx, ny 1..64; 16-bit
- * products only up to 32 bases.  Errors: MBT_EINVAL (sizes, non-finite or
- * degenerate geometry, an edge of more than two triangles, a feed edge that is
- * not interior or is parallel to port_dir). */
+ * 2..256 triangles, 3..4096 vertices, 1..8 feed edges, nx, ny 1..64; the
+ * triangles' extent along x (y) below 2 dx (2 dy) when nx (ny) >= 3, so that
+ * elements two or more steps apart, which the point rule alone integrates, are
+ * disjoint; 16-bit products only up to 32 bases.  Errors: MBT_EINVAL (sizes,
+ * non-finite or degenerate geometry, an edge of more than two triangles, a feed
+ * edge that is not interior or is parallel to port_dir, an element too large for
+ * its lattice). */
 mbt_status mbt_array_create_rwg(mbt_ctx* ctx, const mbt_rwg_mesh* mesh, const mbt_lattice* lat, mbt_array** out);
 
 /* Array whose impedance matrix has a margin besides its elements (Sec. II-A

@@ -435,6 +435,22 @@ std::shared_ptr<OpData> get_op(mbt_ctx* ctx, const mbt_array* arr, double s, boo
     return op;
 }
 
+// A private operator with every piece the options need (MBT_FLAG_NO_CACHE): the
+// same pieces get_op adds to a cached entry.
+static std::shared_ptr<OpData> build_uncached(const mbt_array* arr, double s, const mbt_solve_opts& o, Worker& wk) {
+    const int fmt = fmt16_of(o.prec);
+    MBT_REQUIRE(fmt == kFmtNone || arr->g.M <= 32, "16-bit products support at most 32 bases per element");
+    auto op = build_op(arr, s, wk);
+    const bool pa = o.pc == MBT_PC_NORMAL_EQ;
+    if (pa) build_pa(*op, wk);
+    if (o.prec != MBT_FP64) {
+        build_32(*op, wk);
+        if (pa) build_32_pa(*op, wk);
+    }
+    if (fmt != kFmtNone) build_16(*op, fmt, wk);
+    return op;
+}
+
 // ------------------------------------------------------------------ operator application
 template <typename T> struct OpV {
     const Geom* g;
@@ -492,8 +508,10 @@ OpV<double> make_view<double>(const OpData& op, int pc, void* Xh, void* Yh, void
         v.zb = op.ZB.as<double2>();
         v.zc = op.ZC.as<double2>();
         v.pcinv = pc == MBT_PC_NORMAL_EQ ? op.PcInv.as<double2>() : op.ZcInv.as<double2>();
+        MBT_REQUIRE(v.zb && v.zc && v.pcinv, "margin pieces not built for this operator");
     }
     v.pinv = pc == MBT_PC_NORMAL_EQ ? op.PaInv.as<double2>() : op.PkInv.as<double2>();
+    MBT_REQUIRE(v.pinv != nullptr, "preconditioner not built for this operator");
     v.pstride = pc == MBT_PC_NORMAL_EQ ? (int64_t)op.g.M * op.g.M : 0;
     v.twx = op.tw.as<double2>();
     v.twy = op.tw.as<double2>() + op.g.Px;
@@ -524,8 +542,10 @@ OpV<float> make_view<float>(const OpData& op, int pc, void* Xh, void* Yh, void* 
         v.zb = op.ZB32.as<float2>();
         v.zc = op.ZC32.as<float2>();
         v.pcinv = pc == MBT_PC_NORMAL_EQ ? op.PcInv32.as<float2>() : op.ZcInv32.as<float2>();
+        MBT_REQUIRE(v.zb && v.zc && v.pcinv, "margin pieces not built for this operator");
     }
     v.pinv = pc == MBT_PC_NORMAL_EQ ? op.PaInv32.as<float2>() : op.PkInv32.as<float2>();
+    MBT_REQUIRE(v.pinv != nullptr && v.Chat != nullptr, "FP32 operator pieces not built");
     v.pstride = pc == MBT_PC_NORMAL_EQ ? (int64_t)op.g.M * op.g.M : 0;
     v.twx = op.tw32.as<float2>();
     v.twy = op.tw32.as<float2>() + op.g.Px;
@@ -928,11 +948,7 @@ SolveOut admittance(mbt_ctx* ctx, const mbt_array* arr, double s, const int32_t*
     const double t0 = now_s();
     std::shared_ptr<OpData> op;
     if (o.flags & MBT_FLAG_NO_CACHE) {
-        MBT_REQUIRE(fmt16_of(o.prec) == kFmtNone || g.M <= 32, "16-bit products support at most 32 bases per element");
-        op = build_op(arr, s, wk);
-        if (o.pc == MBT_PC_NORMAL_EQ) build_pa(*op, wk);
-        if (o.prec != MBT_FP64) build_32(*op, wk);
-        if (fmt16_of(o.prec) != kFmtNone) build_16(*op, fmt16_of(o.prec), wk);
+        op = build_uncached(arr, s, o, wk);
     } else {
         op = get_op(ctx, arr, s, o.pc == MBT_PC_NORMAL_EQ, o.prec, wk);
     }
@@ -1007,11 +1023,7 @@ static SolveOut scan_solve(mbt_ctx* ctx, const mbt_array* arr, double s, const m
     const double t0 = now_s();
     std::shared_ptr<OpData> op;
     if (o.flags & MBT_FLAG_NO_CACHE) {
-        MBT_REQUIRE(fmt16_of(o.prec) == kFmtNone || g.M <= 32, "16-bit products support at most 32 bases per element");
-        op = build_op(arr, s, wk);
-        if (o.pc == MBT_PC_NORMAL_EQ) build_pa(*op, wk);
-        if (o.prec != MBT_FP64) build_32(*op, wk);
-        if (fmt16_of(o.prec) != kFmtNone) build_16(*op, fmt16_of(o.prec), wk);
+        op = build_uncached(arr, s, o, wk);
     } else {
         op = get_op(ctx, arr, s, o.pc == MBT_PC_NORMAL_EQ, o.prec, wk);
     }
@@ -1257,6 +1269,19 @@ mbt_status mbt_array_create_rwg(mbt_ctx* ctx, const mbt_rwg_mesh* mesh, const mb
     MBT_REQUIRE(l->dx > 0 && l->dy > 0 && std::isfinite(l->dx) && std::isfinite(l->dy),
                 "lattice spacing must be positive");
     auto h = std::make_shared<RwgMesh>(rwg_from_mesh(*mesh));
+    // Only elements at most one step apart get the closed-form static part; farther
+    // ones are integrated by the point rule alone and must therefore be disjoint:
+    // the triangles' extent along an axis with three or more elements stays below
+    // two lattice steps.
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (const double2& v : h->tv) {
+        x0 = std::min(x0, v.x);
+        x1 = std::max(x1, v.x);
+        y0 = std::min(y0, v.y);
+        y1 = std::max(y1, v.y);
+    }
+    MBT_REQUIRE(l->nx < 3 || x1 - x0 < 2.0 * l->dx, "the element's x extent must stay below two lattice steps");
+    MBT_REQUIRE(l->ny < 3 || y1 - y0 < 2.0 * l->dy, "the element's y extent must stay below two lattice steps");
     std::unique_ptr<mbt_array> a(new mbt_array());
     a->g = make_geom_blocks(l->nx, l->ny, h->M);
     a->g.dx = l->dx;

@@ -175,3 +175,28 @@ def test_pcg_with_16bit_products_refines(ctx, cfg1, cfg1_oracle, prec):
     assert errs[1] < errs[0] / 10
     if prec == "fp16":
         assert errs[1] <= 1e-8
+
+
+@pytest.mark.parametrize("solver", ["gmres", "pcg"])
+def test_uncached_reduced_precision_normal_equations(ctx, cfg1, cfg1_oracle, solver):
+    """MBT_FLAG_NO_CACHE builds a private operator with every piece the options
+    need; with P_A and FP32 inner solves that includes the FP32 copy of the P_A
+    inverses, for the admittance route and for the phased-voltage scan solve."""
+    from paper_2608_17844_amd import mbt
+    from oracle import rwg
+    flags = mbt.MBT_FLAG_NO_CACHE | (mbt.MBT_FLAG_PCG if solver == "pcg" else 0)
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_NORMAL_EQ, flags=flags, refine_tol=1e-11,
+                                refine_max=8)
+    a = mbt.mbt_array_create_dipole(ctx, cfg1.dipole, cfg1.lattice)
+    try:
+        out = mbt.mbt_solve(ctx, a, 1.0, opts, cfg1.theta, cfg1.phi, cfg1.z0)
+        scan = mbt.mbt_scan_solve(ctx, a, 1.0, opts, cfg1.theta, cfg1.phi)
+    finally:
+        mbt.mbt_array_destroy(a)
+    ref = cfg1_oracle
+    ez = np.linalg.norm(out["Zp"] - ref.Zp) / np.linalg.norm(ref.Zp)
+    V = rwg.scan_voltages(cfg1.lattice, 1.0, cfg1.theta, cfg1.phi)
+    Ipr = ref.Yp @ V
+    ei = np.abs(scan["Ip"] - Ipr).max() / np.abs(Ipr).max()
+    _say("uncached %s fp32 P_A: |dZp|/|Zp| %.2e, scan |dIp| %.2e" % (solver, ez, ei))
+    assert ez <= 1e-9 and ei <= 1e-9

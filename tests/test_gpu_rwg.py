@@ -232,3 +232,9 @@ def test_rwg_mesh_validation(ctx):
     t = good.triangles.copy()
     t[0, 0] = 10_000
     assert "out of range" in bad(triangles=t)
+    # elements two steps apart would overlap: only nearer blocks take the singular part in closed form
+    with pytest.raises(mbt.MbtError) as e:
+        mbt.mbt_array_create_rwg(ctx, W.strip_mesh(1.0, 0.02, 20, 1), W.Lattice(3, 1, 0.45, 0.5))
+    assert e.value.status == mbt.MBT_EINVAL and "extent" in str(e.value)
+    a = mbt.mbt_array_create_rwg(ctx, W.strip_mesh(1.0, 0.02, 20, 1), W.Lattice(2, 3, 0.45, 0.5))
+    mbt.mbt_array_destroy(a)
