@@ -84,6 +84,11 @@ def test_fill_blocks_match_dense_oracle(ctx, make_array, shape):
         assert worst <= 1e-13 * np.max(np.abs(Z)), worst
 
 
+
+def _pow2(n):
+    """The lattice transform length along an axis: the power of two >= n, at least 8."""
+    return max(8, 1 << (int(n) - 1).bit_length())
+
 @pytest.mark.parametrize("shape", SHAPES, ids=[_ids(s) for s in SHAPES])
 def test_toeplitz_matvec_matches_dense(ctx, make_array, shape):
     from paper_2608_17844_amd import mbt
@@ -93,13 +98,22 @@ def test_toeplitz_matvec_matches_dense(ctx, make_array, shape):
     Z = mom.fill_dense(lat, dip, 1.0)
     N = Z.shape[0]
     x = W.random_vectors(N, 5, seed=7)
-    for op, ref in ((0, Z @ x), (1, Z.conj().T @ x), (2, Z.conj().T @ (Z @ x))):
+    # element by element against |Z| |x| (the sum of the magnitudes that rounding acts on):
+    # each output goes through the two lattice transforms (log2 of the grid size) and a
+    # sum over the M bases of its bin, so 16 (log2(grid) + M) units of roundoff
+    grid = 4 * _pow2(lat.nx) * _pow2(lat.ny)
+    c = 16 * (np.log2(grid) + dip.nbases)
+    aZ, ax = np.abs(Z), np.abs(x)
+    for op, ref, mag in ((0, Z @ x, aZ @ ax), (1, Z.conj().T @ x, aZ.T @ ax),
+                         (2, Z.conj().T @ (Z @ x), aZ.T @ (aZ @ ax))):
         y = mbt.mbt_dbg_matvec(ctx, a, 1.0, x, op=op)
         err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
         assert err <= 1e-13, (op, err)
+        assert np.all(np.abs(y - ref) <= c * 2.0 ** -53 * (2 if op == 2 else 1) * mag), op
         y32 = mbt.mbt_dbg_matvec(ctx, a, 1.0, x, op=op, prec=mbt.MBT_FP32)
         err32 = np.linalg.norm(y32 - ref) / np.linalg.norm(ref)
         assert err32 <= 2e-6, (op, err32)
+        assert np.all(np.abs(y32 - ref) <= c * 2.0 ** -24 * (2 if op == 2 else 1) * mag), op
 
 
 def test_matvec_columns_are_independent_of_batch(ctx, make_array):
@@ -130,12 +144,26 @@ def test_preconditioner_blocks_and_apply(ctx, make_array, shape):
     Pk = mbt.mbt_dbg_precond_blocks(ctx, a, 1.0, mbt.MBT_PC_ELEMENT_BLOCK, P, M)
     assert np.abs(Pk[0] - mom.block(Z, lat, dip, 0, 0)).max() <= 1e-13 * np.abs(Z).max()
     x = W.random_vectors(Z.shape[0], 3, seed=5)
+    xb = x.reshape(P, M, 3)
+
+    def componentwise(y, blocks):
+        # each element's block of P^{-1} x element by element: an inverse X of B formed by
+        # elimination is within c M u |X| |B| |X| of the exact one (componentwise), so the
+        # applied block is within 4 M u |X| |B| |X| |x_b| plus the product's own rounding
+        for e in range(P):
+            B = blocks[e if len(blocks) > 1 else 0]
+            X = np.linalg.inv(B)
+            bound = 4 * M * 2.0 ** -53 * (np.abs(X) @ (np.abs(B) @ (np.abs(X) @ np.abs(xb[e]))))
+            assert np.all(np.abs(y.reshape(P, M, 3)[e] - X @ xb[e]) <= bound), e
+
     y = mbt.mbt_dbg_precond_apply(ctx, a, 1.0, x, mbt.MBT_PC_NORMAL_EQ)
     ref = np.stack([og.pa_apply(og.pa_factors(ref_blocks), x[:, j], M) for j in range(3)], axis=1)
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-11
+    componentwise(y, ref_blocks)
     y = mbt.mbt_dbg_precond_apply(ctx, a, 1.0, x, mbt.MBT_PC_ELEMENT_BLOCK)
     ref = np.stack([og.pk_apply(og.pk_factors(Z, lat, dip), x[:, j], M) for j in range(3)], axis=1)
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-11
+    componentwise(y, [mom.block(Z, lat, dip, 0, 0)])
 
 
 def _tie(ref, k):
