@@ -32,6 +32,11 @@ def ctx():
 CASES = [(3, 2, 48), (4, 4, 96), (2, 3, 128), (5, 1, 33)]
 
 
+
+def _pow2(n):
+    """The lattice transform length along an axis: the power of two >= n, at least 8."""
+    return max(8, 1 << (int(n) - 1).bit_length())
+
 @pytest.mark.parametrize("case", CASES, ids=["%dx%d_m%d" % c for c in CASES])
 def test_block_matvec_matches_dense(ctx, case):
     from paper_2608_17844_amd import mbt
@@ -43,13 +48,19 @@ def test_block_matvec_matches_dense(ctx, case):
         assert np.array_equal(Tg, T)
         Z = ob.dense_from_blocks(T, nx, ny)
         x = W.random_vectors(Z.shape[0], 19, seed=1)
-        for prec, tol in ((0, 1e-13), (1, 3e-6)):
+        # element by element against |Z| |x|: two lattice transforms and a sum over M bases
+        c = 16 * (np.log2(4 * _pow2(nx) * _pow2(ny)) + M)
+        aZ, ax = np.abs(Z), np.abs(x)
+        for prec, tol, u in ((0, 1e-13, 2.0 ** -53), (1, 3e-6, 2.0 ** -24)):
             for op in (0, 1, 2):
                 y = mbt.mbt_dbg_matvec(ctx, a, 1.0, x, op=op, prec=prec)
                 ref = Z @ x if op == 0 else (Z.conj().T @ x if op == 1 else Z.conj().T @ (Z @ x))
+                mag = aZ @ ax if op == 0 else (aZ.T @ ax if op == 1 else aZ.T @ (aZ @ ax))
                 err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
-                _say("%dx%d M=%d prec=%d op=%d err=%.2e" % (nx, ny, M, prec, op, err))
+                comp = np.max(np.abs(y - ref) / mag)
+                _say("%dx%d M=%d prec=%d op=%d err=%.2e componentwise %.2e" % (nx, ny, M, prec, op, err, comp))
                 assert err <= tol
+                assert comp <= c * u * (2 if op == 2 else 1)
     finally:
         mbt.mbt_array_destroy(a)
 

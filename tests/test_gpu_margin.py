@@ -51,13 +51,20 @@ def test_margin_matvec_matches_dense(ctx, case):
         assert info["N"] == nx * ny * M + nc
         Z = omg.dense(T, nx, ny, ZB, ZC)
         x = W.random_vectors(Z.shape[0], 13, seed=2)
-        for prec, tol in ((0, 1e-13), (1, 3e-6)):
+        # element by element against |Z| |x|: the lattice part as for block arrays, plus the
+        # dense margin terms, sums of at most N terms (the worst-case bound of plain summation)
+        c = 16 * (np.log2(4 * max(8, 1 << (nx - 1).bit_length()) * max(8, 1 << (ny - 1).bit_length())) + M) + Z.shape[0]
+        aZ, ax = np.abs(Z), np.abs(x)
+        for prec, tol, u in ((0, 1e-13, 2.0 ** -53), (1, 3e-6, 2.0 ** -24)):
             for op in (0, 1, 2):
                 y = mbt.mbt_dbg_matvec(ctx, a, 1.0, x, op=op, prec=prec)
                 ref = Z @ x if op == 0 else (Z.conj().T @ x if op == 1 else Z.conj().T @ (Z @ x))
+                mag = aZ @ ax if op == 0 else (aZ.T @ ax if op == 1 else aZ.T @ (aZ @ ax))
                 err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
-                _say("%s prec=%d op=%d err=%.2e" % (case, prec, op, err))
+                comp = np.max(np.abs(y - ref) / mag)
+                _say("%s prec=%d op=%d err=%.2e componentwise %.2e" % (case, prec, op, err, comp))
                 assert err <= tol
+                assert comp <= c * u * (2 if op == 2 else 1)
     finally:
         mbt.mbt_array_destroy(a)
 
