@@ -65,10 +65,14 @@ typedef enum {
  * MBT_FP32, but the forward FFT stores the spectrum X^ in 16-bit complex and
  * the per-bin products take X^ and the block spectra C^ in bfloat16 / binary16
  * on the 16x16x32 MFMA with FP32 accumulation and FP32 output.  In every
- * reduced precision the Krylov basis is stored in FP32 with FP64 dot products,
- * Givens rotations are FP64, the preconditioner apply is FP32, and FP64
- * iterative refinement with an FP64 residual recovers the accuracy (inner
- * tolerance by default 1e-4 for FP32, 1e-3 for FP16, 1e-2 for BF16). */
+ * reduced precision the Krylov basis is kept in reduced precision (see
+ * MBT_FLAG_FP32_BASIS) with FP64 dot products, Givens rotations are FP64, the
+ * preconditioner apply is FP32, and FP64 iterative refinement with an FP64
+ * residual recovers the accuracy (inner tolerance by default 1e-4 for FP32,
+ * 1e-3 for FP16, 1e-2 for BF16).  A refinement step that raises a RHS's FP64
+ * residual is taken back and that RHS stops refining, so the returned currents
+ * are the best iterate; it then counts as not converged unless it met
+ * refine_tol. */
 typedef enum { MBT_FP64 = 0, MBT_FP32 = 1, MBT_BF16 = 2, MBT_FP16 = 3 } mbt_prec;
 
 /* Preconditioning strategy.
