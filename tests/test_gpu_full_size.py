@@ -178,3 +178,21 @@ def test_pcg_mixed_full_size(setup):
     _say({k: "%.2e" % v for k, v in e.items()}, out["stats"]["outer_steps"], out["stats"]["iters_max"])
     assert out["stats"]["nconverged"] == 1024
     assert _mixed_bar(e), e
+
+
+def test_bf16_products_full_size(setup):
+    """bfloat16 per-bin products (the survey's mixed-BF16 variant) at full size:
+    inner GMRES(32) to 1e-2, up to 8 FP64 refinement steps towards 1e-7.  The
+    products carry a 1e-3 operator error and the refinement contracts slowly on
+    this ill-conditioned array, so most RHS stop short of 1e-7 (reported as not
+    converged); the port quantities still reach the measured 3e-8 norm-wise
+    (bounds here with a margin of about 30)."""
+    mbt, ctx, arr, w, ref = setup
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_BF16, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=32, refine_tol=1e-7,
+                                refine_max=8, inner_tol=1e-2, flags=mbt.MBT_FLAG_NO_CACHE)
+    out = mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0, allow_noconv=True)
+    e = _errors(out, ref)
+    _say({k: "%.2e" % v for k, v in e.items()}, out["stats"]["outer_steps"], out["stats"]["nconverged"])
+    assert out["status"] in (mbt.MBT_OK, mbt.MBT_ENOCONV)
+    assert e["zp_fro_rel_sketch"] <= 1e-6 and e["zp_center_row"] <= 1e-6
+    assert e["zp_samples_elementwise"] <= 1e-4 and e["gamma_rel"] <= 1e-5
