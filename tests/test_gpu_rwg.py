@@ -238,3 +238,32 @@ def test_rwg_mesh_validation(ctx):
     assert e.value.status == mbt.MBT_EINVAL and "extent" in str(e.value)
     a = mbt.mbt_array_create_rwg(ctx, W.strip_mesh(1.0, 0.02, 20, 1), W.Lattice(2, 3, 0.45, 0.5))
     mbt.mbt_array_destroy(a)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_rwg_16bit_products_with_refinement(ctx, prec):
+    """Planar elements with at most 32 RWG functions take the 16-bit per-bin
+    products too: a 3 x 2 array of flat strips (12 cells, 23 functions), all
+    ports, FP64 refinement on top, against the oracle's LU admittance.  binary16
+    meets the 1e-11 residual in 6 steps; bfloat16 contracts by about 10x per step
+    and stops just above it after 12 (reported as not converged), both within
+    1e-9 of the oracle."""
+    from paper_2608_17844_amd import mbt
+    mesh = W.strip_mesh(0.5, 0.02, 12, 1)
+    el = rwg.rwg_element(mesh)
+    assert el.M == 23
+    lat = W.Lattice(3, 2, 0.5, 0.5)
+    Yref = rwg.port_admittance(rwg.fill_dense(el, lat, 1.0), el, lat)
+    a = mbt.mbt_array_create_rwg(ctx, mesh, lat)
+    try:
+        p = mbt.MBT_FP16 if prec == "fp16" else mbt.MBT_BF16
+        opts = mbt.mbt_default_opts(prec=p, refine_tol=1e-11, refine_max=12)
+        Y, it, st = mbt.mbt_port_admittance(ctx, a, 1.0, None, opts, allow_noconv=True)
+        err = np.abs(Y - Yref).max() / np.abs(Yref).max()
+        _say("%s strips: Y_p error %.2e, outer steps %d, converged %d of %d, relres %.2e" % (
+            prec, err, st["outer_steps"], st["nconverged"], st["nrhs"], st["true_relres_max"]))
+        assert err < 1e-9
+        if prec == "fp16":
+            assert st["nconverged"] == st["nrhs"]
+    finally:
+        mbt.mbt_array_destroy(a)
