@@ -11,13 +11,21 @@
 // closed form at each test point (coplanar potential integrals of Wilton et al.,
 // IEEE TAP 1984), the remainder (exp(-jkR) - 1)/(4 pi R) by the rule.
 //
-// One workgroup per (lattice offset, test basis m).  Phase 1: a thread per
-// (test triangle of m, source triangle u) integrates over the 7 x 7 point
-// pairs the four moments h0 = <<G>>, hv = <<(r - v_m) G>> (two components) and
-// hw = <<(r - v_m) . r' G>>, kept in LDS.  Phase 2: a thread per source basis q
-// combines the moments of its two triangles in a fixed order:
-//   <<(r - v_m) . (r' - v_q) G>> = hw - v_q . hv,
-// so the block row is deterministic.  The work is FP64 transcendental-bound.
+// One workgroup per lattice offset.  The source triangles are taken in chunks
+// of U (the chunk's moments fill at most 64 KB of LDS).  Phase 1: a thread per
+// (test triangle t, source triangle u) integrates over the 7 x 7 point pairs
+// the six moments, taken about the test triangle's centroid c_t,
+//   m0 = <<G>>, mr = <<(r - c_t) G>> (two components), mp = <<r' G>> (two
+//   components) and mrp = <<(r - c_t) . r' G>>,
+// once per triangle pair (a triangle carries up to three RWG functions, so
+// moments per function would repeat this work about 2.6 times on the bowtie).
+// Phase 2: a thread per (test basis m, source basis q) combines, for each of q's
+// triangles in the chunk, the moments of m's two triangles (v_m and v_q the
+// free vertices, d_m = v_m - c_t):
+//   <<(r - v_m) . (r' - v_q) G>> = mrp - d_m . mp - v_q . (mr - d_m m0),
+// writing the T+ contribution of q (its lower-index triangle, always in an
+// earlier or the same chunk) and adding the T- one, in a fixed order, so the
+// block is deterministic.  The work is FP64 transcendental-bound.
 // Blocks two or more lattice steps apart use the same rule on test and source
 // side, so T[-d] = T[d]^T for them (Galerkin reciprocity of the discrete
 // operator): only one of each such pair is integrated and the other is its
@@ -43,10 +51,15 @@ struct RwgDev {
     const double* qw;
     const double2* tv;
     const double* area;
+    const double2* tcen;   // nt: triangle centroids
     const int* btri;
     const double2* bfree;
+    const double2* bdel;   // 2M: free vertex minus the centroid of its triangle
     const double* blen;
 };
+
+constexpr int kPairVals = 6;                      // m0, mr (x, y), mp (x, y), mrp per triangle pair
+constexpr int kPairLdsBytes = 64 * 1024;          // LDS for one chunk of pair moments
 
 // exp(-jkR)/(4 pi R)
 __device__ __forceinline__ double2 green_full(double k, double R) {
@@ -108,96 +121,111 @@ __device__ void static_potentials(const double2* v, double2 rho, double& S0, dou
     }
 }
 
-__global__ __launch_bounds__(512) void rwg_fill_kernel(RwgDev d, int nt, int M, int nx, int ny, double ldx,
+__global__ __launch_bounds__(256) void rwg_fill_kernel(RwgDev d, int nt, int M, int U, int nx, int ny, double ldx,
                                                        double ldy, double k, double2* __restrict__ T) {
-    __shared__ double2 acc[2 * kRwgMaxTri * 4];
+    extern __shared__ double2 pm[];   // [t][u - u0][kPairVals]
     const int nox = 2 * nx - 1;
     const int off = blockIdx.x;
-    const int m = blockIdx.y;
     const int ox = off % nox - (nx - 1), oy = off / nox - (ny - 1);
     // the test element sits at lattice offset (ox, oy) from the source element at the origin
     const double sx = ox * ldx, sy = oy * ldy;
     const bool near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
     if (!near && (oy < 0 || (oy == 0 && ox < 0))) return;   // the transpose of T[-d], filled afterwards
-    for (int task = threadIdx.x; task < 2 * nt; task += blockDim.x) {
-        const int side = task / nt, u = task - side * nt;
-        const int t = d.btri[2 * m + side];
-        const double2 vf = d.bfree[2 * m + side];
-        const double vmx = vf.x + sx, vmy = vf.y + sy;
-        double2 rs[kRwgQ];
-        double ws[kRwgQ];
-#pragma unroll
-        for (int j = 0; j < kRwgQ; ++j) {
-            rs[j] = d.qp[u * kRwgQ + j];
-            ws[j] = d.qw[u * kRwgQ + j];
-        }
-        double2 tvu[3];
-        if (near) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) tvu[j] = d.tv[u * 3 + j];
-        }
-        double2 h0 = make_double2(0, 0), hvx = make_double2(0, 0), hvy = make_double2(0, 0), hw = make_double2(0, 0);
-        for (int i = 0; i < kRwgQ; ++i) {
-            const double2 q = d.qp[t * kRwgQ + i];
-            const double rox = q.x + sx, roy = q.y + sy;
-            const double wo = d.qw[t * kRwgQ + i];
-            double2 g0 = make_double2(0, 0), g1x = make_double2(0, 0), g1y = make_double2(0, 0);
+    double2* Tb = T + (int64_t)off * M * M;
+    for (int u0 = 0; u0 < nt; u0 += U) {
+        const int nu = min(U, nt - u0);
+        for (int task = threadIdx.x; task < nt * nu; task += blockDim.x) {
+            const int t = task / nu, u = u0 + task - (task / nu) * nu;
+            const double2 ct = d.tcen[t];
+            double2 rs[kRwgQ];
+            double ws[kRwgQ];
 #pragma unroll
             for (int j = 0; j < kRwgQ; ++j) {
-                const double dx = rox - rs[j].x, dy = roy - rs[j].y;
-                const double R = sqrt(dx * dx + dy * dy);
-                const double2 G = near ? green_rem(k, R) : green_full(k, R);
-                const double2 wg = make_double2(ws[j] * G.x, ws[j] * G.y);
-                g0 = cadd(g0, wg);
-                g1x = cadd(g1x, make_double2(rs[j].x * wg.x, rs[j].x * wg.y));
-                g1y = cadd(g1y, make_double2(rs[j].y * wg.x, rs[j].y * wg.y));
+                rs[j] = d.qp[u * kRwgQ + j];
+                ws[j] = d.qw[u * kRwgQ + j];
             }
+            double2 tvu[3];
             if (near) {
-                double S0;
-                double2 S1;
-                static_potentials(tvu, make_double2(rox, roy), S0, S1);
-                g0.x += S0 * kInv4Pi;
-                g1x.x += (S1.x + rox * S0) * kInv4Pi;
-                g1y.x += (S1.y + roy * S0) * kInv4Pi;
-            }
-            const double ax = rox - vmx, ay = roy - vmy;
-            h0 = cadd(h0, make_double2(wo * g0.x, wo * g0.y));
-            hvx = cadd(hvx, make_double2(wo * ax * g0.x, wo * ax * g0.y));
-            hvy = cadd(hvy, make_double2(wo * ay * g0.x, wo * ay * g0.y));
-            hw = cadd(hw, make_double2(wo * (ax * g1x.x + ay * g1y.x), wo * (ax * g1x.y + ay * g1y.y)));
-        }
-        double2* a = acc + (side * kRwgMaxTri + u) * 4;
-        a[0] = h0;
-        a[1] = hvx;
-        a[2] = hvy;
-        a[3] = hw;
-    }
-    __syncthreads();
-    const double lm = d.blen[m];
-    for (int qb = threadIdx.x; qb < M; qb += blockDim.x) {
-        const double lq = d.blen[qb];
-        double2 sum = make_double2(0, 0);
 #pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const double At = d.area[d.btri[2 * m + side]];
+                for (int j = 0; j < 3; ++j) tvu[j] = d.tv[u * 3 + j];
+            }
+            double2 m0 = make_double2(0, 0), mrx = m0, mry = m0, mpx = m0, mpy = m0, mrp = m0;
+            for (int i = 0; i < kRwgQ; ++i) {
+                const double2 q = d.qp[t * kRwgQ + i];
+                const double rox = q.x + sx, roy = q.y + sy;
+                const double wo = d.qw[t * kRwgQ + i];
+                double2 g0 = make_double2(0, 0), g1x = make_double2(0, 0), g1y = make_double2(0, 0);
+#pragma unroll
+                for (int j = 0; j < kRwgQ; ++j) {
+                    const double dx = rox - rs[j].x, dy = roy - rs[j].y;
+                    const double R = sqrt(dx * dx + dy * dy);
+                    const double2 G = near ? green_rem(k, R) : green_full(k, R);
+                    const double2 wg = make_double2(ws[j] * G.x, ws[j] * G.y);
+                    g0 = cadd(g0, wg);
+                    g1x = cadd(g1x, make_double2(rs[j].x * wg.x, rs[j].x * wg.y));
+                    g1y = cadd(g1y, make_double2(rs[j].y * wg.x, rs[j].y * wg.y));
+                }
+                if (near) {
+                    double S0;
+                    double2 S1;
+                    static_potentials(tvu, make_double2(rox, roy), S0, S1);
+                    g0.x += S0 * kInv4Pi;
+                    g1x.x += (S1.x + rox * S0) * kInv4Pi;
+                    g1y.x += (S1.y + roy * S0) * kInv4Pi;
+                }
+                // about the centroid in the element frame: the lattice shift cancels exactly
+                const double ax = q.x - ct.x, ay = q.y - ct.y;
+                m0 = cadd(m0, make_double2(wo * g0.x, wo * g0.y));
+                mrx = cadd(mrx, make_double2(wo * ax * g0.x, wo * ax * g0.y));
+                mry = cadd(mry, make_double2(wo * ay * g0.x, wo * ay * g0.y));
+                mpx = cadd(mpx, make_double2(wo * g1x.x, wo * g1x.y));
+                mpy = cadd(mpy, make_double2(wo * g1y.x, wo * g1y.y));
+                mrp = cadd(mrp, make_double2(wo * (ax * g1x.x + ay * g1y.x), wo * (ax * g1x.y + ay * g1y.y)));
+            }
+            double2* a = pm + ((int64_t)t * U + (u - u0)) * kPairVals;
+            a[0] = m0;
+            a[1] = mrx;
+            a[2] = mry;
+            a[3] = mpx;
+            a[4] = mpy;
+            a[5] = mrp;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
+            const int m = e / M, qb = e - (e / M) * M;
+            const double lmq = d.blen[m] * d.blen[qb];
 #pragma unroll
             for (int tau = 0; tau < 2; ++tau) {
                 const int u = d.btri[2 * qb + tau];
+                if (u < u0 || u >= u0 + nu) continue;
                 const double Au = d.area[u];
                 const double2 vq = d.bfree[2 * qb + tau];
-                const double2* a = acc + (side * kRwgMaxTri + u) * 4;
-                const double2 A = make_double2(a[3].x - (vq.x * a[1].x + vq.y * a[2].x),
-                                               a[3].y - (vq.x * a[1].y + vq.y * a[2].y));
-                // j k eta A / (4 At Au) - j (eta / k) h0 / (At Au)
-                const double cv = k * kEta / (4.0 * At * Au), cs = kEta / (k * At * Au);
-                const double re = -(cv * A.y - cs * a[0].y);
-                const double im = cv * A.x - cs * a[0].x;
-                const double sg = ((side == tau) ? 1.0 : -1.0) * lm * lq;
-                sum.x += sg * re;
-                sum.y += sg * im;
+                double2 sum = make_double2(0, 0);
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const int t = d.btri[2 * m + side];
+                    const double At = d.area[t];
+                    const double2 dm = d.bdel[2 * m + side];
+                    const double2* a = pm + ((int64_t)t * U + (u - u0)) * kPairVals;
+                    const double2 hvx = csub(a[1], make_double2(dm.x * a[0].x, dm.x * a[0].y));
+                    const double2 hvy = csub(a[2], make_double2(dm.y * a[0].x, dm.y * a[0].y));
+                    const double2 hw = make_double2(a[5].x - (dm.x * a[3].x + dm.y * a[4].x),
+                                                    a[5].y - (dm.x * a[3].y + dm.y * a[4].y));
+                    const double2 A = make_double2(hw.x - (vq.x * hvx.x + vq.y * hvy.x),
+                                                   hw.y - (vq.x * hvx.y + vq.y * hvy.y));
+                    // j k eta A / (4 At Au) - j (eta / k) m0 / (At Au)
+                    const double cv = k * kEta / (4.0 * At * Au), cs = kEta / (k * At * Au);
+                    const double re = -(cv * A.y - cs * a[0].y);
+                    const double im = cv * A.x - cs * a[0].x;
+                    const double sg = (side == tau) ? lmq : -lmq;
+                    sum.x += sg * re;
+                    sum.y += sg * im;
+                }
+                if (tau == 0) Tb[e] = sum;
+                else Tb[e] = cadd(Tb[e], sum);
             }
         }
-        T[((int64_t)off * M + m) * M + qb] = sum;
+        __syncthreads();
     }
 }
 
@@ -319,14 +347,22 @@ RwgMesh rwg_from_mesh(const mbt_rwg_mesh& ms) {
 void rwg_fill_blocks(const Geom& g, const RwgMesh& h, double k, double2* T, hipStream_t s) {
     const int nt = h.nt, M = h.M;
     MBT_REQUIRE(M == g.M, "mesh and geometry disagree on the number of bases");
+    // triangle centroids and each free vertex relative to its triangle's centroid
+    std::vector<double2> tcen(nt), bdel(2 * (size_t)M);
+    for (int t = 0; t < nt; ++t)
+        tcen[t] = make_double2((h.tv[3 * t].x + h.tv[3 * t + 1].x + h.tv[3 * t + 2].x) / 3.0,
+                               (h.tv[3 * t].y + h.tv[3 * t + 1].y + h.tv[3 * t + 2].y) / 3.0);
+    for (int i = 0; i < 2 * M; ++i)
+        bdel[i] = make_double2(h.bfree[i].x - tcen[h.btri[i]].x, h.bfree[i].y - tcen[h.btri[i]].y);
     // one upload of the mesh tables, laid out back to back
     const size_t b_qp = sizeof(double2) * h.qp.size(), b_qw = sizeof(double) * h.qw.size();
     const size_t b_tv = sizeof(double2) * h.tv.size(), b_ar = sizeof(double) * h.area.size();
-    const size_t b_bt = sizeof(int) * h.btri.size(), b_bf = sizeof(double2) * h.bfree.size();
+    const size_t b_tc = sizeof(double2) * tcen.size(), b_bt = sizeof(int) * h.btri.size();
+    const size_t b_bf = sizeof(double2) * h.bfree.size(), b_bd = sizeof(double2) * bdel.size();
     const size_t b_bl = sizeof(double) * h.blen.size();
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     DBuf buf;
-    buf.alloc(up(b_qp) + up(b_qw) + up(b_tv) + up(b_ar) + up(b_bt) + up(b_bf) + up(b_bl));
+    buf.alloc(up(b_qp) + up(b_qw) + up(b_tv) + up(b_ar) + up(b_tc) + up(b_bt) + up(b_bf) + up(b_bd) + up(b_bl));
     char* p = buf.as<char>();
     RwgDev d;
     auto put = [&](const void* src, size_t b) {
@@ -339,12 +375,16 @@ void rwg_fill_blocks(const Geom& g, const RwgMesh& h, double k, double2* T, hipS
     d.qw = reinterpret_cast<const double*>(put(h.qw.data(), b_qw));
     d.tv = reinterpret_cast<const double2*>(put(h.tv.data(), b_tv));
     d.area = reinterpret_cast<const double*>(put(h.area.data(), b_ar));
+    d.tcen = reinterpret_cast<const double2*>(put(tcen.data(), b_tc));
     d.btri = reinterpret_cast<const int*>(put(h.btri.data(), b_bt));
     d.bfree = reinterpret_cast<const double2*>(put(h.bfree.data(), b_bf));
+    d.bdel = reinterpret_cast<const double2*>(put(bdel.data(), b_bd));
     d.blen = reinterpret_cast<const double*>(put(h.blen.data(), b_bl));
-    const int threads = std::min(512, ((2 * nt + 63) / 64) * 64);
-    hipLaunchKernelGGL(rwg_fill_kernel, dim3((unsigned)g.noff(), (unsigned)M), dim3(threads), 0, s, d, nt, M, g.nx,
-                       g.ny, g.dx, g.dy, k, T);
+    // source triangles per chunk: the chunk's pair moments fit the LDS allowance
+    const int U = std::max(1, std::min(nt, kPairLdsBytes / (nt * kPairVals * (int)sizeof(double2))));
+    const size_t lds = sizeof(double2) * (size_t)nt * U * kPairVals;
+    hipLaunchKernelGGL(rwg_fill_kernel, dim3((unsigned)g.noff()), dim3(256), lds, s, d, nt, M, U, g.nx, g.ny, g.dx,
+                       g.dy, k, T);
     MBT_LAUNCH_CHECK();
     hipLaunchKernelGGL(rwg_mirror_kernel, dim3((unsigned)g.noff(), (unsigned)M), dim3(128), 0, s, M, g.nx, g.ny, T);
     MBT_LAUNCH_CHECK();
