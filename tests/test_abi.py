@@ -4,6 +4,8 @@ device work."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -57,6 +59,34 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(mbt.mbt_lattice) == 24
     assert ctypes.sizeof(mbt.mbt_solve_opts) == 56
     assert ctypes.sizeof(mbt.mbt_stats) == 72
+
+
+STRUCTS = ["mbt_dipole", "mbt_lattice", "mbt_solve_opts", "mbt_stats", "mbt_predictors", "mbt_rwg_mesh",
+           "mbt_request", "mbt_result"]
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="no C compiler")
+def test_header_is_c99_and_binding_layouts_match_the_c_compiler(tmp_path):
+    """The header compiles as strict C99, and every structure of the binding has
+    the size and field offsets that the C compiler gives the header's."""
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "mbt.h"', 'int main(void) {']
+    for name in STRUCTS:
+        lines.append('    printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for field, _ in getattr(mbt, name)._fields_:
+            lines.append('    printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, field, name, field))
+    lines += ['    return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for name in STRUCTS:
+        cls = getattr(mbt, name)
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got["%s.%s" % (name, field)]) == getattr(cls, field).offset, (name, field)
 
 
 def test_binding_fails_loudly_without_the_library(monkeypatch):
