@@ -1132,11 +1132,9 @@ inline unsigned ew_grid(int64_t n) {
 
 // Chunks of the row range for the reduction sweeps: a function of N alone, so a
 // right-hand side's sums do not depend on how many others share the batch.  Up
-// to 2048 chunks (at least 256 rows each) keep a few-RHS batch spread over the
-// whole chip while the partial sums stay small next to one basis vector (256
-// rows measured faster than 64, 128, 384 and 512 on the 32 x 32 all-port solve:
-// fewer partials to write and reduce, still enough workgroups to fill the CUs).
-int64_t gmres_rows_per_chunk(int64_t N) { return std::max<int64_t>(256, (N + 2047) / 2048); }
+// to 2048 chunks (at least 128 rows each) keep a few-RHS batch spread over the
+// whole chip while the partial sums stay small next to one basis vector.
+int64_t gmres_rows_per_chunk(int64_t N) { return std::max<int64_t>(128, (N + 2047) / 2048); }
 int gmres_nchunk(int64_t N) { return (int)((N + gmres_rows_per_chunk(N) - 1) / gmres_rows_per_chunk(N)); }
 
 // Row folding: the DCGS2 sweeps give each lane one RHS column (two with the
