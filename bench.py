@@ -58,9 +58,9 @@ def zp_errors(out, ref):
             "gamma_max_rel": float(np.max(dg / np.abs(ref["Gamma"])))}
 
 
-def run_steps(mbt, ctx, arr, w, opts, steps, warmup, kernel=None):
+def run_steps(mbt, ctx, arr, w, opts, steps, warmup, kernel=None, allow_noconv=False):
     for _ in range(warmup):
-        mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
+        mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0, allow_noconv=allow_noconv)
     import torch
     torch.cuda.synchronize()
     if kernel:
@@ -69,7 +69,7 @@ def run_steps(mbt, ctx, arr, w, opts, steps, warmup, kernel=None):
     t0 = time.perf_counter()
     for _ in range(steps):
         ts = time.perf_counter()
-        out = mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
+        out = mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0, allow_noconv=allow_noconv)
         times.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
@@ -183,7 +183,7 @@ def kernel_rooflines(mbt, ctx, arr, w, opts, classes):
     out = {}
     for name in classes:
         mbt.mbt_prof_start(KERNEL_CODES[name])
-        mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0)
+        mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0, allow_noconv=True)
         p = mbt.mbt_prof_read()
         mbt.mbt_prof_start(0)
         if p["launches"] and p["ms"] > 0:
@@ -221,10 +221,16 @@ def headline(args):
     result = {}
     try:
         bflags = mbt.MBT_FLAG_FP32_BASIS if args.fp32_basis else 0
+        # the FP32 COCG inner solves run away on a few RHS (the FP32 short recurrence): cap them at
+        # 20 x 32 = 640 steps per refinement step instead of the default 400 x 32
+        cyc = {"max_cycles": 20} if args.solver == "cocg" else {}
         o32 = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=pc, restart=args.restart, refine_tol=args.refine_tol,
-                                   inner_tol=args.inner_tol, flags=mbt.MBT_FLAG_NO_CACHE | sflags | bflags)
+                                   inner_tol=args.inner_tol, flags=mbt.MBT_FLAG_NO_CACHE | sflags | bflags, **cyc)
         log("fp32-mfma path: warmup %d, steps %d" % (args.warmup, args.steps))
-        total, times, out, prof = run_steps(mbt, ctx, arr, w, o32, args.steps, args.warmup, args.kernel)
+        # the mixed COCG comparator is reported with the RHS it leaves short of the tolerance
+        # (status and count in the line); every other configuration must converge
+        total, times, out, prof = run_steps(mbt, ctx, arr, w, o32, args.steps, args.warmup, args.kernel,
+                                            allow_noconv=args.solver == "cocg")
         err32 = zp_errors(out, ref)
         st32 = out["stats"]
         value = P * args.steps / total
@@ -283,6 +289,7 @@ def headline(args):
                        "refine_tol": args.refine_tol, "inner_tol": args.inner_tol,
                        "accuracy_target": "Z_p entries and center ARC within 1e-6 relative of the FP64 oracle"},
             "accuracy": err32, "iters_max": st32["iters_max"], "outer_steps": st32["outer_steps"],
+            "status": out["status"], "nconverged": st32["nconverged"],
             "matvecs_per_step": st32["matvecs"],
             "matvecs_per_s": st32["matvecs"] * args.steps / total,
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),

@@ -70,9 +70,10 @@ typedef enum {
  * preconditioner apply is FP32, and FP64 iterative refinement with an FP64
  * residual recovers the accuracy (inner tolerance by default 1e-4 for FP32,
  * 1e-3 for FP16, 1e-2 for BF16).  A refinement step that raises a RHS's FP64
- * residual is taken back and that RHS stops refining, so the returned currents
- * are the best iterate; it then counts as not converged unless it met
- * refine_tol. */
+ * residual is taken back (a correction over 1e3 times the iterate, a runaway
+ * inner solve, is dropped before it is added) and that RHS stops refining, so
+ * the returned currents are the best iterate; it then counts as not converged
+ * unless it met refine_tol. */
 typedef enum { MBT_FP64 = 0, MBT_FP32 = 1, MBT_BF16 = 2, MBT_FP16 = 3 } mbt_prec;
 
 /* Preconditioning strategy.

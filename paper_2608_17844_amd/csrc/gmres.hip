@@ -1658,6 +1658,10 @@ __global__ void cocg_beta_kernel(CocgState st, const double2* __restrict__ red, 
         } else if (sqrt(rr / st.bnorm2[r]) <= st.tol) {
             st.conv[r] = 1;
             st.active[r] = 0;
+        } else if (rr > 1e12 * st.bnorm2[r]) {
+            // a residual a million times the right-hand side: the recurrence has run away
+            // (the FP32 short recurrence does so on a few RHS); stop it unconverged
+            st.active[r] = 0;
         } else {
             b = cdiv(rz, st.rho[r]);
             st.rho[r] = rz;

@@ -830,6 +830,7 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
         std::vector<int> done(R, 0), flagged(R, 0), raised(R, 0);
         // FP64 residual norm before the last correction (X = 0 at first: ||V||)
         std::vector<double> prev(vn), hundo(R);
+        bool unchecked = false;   // the last correction has not been checked against prev yet
         for (int outer = 0; outer < o.refine_max; ++outer) {
             if (outer == 0) {
                 convert<double2, double2>(V, r64, NR, s);
@@ -840,6 +841,9 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
             }
             std::vector<double> rn;
             norms_host(r64, g.N, R, arena, rn, s);
+            unchecked = false;
+            for (int r = 0; r < R; ++r)
+                if (!std::isfinite(rn[r])) flagged[r] = 1;   // non-finite input or iterate: breakdown
             // Refinement contracts only while the reduced-precision operator's error is small
             // against the smallest singular values of Z; where it is not, the iterates can
             // grow without bound.  A correction that raised the FP64 residual is taken back
@@ -902,7 +906,29 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
                 gr = gmres_batched<float2>(f, b32, d, basis, g.N, R, prm, arena, s);
             }
             scale_columns_d(d, unscale, g.N, R, s);
+            if (outer > 0) {
+                // A correction a thousand times the iterate is a runaway inner solve, not
+                // refinement; adding it and subtracting it again would cancel the iterate's
+                // digits, so it is dropped here and that RHS stops refining.
+                std::vector<double> dn, xn;
+                norms_host(d, g.N, R, arena, dn, s);
+                norms_host(X, g.N, R, arena, xn, s);
+                int nrej = 0;
+                for (int r = 0; r < R; ++r) {
+                    const bool rej = !done[r] && !(dn[r] <= 1e3 * xn[r]);
+                    hundo[r] = rej ? 0.0 : 1.0;
+                    if (rej) {
+                        raised[r] = 1;
+                        ++nrej;
+                    }
+                }
+                if (nrej > 0) {
+                    MBT_HIP(hipMemcpyAsync(mask, hundo.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+                    scale_columns_d(d, mask, g.N, R, s);
+                }
+            }
             add_to_f64<double2>(X, d, NR, s);
+            unchecked = true;
             out.outer = outer + 1;
             out.cycles += gr.cycles;
             out.matvecs += gr.matvecs;
@@ -911,13 +937,27 @@ SolveOut solve_rhs(const OpData& op, const mbt_solve_opts& o, const double2* V, 
                 if (gr.flag[r]) flagged[r] = 1;
             }
         }
-        // final verdict on the FP64 residual
-        zmul<double>(ov, 0, X, tmp);
-        out.matvecs += 1;
-        sub_d(V, tmp, r64, NR, s);
+        // final verdict on the FP64 residual; the last correction, when the step budget ran
+        // out before it could be checked, is taken back like any other that raised the residual
         std::vector<double> rn;
-        norms_host(r64, g.N, R, arena, rn, s);
+        for (int pass = 0; pass < 2; ++pass) {
+            zmul<double>(ov, 0, X, tmp);
+            out.matvecs += 1;
+            sub_d(V, tmp, r64, NR, s);
+            norms_host(r64, g.N, R, arena, rn, s);
+            if (pass == 1 || !unchecked) break;
+            int nundo = 0;
+            for (int r = 0; r < R; ++r) {
+                hundo[r] = (!raised[r] && rn[r] > prev[r]) ? 1.0 : 0.0;
+                nundo += hundo[r] > 0 ? 1 : 0;
+            }
+            if (nundo == 0) break;
+            MBT_HIP(hipMemcpyAsync(mask, hundo.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+            scale_columns_d(d, mask, g.N, R, s);
+            sub_d(X, d, X, NR, s);
+        }
         for (int r = 0; r < R; ++r) {
+            if (!std::isfinite(rn[r])) flagged[r] = 1;
             const double rel = vn[r] > 0 ? rn[r] / vn[r] : 0.0;
             out.conv[r] = (rel <= o.refine_tol && !flagged[r]) ? 1 : 0;
             out.flag[r] = flagged[r] ? 1 : 0;

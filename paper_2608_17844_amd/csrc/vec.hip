@@ -150,7 +150,8 @@ __global__ void scale_columns_kernel(double2* __restrict__ X, const double* __re
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
         const double f = sc[t % R];
         const double2 v = X[t];
-        X[t] = make_double2(v.x * f, v.y * f);
+        // a zero factor clears the column exactly, also where it holds Inf or NaN
+        X[t] = f == 0.0 ? make_double2(0.0, 0.0) : make_double2(v.x * f, v.y * f);
     }
 }
 
