@@ -196,3 +196,20 @@ def test_bf16_products_full_size(setup):
     assert out["status"] in (mbt.MBT_OK, mbt.MBT_ENOCONV)
     assert e["zp_fro_rel_sketch"] <= 1e-6 and e["zp_center_row"] <= 1e-6
     assert e["zp_samples_elementwise"] <= 1e-4 and e["gamma_rel"] <= 1e-5
+
+
+def test_mixed_cocg_runaway_inner_solve_is_contained(setup):
+    """FP32 COCG inner solves at full size: on one port the third inner
+    recurrence runs away and returns a correction about 1e11 times its iterate.
+    The refinement drops it before adding it and keeps the port's previous
+    iterate, so the solve reports that port as not converged instead of
+    returning it wrecked (without the guard its residual ends near 3e11)."""
+    mbt, ctx, arr, w, ref = setup
+    opts = mbt.mbt_default_opts(prec=mbt.MBT_FP32, pc=mbt.MBT_PC_ELEMENT_BLOCK, restart=32, refine_tol=1e-7,
+                                inner_tol=1e-3, max_cycles=20, flags=mbt.MBT_FLAG_COCG | mbt.MBT_FLAG_NO_CACHE)
+    out = mbt.mbt_solve(ctx, arr, 1.0, opts, w.theta, w.phi, w.z0, allow_noconv=True)
+    e = _errors(out, ref)
+    st = out["stats"]
+    _say({k: "%.2e" % v for k, v in e.items()}, st["nconverged"], "%.2e" % st["true_relres_max"])
+    assert st["nconverged"] >= 1020 and st["true_relres_max"] <= 1e-5
+    assert e["zp_fro_rel_sketch"] <= 1e-6 and e["zp_samples_elementwise"] <= 1e-4
