@@ -534,15 +534,17 @@ __global__ __launch_bounds__(kLineNT) void fft_cols_fwd_kernel(const float2* __r
 }
 
 // the value of element j (j < L/2) of the two halves' sum that this half
-// writes: its own element j + half*L/2 plus the other half's
+// writes: half 0 element j, half 1 element j + L/2.  One v_permlane32_swap per
+// component trades lanes 32-63 of v[j] with lanes 0-31 of v[j + L/2], after
+// which each lane holds both halves' copies of its element (all 64 lanes must
+// take part).
 template <int L>
 __device__ __forceinline__ float2 half_sum(const float2 (&v)[L], int j, int half) {
-    const float2 send = half ? v[j] : v[j + L / 2];
-    const float2 mine = half ? v[j + L / 2] : v[j];
-    float2 recv;
-    recv.x = __shfl_xor(send.x, 32);
-    recv.y = __shfl_xor(send.y, 32);
-    return cadd(mine, recv);
+    (void)half;
+    const float2 a = v[j], b = v[j + L / 2];
+    const auto sx = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
+    const auto sy = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
+    return make_float2(__uint_as_float(sx[0]) + __uint_as_float(sx[1]), __uint_as_float(sy[0]) + __uint_as_float(sy[1]));
 }
 
 // Inverse, pass 1: columns.  Z[iy][kx][c] = sum_al tw_al(iy)* IDFT_Ly(Yh[2a+al][kx][c])[iy], iy < ny.
