@@ -539,8 +539,7 @@ __global__ __launch_bounds__(kLineNT) void fft_cols_fwd_kernel(const float2* __r
 // which each lane holds both halves' copies of its element (all 64 lanes must
 // take part).
 template <int L>
-__device__ __forceinline__ float2 half_sum(const float2 (&v)[L], int j, int half) {
-    (void)half;
+__device__ __forceinline__ float2 half_sum(const float2 (&v)[L], int j) {
     const float2 a = v[j], b = v[j + L / 2];
     const auto sx = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
     const auto sy = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
@@ -563,7 +562,7 @@ __global__ __launch_bounds__(kLineNT) void fft_cols_inv_kernel(const float2* __r
     for (int iy = 1; iy < LY; ++iy) g[iy] = par_tw<true>(g[iy], twy, iy, t.half);
 #pragma unroll
     for (int j = 0; j < LY / 2; ++j) {
-        const float2 v = half_sum<LY>(g, j, t.half);
+        const float2 v = half_sum<LY>(g, j);
         const int iy = j + t.half * (LY / 2);
         if (t.cv && iy < ny) Z[((int64_t)iy * PX + kx) * B + t.c] = v;
     }
@@ -585,7 +584,7 @@ __global__ __launch_bounds__(kLineNT) void fft_rows_inv_kernel(const float2* __r
     for (int ix = 1; ix < LX; ++ix) h[ix] = par_tw<true>(h[ix], twx, ix, t.half);
 #pragma unroll
     for (int j = 0; j < LX / 2; ++j) {
-        const float2 v = half_sum<LX>(h, j, t.half);
+        const float2 v = half_sum<LX>(h, j);
         const int ix = j + t.half * (LX / 2);
         if (t.cv && ix < nx) Y[(int64_t)(iy * nx + ix) * B + t.c] = v;
     }
