@@ -131,9 +131,118 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const cplx<T>* __restrict__ 
     }
 }
 
+// FP32 with an even number of columns: each lane carries two adjacent columns,
+// so every access of X and Y is 16 bytes; a wave tile is 32 columns, run as two
+// interleaved 16-column MFMA products with the same fragments of A (per column
+// the arithmetic and its order are those of cgemm_kernel).
+template <int MP, bool HERM>
+__global__ __launch_bounds__(256) void cgemm_pair_kernel(const float2* __restrict__ A, int64_t strideA,
+                                                         const float2* __restrict__ X, float2* __restrict__ Y, int M,
+                                                         int R, int groups, int tpw) {
+    using V = f4;
+    constexpr int NRT = MP / 8;
+    constexpr int NS = MP / 4;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t b = blockIdx.x / groups;
+    const int grp = blockIdx.x % groups;
+    const int ntiles = (R + 31) >> 5;
+    const int t0 = (grp * 4 + wave) * tpw;
+    if (t0 >= ntiles) return;
+    const int t1 = min(t0 + tpw, ntiles);
+
+    const float2* Ab = A + b * strideA;
+    const float2* Xb = X + b * (int64_t)M * R;
+    float2* Yb = Y + b * (int64_t)M * R;
+    const int g = lane >> 4;
+    const int li = lane & 15;
+
+    float are[NRT][NS], aim[NRT][NS];
+#pragma unroll
+    for (int t = 0; t < NRT; ++t) {
+        const int rho = 16 * t + li;
+        const int p = rho >> 1;
+        const bool odd = rho & 1;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int q = 4 * s + g;
+            float2 c = make_float2(0.f, 0.f);
+            if (p < M && q < M) {
+                c = HERM ? Ab[(int64_t)q * M + p] : Ab[(int64_t)p * M + q];
+                if (HERM) c.y = -c.y;
+            }
+            are[t][s] = odd ? c.y : c.x;
+            aim[t][s] = odd ? c.x : -c.y;
+        }
+    }
+
+    float4 bcur[NS], bnext[NS];
+    auto load = [&](int tile, float4* dst) {
+        const int col = tile * 32 + 2 * li;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int q = 4 * s + g;
+            dst[s] = (q < M && col < R) ? *reinterpret_cast<const float4*>(Xb + (int64_t)q * R + col)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    load(t0, bcur);
+    for (int tile = t0; tile < t1; ++tile) {
+        if (tile + 1 < t1) load(tile + 1, bnext);
+        V acc0[NRT], acc1[NRT];
+#pragma unroll
+        for (int t = 0; t < NRT; ++t) acc0[t] = acc1[t] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) {
+                acc0[t] = mfma(are[t][s], bcur[s].x, acc0[t]);
+                acc0[t] = mfma(aim[t][s], bcur[s].y, acc0[t]);
+                acc1[t] = mfma(are[t][s], bcur[s].z, acc1[t]);
+                acc1[t] = mfma(aim[t][s], bcur[s].w, acc1[t]);
+            }
+        }
+        const int col = tile * 32 + 2 * li;
+        if (col < R) {
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) {
+                const int p0 = 8 * t + 2 * g;
+                if (p0 < M)
+                    *reinterpret_cast<float4*>(Yb + (int64_t)p0 * R + col) =
+                        make_float4(acc0[t][0], acc0[t][1], acc1[t][0], acc1[t][1]);
+                if (p0 + 1 < M)
+                    *reinterpret_cast<float4*>(Yb + (int64_t)(p0 + 1) * R + col) =
+                        make_float4(acc0[t][2], acc0[t][3], acc1[t][2], acc1[t][3]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bcur[s] = bnext[s];
+    }
+}
+
 template <typename T, int MP>
 void launch_mp(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, int M, int R, int64_t nbatch,
                int op, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        if (R % 2 == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15) == 0) {
+            const int ntiles = (R + 31) / 32;
+            const int64_t total = nbatch * ntiles;
+            int tpw = (int)std::max<int64_t>(1, std::min<int64_t>(4, total / 32768));
+            if (strideA == 0) tpw = 4;
+            tpw = std::min(tpw, ntiles);
+            const int groups = (ntiles + 4 * tpw - 1) / (4 * tpw);
+            const int64_t blocks = nbatch * groups;
+            MBT_REQUIRE(blocks < (1LL << 31), "cgemm: grid too large");
+            if (op == 0)
+                hipLaunchKernelGGL((cgemm_pair_kernel<MP, false>), dim3((unsigned)blocks), dim3(256), 0, s, A, strideA,
+                                   X, Y, M, R, groups, tpw);
+            else
+                hipLaunchKernelGGL((cgemm_pair_kernel<MP, true>), dim3((unsigned)blocks), dim3(256), 0, s, A, strideA,
+                                   X, Y, M, R, groups, tpw);
+            MBT_LAUNCH_CHECK();
+            return;
+        }
+    }
     const int ntiles = (R + 15) / 16;
     const int64_t total = nbatch * ntiles;
     int tpw = (int)std::max<int64_t>(1, std::min<int64_t>(8, total / 32768));
