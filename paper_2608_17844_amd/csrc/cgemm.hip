@@ -270,7 +270,9 @@ void launch_mp(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>* Y, 
 // registers; the next chunk's A elements and X fragments are loaded while the
 // current chunk computes.  At M = 96 and 32 columns a bin moves 123 KB (FP32)
 // for 2.4 MFLOP, at the FP32 MFMA ridge.
-template <typename T, int MP, bool HERM, int CT>
+// PAIR (FP32, Ĉ_b untransposed, even M): each thread loads two adjacent K
+// entries of a row of A as one 16-byte access; the LDS stage holds the same values.
+template <typename T, int MP, bool HERM, int CT, bool PAIR>
 __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restrict__ A, int64_t strideA,
                                                         const cplx<T>* __restrict__ X, cplx<T>* __restrict__ Y, int M,
                                                         int R) {
@@ -317,10 +319,24 @@ __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restric
         for (int c = 0; c < CT; ++c) acc[i][c] = V{0, 0, 0, 0};
 
     // the next chunk's A elements and X fragments are loaded while this chunk computes
+    static_assert(!PAIR || (sizeof(T) == 4 && !HERM), "paired A loads are for FP32 untransposed blocks");
     constexpr int AE = (MP * KC + 255) / 256;
-    C areg[AE];
+    constexpr int AE2 = (MP * KC / 2 + 255) / 256;
+    C areg[PAIR ? 1 : AE];
+    float4 areg2[PAIR ? AE2 : 1];
     C xcur[KC / 4][CT], xnxt[KC / 4][CT];
     auto load_a = [&](int kc) {
+        if constexpr (PAIR) {
+#pragma unroll
+            for (int t = 0; t < AE2; ++t) {
+                const int e = threadIdx.x + 256 * t;
+                const int p = e / (KC / 2), j = 2 * (e - p * (KC / 2)), q = kc + j;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (e < MP * KC / 2 && p < M && q < M) v = *reinterpret_cast<const float4*>(Ab + (int64_t)p * M + q);
+                areg2[t] = v;
+            }
+            return;
+        }
 #pragma unroll
         for (int t = 0; t < AE; ++t) {
             const int e = threadIdx.x + 256 * t;
@@ -348,10 +364,22 @@ __global__ __launch_bounds__(256) void cgemm_big_kernel(const cplx<T>* __restric
     load_x(0, xcur);
     for (int kc = 0; kc < M; kc += KC) {
         __syncthreads();
+        if constexpr (PAIR) {
 #pragma unroll
-        for (int t = 0; t < AE; ++t) {
-            const int e = threadIdx.x + 256 * t;
-            if (e < MP * KC) As[(e / KC) * LDA + (e % KC)] = areg[t];
+            for (int t = 0; t < AE2; ++t) {
+                const int e = threadIdx.x + 256 * t;
+                if (e < MP * KC / 2) {
+                    const int p = e / (KC / 2), j = 2 * (e - p * (KC / 2));
+                    As[p * LDA + j] = make_float2(areg2[t].x, areg2[t].y);
+                    As[p * LDA + j + 1] = make_float2(areg2[t].z, areg2[t].w);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < AE; ++t) {
+                const int e = threadIdx.x + 256 * t;
+                if (e < MP * KC) As[(e / KC) * LDA + (e % KC)] = areg[t];
+            }
         }
         if (kc + KC < M) {
             load_a(kc + KC);
@@ -401,10 +429,15 @@ void launch_big_ct(const cplx<T>* A, int64_t strideA, const cplx<T>* X, cplx<T>*
     const int groups = (ntiles + CT - 1) / CT;
     MBT_REQUIRE(nbatch < (1LL << 31) && groups < 65536, "cgemm: grid too large");
     const dim3 grid((unsigned)nbatch, (unsigned)groups);
-    if (op == 0)
-        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, false, CT>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
+    const bool pair = sizeof(T) == 4 && op == 0 && M % 2 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+    if (op == 0 && pair) {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((cgemm_big_kernel<T, MP, false, CT, true>), grid, dim3(256), 0, s, A, strideA, X, Y, M,
+                               R);
+    } else if (op == 0)
+        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, false, CT, false>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
     else
-        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, true, CT>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
+        hipLaunchKernelGGL((cgemm_big_kernel<T, MP, true, CT, false>), grid, dim3(256), 0, s, A, strideA, X, Y, M, R);
     MBT_LAUNCH_CHECK();
 }
 
