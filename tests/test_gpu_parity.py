@@ -129,6 +129,24 @@ def test_matvec_columns_are_independent_of_batch(ctx, make_array):
         assert np.array_equal(y1[:, 0], y_all[:, j])
 
 
+@pytest.mark.parametrize("nb", [15, 31])
+def test_fp32_products_agree_across_column_pairing(ctx, make_array, nb):
+    """FP32 per-bin products carry two adjacent columns per lane when the batch is
+    even and one column per lane when it is odd; either way a column's result is
+    bit-identical (op 0 and op 1)."""
+    from paper_2608_17844_amd import mbt
+    lat, dip = W.Lattice(5, 4, 0.5, 0.5), W.Dipole(0.5, 0.005, nb)
+    a = make_array(lat, dip)
+    N = lat.nx * lat.ny * dip.nbases
+    x = W.random_vectors(N, 38, seed=4)
+    for op in (0, 1):
+        y_even = mbt.mbt_dbg_matvec(ctx, a, 1.0, x, op=op, prec=mbt.MBT_FP32)
+        y_odd = mbt.mbt_dbg_matvec(ctx, a, 1.0, x[:, :37], op=op, prec=mbt.MBT_FP32)
+        assert np.array_equal(y_even[:, :37], y_odd), op
+        y1 = mbt.mbt_dbg_matvec(ctx, a, 1.0, x[:, 5:6], op=op, prec=mbt.MBT_FP32)
+        assert np.array_equal(y1[:, 0], y_even[:, 5]), op
+
+
 @pytest.mark.parametrize("shape", SHAPES[2:5], ids=[_ids(s) for s in SHAPES[2:5]])
 def test_preconditioner_blocks_and_apply(ctx, make_array, shape):
     from paper_2608_17844_amd import mbt
