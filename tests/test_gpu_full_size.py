@@ -181,7 +181,7 @@ def test_pcg_mixed_full_size(setup):
 
 
 def test_bf16_products_full_size(setup):
-    """bfloat16 per-bin products (the survey's mixed-BF16 variant) at full size:
+    """bfloat16 per-bin products (the mixed-BF16 variant of this workload) at full size:
     inner GMRES(32) to 1e-2, up to 8 FP64 refinement steps towards 1e-7.  The
     products carry a 1e-3 operator error and the refinement contracts slowly on
     this ill-conditioned array, so most RHS stop short of 1e-7 (reported as not
